@@ -1,0 +1,196 @@
+"""Throughput of the FP64 Lennard-Jones MD step on one MI355X.
+
+A step is one velocity-Verlet step of the whole hot path (kick + drift +
+wrap, cell binning and neighbor-list rebuild every 20 steps, force sum, kick)
+on a seeded synthetic FCC box, with all state resident in HBM.
+
+Primary workload: FCC 32^3 unit cells = 131,072 atoms, rho 0.8442, T 1.44,
+cutoff 2.5 + skin 0.3, dt 0.005, rebuild every 20 steps (the paper's
+single-core CPU shape).  Secondary (same JSON line): FCC 96^3 = 3,538,944
+atoms jittered by +-0.01 (one node's subdomain in the paper's CPU weak
+scaling), 500 steps.
+
+Prints one JSON line.  Fields beyond the contract: "roofline" (force kernel
+against the HBM roofline, from HIP events recorded around every force launch
+on the launch stream), "cpu_baseline" (the CPU oracle on a bounded sample of
+the primary workload) and "secondary".
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
+METRIC = "atom-steps/s (FP64 LJ) at 131k & 3.5M atoms; batched, adjoint vs plain"
+KERNEL_SRC = os.path.join(ROOT, "paper_2009_07400_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
+
+WORKLOADS = {
+    "c1": dict(ncell=32, rho=0.8442, T=1.44, jitter=0.0, seed=1001, steps=1000,
+               name="LJ FCC 32^3 = 131,072 atoms, rho 0.8442, T 1.44, rc 2.5 + skin 0.3, dt 0.005, rebuild 20"),
+    "c2": dict(ncell=96, rho=0.8442, T=1.44, jitter=0.02, seed=1002, steps=500,
+               name="LJ FCC 96^3 = 3,538,944 atoms jittered +-0.01, rho 0.8442, T 1.44, rc 2.5 + skin 0.3, "
+                    "dt 0.005, rebuild 20"),
+}
+
+
+def _kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def _traffic(workload: str):
+    """HBM bytes per force launch from stored rocprofv3 FETCH_SIZE/WRITE_SIZE
+    counters, valid only for the kernel source they were taken from."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload)
+    if not ent or rec.get("kernel_sha256_16") != _kernel_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_gpu(workload: str, steps: int, warmup: int):
+    import torch
+
+    from paper_2009_07400_amd import System
+    from workloads import md_system
+
+    w = WORKLOADS[workload]
+    s = md_system(w["ncell"], w["rho"], w["T"], seed=w["seed"], jitter=w["jitter"])
+    g = System(s.n, s.L, max_neighbors=128)
+    g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
+    g.integrate(warmup)
+    g.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.integrate(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.sync()
+    elapsed = t1 - t0
+
+    # Kernel timing pass: the same number of steps again with HIP events
+    # recorded on the launch stream around every kernel.
+    g.set_timing(True)
+    g.integrate(steps)
+    g.sync()
+    tm = g.get_timing()
+    g.set_timing(False)
+    counts, _ = g.get_neighbors()
+    mean_list = float(counts.double().mean().item())
+    g.sync()
+    ms, launches = tm["force"]
+    avg_s = ms / max(launches, 1) * 1e-3
+    # algorithmic bytes of the fused force + kick + drift kernel per atom:
+    # count 4 + list 4*n_list + x_i 24 + v read 24 + v write 24 + x_new 24
+    bytes_per_atom = 100.0 + 4.0 * mean_list
+    alg_bytes = bytes_per_atom * s.n
+    achieved = alg_bytes / avg_s / 1e9
+    traffic = _traffic(workload)
+    res = {
+        "n": s.n,
+        "steps": steps,
+        "warmup": warmup,
+        "elapsed_s": elapsed,
+        "value": s.n * steps / elapsed,
+        "ms_per_step": elapsed / steps * 1e3,
+        "mean_list_length": mean_list,
+        "kernel_ms": {k: (v[0] / max(v[1], 1), v[1]) for k, v in tm.items() if v[1]},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_force<2,false> (force + kick + kick + drift, fused)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_us": avg_s * 1e6,
+        },
+    }
+    g.close()
+    return res
+
+
+def run_cpu_baseline(workload: str, sample_steps: int):
+    import oracle
+    from workloads import md_system
+
+    w = WORKLOADS[workload]
+    s = md_system(w["ncell"], w["rho"], w["T"], seed=w["seed"], jitter=w["jitter"])
+    t0 = time.perf_counter()
+    oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.L, sample_steps, thermo=False)
+    dt = time.perf_counter() - t0
+    return {"value": s.n * sample_steps / dt, "unit": "atom-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{w['name']}: first {sample_steps} steps (initial list build + {sample_steps // 20} "
+                      f"rebuilds), OpenMP over atoms, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's step count)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c1")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 3.5M-atom secondary workload")
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU available"}))
+        sys.exit(1)
+    steps = args.steps if args.steps is not None else WORKLOADS[args.workload]["steps"]
+    prim = run_gpu(args.workload, steps, args.warmup)
+    print(f"# primary {args.workload}: {prim['value']:.4g} atom-steps/s, {prim['ms_per_step']:.4f} ms/step",
+          file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC,
+        "value": prim["value"],
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": prim["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded FCC lattice, SplitMix64 velocities)",
+        "config": {"workload": WORKLOADS[args.workload]["name"], "n_atoms": prim["n"],
+                   "neighbor_list": "full", "max_neighbors": 128},
+        "roofline": prim["roofline"],
+        "kernel_avg_ms": prim["kernel_ms"],
+        "mean_list_length": prim["mean_list_length"],
+    }
+    if not args.no_secondary and args.workload != "c2":
+        sec = run_gpu("c2", WORKLOADS["c2"]["steps"], args.warmup)
+        print(f"# secondary c2: {sec['value']:.4g} atom-steps/s", file=sys.stderr, flush=True)
+        out["secondary"] = {"c2": {"workload": WORKLOADS["c2"]["name"], "value": sec["value"],
+                                   "ms_per_step": sec["ms_per_step"], "steps": sec["steps"],
+                                   "roofline": sec["roofline"], "kernel_avg_ms": sec["kernel_ms"],
+                                   "mean_list_length": sec["mean_list_length"]}}
+    if not args.no_cpu:
+        out["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

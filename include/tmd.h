@@ -1,0 +1,188 @@
+/*
+ * tmd.h - C ABI of the MI355X (gfx950) Lennard-Jones molecular-dynamics hot
+ * path described in tinyMD (arXiv 2009.07400).
+ *
+ * The library advances a periodic cubic box of point particles under the
+ * Lennard-Jones 12-6 pair force (Sec. 3.2, Eq. 2) using cell lists and a full
+ * Verlet neighbor list built at cutoff + skin (Sec. 3.2, Fig. 1; full lists as
+ * in the evaluation setup of Sec. 6), the force sum over each atom's list
+ * (the compute_potential example of Sec. 4.2), and velocity-Verlet
+ * integration of Newton's law (Sec. 3.2, Eq. 1) with the list rebuilt on a
+ * fixed schedule (every 20 steps in Sec. 6).
+ *
+ * Conventions shared by every entry point
+ *   - Floating point is IEEE double (FP64) throughout, as in the paper's runs.
+ *   - Arrays exchanged with the caller are device pointers in structure-of-
+ *     arrays form (x[N], y[N], z[N]) indexed by ORIGINAL atom id, whatever
+ *     order the library keeps internally.
+ *   - Streams: `tmd_stream` is a hipStream_t (NULL = legacy default stream).
+ *     Every call that takes a stream only enqueues work on it and returns;
+ *     pointers passed to such a call must stay valid until that work is done.
+ *   - Memory: the library never allocates device memory.  The caller asks
+ *     tmd_workspace_size(), allocates that many bytes (256-byte aligned) and
+ *     binds them; all device state lives there.  The library never frees
+ *     caller memory.
+ *   - Errors: argument and call-order errors are returned synchronously.
+ *     Conditions detected on the device (list overflow, non-finite state) set
+ *     a device error word; tmd_sync() (and any later call that synchronises)
+ *     returns them.  Once set, the word stays set until tmd_set_state().
+ *   - No entry point is thread-safe on the same tmd_system.
+ */
+#ifndef TMD_H
+#define TMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TMD_OK = 0,
+    TMD_EINVAL = -1,        /* bad argument: NULL handle, N <= 0, non-finite or non-positive parameter */
+    TMD_EBOX = -2,          /* cutoff + skin >= L/2: the minimum image is not unique */
+    TMD_ESTATE = -3,        /* wrong call order (no workspace bound, no state set, ...) */
+    TMD_ENBR_OVERFLOW = -4, /* an atom had more than max_neighbors list entries (deferred) */
+    TMD_ENONFINITE = -5,    /* a position or force became NaN/Inf, e.g. coincident atoms (deferred) */
+    TMD_EWORKSPACE = -6,    /* workspace too small or misaligned */
+    TMD_EHIP = -7           /* a HIP runtime call failed; tmd_last_error() has the HIP message */
+} tmd_status;
+
+/* Physical and algorithmic parameters.  epsilon is the depth of the LJ well,
+ * sigma the distance at which the pair potential is zero (Sec. 3.2, Eq. 2);
+ * cutoff and skin give the force cutoff and the list radius cutoff + skin
+ * (Fig. 1 caption; 2.5 and 0.3 in Sec. 6); rebuild_every is the reneighboring
+ * interval (20 in Sec. 6); max_neighbors the list capacity per atom. */
+typedef struct {
+    double epsilon;
+    double sigma;
+    double mass;
+    double cutoff;
+    double skin;
+    double dt;
+    int32_t rebuild_every;
+    int32_t max_neighbors;
+} tmd_params;
+
+typedef struct tmd_system tmd_system; /* opaque, library-owned host object */
+typedef void *tmd_stream;             /* hipStream_t */
+
+/* Read-only facts about a created system (host values). */
+typedef struct {
+    int64_t n_atoms;
+    int64_t n_padded;        /* row stride of the neighbor-major list */
+    int32_t cells_per_axis;  /* floor(L / (cutoff + skin)) */
+    int32_t max_neighbors;
+    int64_t n_cells;
+    size_t workspace_bytes;
+    int64_t step;            /* time-step counter of the current state */
+} tmd_info;
+
+/* Kernel classes reported by tmd_get_timing(). */
+enum {
+    TMD_T_FORCE = 0, /* force sum (fused with the kicks and the drift when integrating) */
+    TMD_T_NEIGHBOR,  /* neighbor-list build */
+    TMD_T_BINNING,   /* cell count, scan, scatter, in-cell ordering and permutation */
+    TMD_T_DRIFT,     /* stand-alone kick + drift (first step of an integrate call) */
+    TMD_T_THERMO,    /* deterministic reductions of energy, virial and kinetic energy */
+    TMD_T_COPY,      /* state load/unload between original and internal order */
+    TMD_T_COUNT
+};
+
+/* Create a system of n_atoms atoms in a periodic cube of side box_length.
+ * Host only; touches no GPU.  Returns TMD_EINVAL for a NULL pointer, n_atoms
+ * <= 0 or > 2^31-1, a non-finite or non-positive epsilon, sigma, mass, cutoff,
+ * dt, box_length, a negative skin, rebuild_every < 1 or max_neighbors outside
+ * [1, 4096]; TMD_EBOX when cutoff + skin >= box_length / 2.  On success *out
+ * owns a handle to release with tmd_destroy(). */
+tmd_status tmd_create(const tmd_params *params, int64_t n_atoms, double box_length, tmd_system **out);
+
+/* Bytes of device workspace the system needs (host only). */
+tmd_status tmd_workspace_size(const tmd_system *sys, size_t *bytes);
+
+/* Bind caller-allocated device memory of at least tmd_workspace_size() bytes,
+ * 256-byte aligned.  Borrowed until tmd_destroy() or the next bind; binding
+ * discards any state.  TMD_EWORKSPACE if too small or misaligned. */
+tmd_status tmd_bind_workspace(tmd_system *sys, void *dev_ptr, size_t bytes);
+
+/* Load positions pos[3] (x, y, z) and velocities vel[3], each a device array
+ * of n_atoms doubles in original atom order, and the step counter.  Positions
+ * are wrapped once into [0, L) (Sec. 3.2, periodic boundaries).  Clears the
+ * device error word and marks the neighbor list and forces stale.  The input
+ * arrays are read on `stream` and may be reused once that work completes. */
+tmd_status tmd_set_state(tmd_system *sys, const double *const pos[3], const double *const vel[3], int64_t step,
+                         tmd_stream stream);
+
+/* Distribute atoms over cells and build the full Verlet list of every atom:
+ * all j != i in the 27 neighboring cells (deduplicated when fewer than three
+ * cells per axis) with |x_ij|^2 < (cutoff + skin)^2 (Sec. 3.2, Fig. 1).  The
+ * library reorders atoms by cell (count / scan / scatter, in-cell order by
+ * original id) and stores the list neighbor-major (Sec. 4.2: the n-th
+ * neighbors of consecutive atoms are contiguous).  Overflow of max_neighbors
+ * is reported by tmd_sync() as TMD_ENBR_OVERFLOW. */
+tmd_status tmd_build_neighbors(tmd_system *sys, tmd_stream stream);
+
+/* Forces at the current positions from the current list:
+ *   F_i = sum_{j in list(i), |x_ij|^2 < cutoff^2} f(s) x_ij,
+ *   f(s) = 48 eps (sigma^6/s^3) (sigma^6/s^3 - 1/2) / s   (Sec. 3.2 Eq. 2; Sec. 4.2 listing)
+ * f[3] (nullable) receives F in original order (device, n_atoms doubles each).
+ * energy_virial (nullable, device, 2 doubles) receives
+ *   U = 1/2 sum_i sum_j 4 eps [(sigma^6/s^3)^2 - sigma^6/s^3]  (unshifted) and
+ *   W = 1/2 sum_i sum_j s f(s).
+ * TMD_ESTATE if no list has been built since the last tmd_set_state(). */
+tmd_status tmd_compute_forces(tmd_system *sys, double *const f[3], double *energy_virial, tmd_stream stream);
+
+/* Advance n_steps velocity-Verlet steps (Sec. 3.2, Eq. 1):
+ *   v += dt/(2m) F;  x += dt v;  wrap x into [0, L);
+ *   if step % rebuild_every == 0: rebuild cells and list;
+ *   F = F(x);  v += dt/(2m) F
+ * where `step` is the absolute step counter (so the schedule survives split
+ * calls).  Builds the list first if none is valid.  With thermo_every > 0,
+ * thermo (device, nullable) receives one row of 5 doubles (KE, T, U, W, E) for
+ * every step that is a multiple of thermo_every within the call, in order;
+ * T = 2 KE / (3N - 3), E = KE + U.  n_steps == 0 is a no-op. */
+tmd_status tmd_integrate(tmd_system *sys, int32_t n_steps, int32_t thermo_every, double *thermo,
+                         tmd_stream stream);
+
+/* Copy the current state out in original atom order (pos[3], vel[3] device
+ * arrays of n_atoms doubles; either may be NULL) and the step counter (host,
+ * nullable). */
+tmd_status tmd_get_state(const tmd_system *sys, double *const pos[3], double *const vel[3], int64_t *step,
+                         tmd_stream stream);
+
+/* Export the current list in original ids: counts[N] (device int32) and
+ * ids[N * max_neighbors] (device int32, row i holds atom i's neighbors sorted
+ * ascending, unused slots -1).  capacity is the length of ids in elements.
+ * TMD_EINVAL if capacity < N * max_neighbors; TMD_ESTATE without a list. */
+tmd_status tmd_get_neighbors(const tmd_system *sys, int32_t *counts, int32_t *ids, int64_t capacity,
+                             tmd_stream stream);
+
+/* Wait for the stream and return the deferred device status (TMD_OK,
+ * TMD_ENBR_OVERFLOW or TMD_ENONFINITE), or TMD_EHIP. */
+tmd_status tmd_sync(tmd_system *sys, tmd_stream stream);
+
+/* Host-side facts about the system. */
+tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
+
+/* Per-kernel-class timing with HIP events recorded on the launch stream around
+ * every kernel (only while enabled).  tmd_get_timing() synchronises, then
+ * returns accumulated milliseconds and launch counts for the TMD_T_* classes
+ * (arrays of at least TMD_T_COUNT entries) and resets the accumulators. */
+tmd_status tmd_set_timing(tmd_system *sys, int32_t enable);
+tmd_status tmd_get_timing(tmd_system *sys, double *ms, int64_t *launches);
+
+/* Static description of a status code. */
+const char *tmd_status_string(tmd_status status);
+
+/* Detail of the last error on this system (never NULL). */
+const char *tmd_last_error(const tmd_system *sys);
+
+/* Release the handle (does not free the workspace).  NULL is a no-op. */
+void tmd_destroy(tmd_system *sys);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TMD_H */

@@ -1,0 +1,481 @@
+// C-ABI layer of the MI355X Lennard-Jones MD library: argument checking,
+// workspace carving, call ordering, the integration schedule and deferred
+// device errors.  Every numerical step runs in the kernels of kernels.hip.
+#include "tmd.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace tmd;
+
+struct tmd_system {
+    tmd_params p{};
+    Geom g{};
+    size_t ws_need = 0;
+    void *ws = nullptr;
+    Buffers b{};
+    int cur = 0;
+    bool bound = false, have_state = false, list_valid = false, force_valid = false;
+    int64_t step = 0;
+    std::string err;
+
+    struct Ev {
+        int cls;
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<Ev> pending;
+    std::vector<hipEvent_t> pool;
+    double t_ms[TMD_T_COUNT] = {};
+    int64_t t_n[TMD_T_COUNT] = {};
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Carve the workspace; with base == nullptr only the size is computed.
+size_t carve(const Geom &g, char *base, Buffers *out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    const size_t np = size_t(g.np);
+    Buffers b{};
+    for (int k = 0; k < 2; ++k) {
+        b.x[k] = (double *)take(np * 8);
+        b.y[k] = (double *)take(np * 8);
+        b.z[k] = (double *)take(np * 8);
+        b.vx[k] = (double *)take(np * 8);
+        b.vy[k] = (double *)take(np * 8);
+        b.vz[k] = (double *)take(np * 8);
+        b.orig[k] = (int32_t *)take(np * 4);
+    }
+    b.fx = (double *)take(np * 8);
+    b.fy = (double *)take(np * 8);
+    b.fz = (double *)take(np * 8);
+    b.cell_of = (int32_t *)take(np * 4);
+    b.slot = (int32_t *)take(np * 4);
+    b.tmp_idx = (int32_t *)take(np * 4);
+    b.cell_count = (int32_t *)take(size_t(g.ncell) * 4);
+    b.cell_start = (int32_t *)take((size_t(g.ncell) + 1) * 4);
+    b.scan_sums = (int32_t *)take((size_t(scan_blocks(g.ncell)) + 1) * 4);
+    b.nbr_count = (int32_t *)take(np * 4);
+    b.nbr = (int32_t *)take(np * size_t(g.maxnb) * 4);
+    b.partials = (double *)take(size_t(atom_grid(g.n)) * kPartialStride * 8);
+    b.scalars = (double *)take(64 * 8);
+    b.err = (int32_t *)take(64);
+    if (out)
+        *out = b;
+    return off;
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+tmd_status fail(tmd_system *s, tmd_status st, const std::string &msg) {
+    if (s)
+        s->err = msg;
+    return st;
+}
+
+tmd_status hip_fail(tmd_system *s, hipError_t e, const char *where) {
+    return fail(s, TMD_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+hipEvent_t get_event(tmd_system *s) {
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Brackets the kernels of one class with events on the launch stream.
+struct Timed {
+    tmd_system *s;
+    int cls;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Timed(tmd_system *s_, int cls_, hipStream_t st_) : s(s_), cls(cls_), st(st_) {
+        if (s->timing && (a = get_event(s)) != nullptr)
+            (void)hipEventRecord(a, st);
+    }
+    ~Timed() {
+        if (!a)
+            return;
+        hipEvent_t b = get_event(s);
+        if (!b) {
+            s->pool.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, st);
+        s->pending.push_back({cls, a, b});
+    }
+};
+
+tmd_status check_ready(tmd_system *s, bool need_state) {
+    if (!s)
+        return TMD_EINVAL;
+    if (!s->bound)
+        return fail(s, TMD_ESTATE, "no workspace bound");
+    if (need_state && !s->have_state)
+        return fail(s, TMD_ESTATE, "no state set");
+    return TMD_OK;
+}
+
+tmd_status rebuild(tmd_system *s, hipStream_t st) {
+    hipError_t e;
+    {
+        Timed t(s, TMD_T_BINNING, st);
+        e = launch_bin(s->g, s->b, s->cur, st);
+    }
+    if (e != hipSuccess)
+        return hip_fail(s, e, "binning");
+    s->cur = 1 - s->cur;
+    {
+        Timed t(s, TMD_T_NEIGHBOR, st);
+        e = launch_build(s->g, s->b, s->cur, st);
+    }
+    if (e != hipSuccess)
+        return hip_fail(s, e, "neighbor build");
+    s->list_valid = true;
+    s->force_valid = false;
+    return TMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tmd_status_string(tmd_status st) {
+    switch (st) {
+    case TMD_OK: return "ok";
+    case TMD_EINVAL: return "invalid argument";
+    case TMD_EBOX: return "cutoff + skin must be smaller than half the box length";
+    case TMD_ESTATE: return "invalid call order";
+    case TMD_ENBR_OVERFLOW: return "neighbor list capacity exceeded";
+    case TMD_ENONFINITE: return "non-finite position, velocity or force";
+    case TMD_EWORKSPACE: return "workspace too small or misaligned";
+    case TMD_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *tmd_last_error(const tmd_system *s) { return s ? s->err.c_str() : "NULL system"; }
+
+tmd_status tmd_create(const tmd_params *p, int64_t n_atoms, double L, tmd_system **out) {
+    if (!p || !out)
+        return TMD_EINVAL;
+    *out = nullptr;
+    if (n_atoms <= 0 || n_atoms > INT32_MAX)
+        return TMD_EINVAL;
+    if (!finite_pos(p->epsilon) || !finite_pos(p->sigma) || !finite_pos(p->mass) || !finite_pos(p->cutoff) ||
+        !finite_pos(p->dt) || !finite_pos(L) || !isfinite(p->skin) || p->skin < 0.0)
+        return TMD_EINVAL;
+    if (p->rebuild_every < 1 || p->max_neighbors < 1 || p->max_neighbors > 4096)
+        return TMD_EINVAL;
+    const double r = p->cutoff + p->skin;
+    if (!(r < 0.5 * L))
+        return TMD_EBOX;
+    const double ncd = floor(L / r);
+    if (ncd > 1290.0)  // keeps nc^3 cell counters within int32
+        return TMD_EINVAL;
+    tmd_system *s = new (std::nothrow) tmd_system();
+    if (!s)
+        return TMD_EINVAL;
+    s->p = *p;
+    Geom &g = s->g;
+    g.n = int32_t(n_atoms);
+    g.np = int32_t((n_atoms + 255) / 256 * 256);
+    g.nc = ncd < 1.0 ? 1 : int32_t(ncd);
+    g.ncell = g.nc * g.nc * g.nc;
+    g.maxnb = p->max_neighbors;
+    g.L = L;
+    g.halfL = 0.5 * L;
+    g.side = L / g.nc;
+    g.rc2 = p->cutoff * p->cutoff;
+    g.rl2 = r * r;
+    g.eps = p->epsilon;
+    const double s2 = p->sigma * p->sigma;
+    g.sigma6 = s2 * s2 * s2;
+    g.h = 0.5 * p->dt / p->mass;
+    g.dt = p->dt;
+    g.mass = p->mass;
+    if (int64_t(g.np) * g.maxnb > (int64_t(1) << 40)) {
+        delete s;
+        return TMD_EINVAL;
+    }
+    s->ws_need = carve(g, nullptr, nullptr);
+    *out = s;
+    return TMD_OK;
+}
+
+tmd_status tmd_workspace_size(const tmd_system *s, size_t *bytes) {
+    if (!s || !bytes)
+        return TMD_EINVAL;
+    *bytes = s->ws_need;
+    return TMD_OK;
+}
+
+tmd_status tmd_bind_workspace(tmd_system *s, void *dev, size_t bytes) {
+    if (!s || !dev)
+        return TMD_EINVAL;
+    if (bytes < s->ws_need || (reinterpret_cast<uintptr_t>(dev) % kAlign) != 0)
+        return fail(s, TMD_EWORKSPACE, "workspace must be 256-byte aligned and at least tmd_workspace_size bytes");
+    s->ws = dev;
+    carve(s->g, static_cast<char *>(dev), &s->b);
+    s->bound = true;
+    s->have_state = s->list_valid = s->force_valid = false;
+    s->cur = 0;
+    return TMD_OK;
+}
+
+tmd_status tmd_set_state(tmd_system *s, const double *const pos[3], const double *const vel[3], int64_t step,
+                         tmd_stream stream) {
+    tmd_status st = check_ready(s, false);
+    if (st != TMD_OK)
+        return st;
+    if (!pos || !vel || !pos[0] || !pos[1] || !pos[2] || !vel[0] || !vel[1] || !vel[2] || step < 0)
+        return fail(s, TMD_EINVAL, "set_state: NULL array or negative step");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    {
+        Timed t(s, TMD_T_COPY, hs);
+        e = launch_fill_i32(s->b.err, 0, 16, hs);
+        if (e == hipSuccess)
+            e = launch_load_state(s->g, pos, vel, s->b, 0, hs);
+    }
+    if (e != hipSuccess)
+        return hip_fail(s, e, "set_state");
+    s->cur = 0;
+    s->step = step;
+    s->have_state = true;
+    s->list_valid = s->force_valid = false;
+    return TMD_OK;
+}
+
+tmd_status tmd_build_neighbors(tmd_system *s, tmd_stream stream) {
+    tmd_status st = check_ready(s, true);
+    if (st != TMD_OK)
+        return st;
+    return rebuild(s, static_cast<hipStream_t>(stream));
+}
+
+tmd_status tmd_compute_forces(tmd_system *s, double *const f[3], double *ev, tmd_stream stream) {
+    tmd_status st = check_ready(s, true);
+    if (st != TMD_OK)
+        return st;
+    if (!s->list_valid)
+        return fail(s, TMD_ESTATE, "compute_forces: no neighbor list built since the state was set");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    {
+        Timed t(s, TMD_T_FORCE, hs);
+        e = launch_force(s->g, s->b, s->cur, 0, ev != nullptr, hs);
+    }
+    if (e != hipSuccess)
+        return hip_fail(s, e, "force");
+    s->force_valid = true;
+    if (ev) {
+        Timed t(s, TMD_T_THERMO, hs);
+        e = launch_reduce(s->g, s->b, ev, 2, hs);
+        if (e != hipSuccess)
+            return hip_fail(s, e, "reduce");
+    }
+    if (f && (f[0] || f[1] || f[2])) {
+        Timed t(s, TMD_T_COPY, hs);
+        e = launch_unload(s->g, s->b.fx, s->b.fy, s->b.fz, s->b.orig[s->cur], f, hs);
+        if (e != hipSuccess)
+            return hip_fail(s, e, "force unload");
+    }
+    return TMD_OK;
+}
+
+tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, double *thermo, tmd_stream stream) {
+    tmd_status st = check_ready(s, true);
+    if (st != TMD_OK)
+        return st;
+    if (n_steps < 0 || thermo_every < 0 || (thermo_every > 0 && !thermo))
+        return fail(s, TMD_EINVAL, "integrate: negative count or thermo_every > 0 without a thermo buffer");
+    if (n_steps == 0)
+        return TMD_OK;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (!s->list_valid && (st = rebuild(s, hs)) != TMD_OK)
+        return st;
+    if (!s->force_valid) {
+        Timed t(s, TMD_T_FORCE, hs);
+        e = launch_force(s->g, s->b, s->cur, 0, false, hs);
+        if (e != hipSuccess)
+            return hip_fail(s, e, "force");
+        s->force_valid = true;
+    }
+    {
+        Timed t(s, TMD_T_DRIFT, hs);
+        e = launch_drift(s->g, s->b, s->cur, hs);
+    }
+    if (e != hipSuccess)
+        return hip_fail(s, e, "drift");
+    s->cur = 1 - s->cur;
+    s->force_valid = false;
+    const int64_t rb = s->p.rebuild_every;
+    for (int32_t k = 1; k <= n_steps; ++k) {
+        const int64_t stepk = s->step + k;
+        if (stepk % rb == 0 && (st = rebuild(s, hs)) != TMD_OK)
+            return st;
+        const bool th = thermo_every > 0 && (k % thermo_every) == 0;
+        const int mode = (k < n_steps) ? 2 : 1;
+        {
+            Timed t(s, TMD_T_FORCE, hs);
+            e = launch_force(s->g, s->b, s->cur, mode, th, hs);
+        }
+        if (e != hipSuccess)
+            return hip_fail(s, e, "force");
+        if (mode == 2)
+            s->cur = 1 - s->cur;
+        if (th) {
+            Timed t(s, TMD_T_THERMO, hs);
+            e = launch_reduce(s->g, s->b, thermo + int64_t(k / thermo_every - 1) * 5, 5, hs);
+            if (e != hipSuccess)
+                return hip_fail(s, e, "reduce");
+        }
+    }
+    s->force_valid = true;
+    s->step += n_steps;
+    return TMD_OK;
+}
+
+tmd_status tmd_get_state(const tmd_system *cs, double *const pos[3], double *const vel[3], int64_t *step,
+                         tmd_stream stream) {
+    tmd_system *s = const_cast<tmd_system *>(cs);
+    tmd_status st = check_ready(s, true);
+    if (st != TMD_OK)
+        return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int c = s->cur;
+    Timed t(s, TMD_T_COPY, hs);
+    if (pos) {
+        hipError_t e = launch_unload(s->g, s->b.x[c], s->b.y[c], s->b.z[c], s->b.orig[c], pos, hs);
+        if (e != hipSuccess)
+            return hip_fail(s, e, "get_state");
+    }
+    if (vel) {
+        hipError_t e = launch_unload(s->g, s->b.vx[c], s->b.vy[c], s->b.vz[c], s->b.orig[c], vel, hs);
+        if (e != hipSuccess)
+            return hip_fail(s, e, "get_state");
+    }
+    if (step)
+        *step = s->step;
+    return TMD_OK;
+}
+
+tmd_status tmd_get_neighbors(const tmd_system *cs, int32_t *counts, int32_t *ids, int64_t capacity,
+                             tmd_stream stream) {
+    tmd_system *s = const_cast<tmd_system *>(cs);
+    tmd_status st = check_ready(s, true);
+    if (st != TMD_OK)
+        return st;
+    if (!counts || !ids || capacity < int64_t(s->g.n) * s->g.maxnb)
+        return fail(s, TMD_EINVAL, "get_neighbors: NULL buffer or capacity below n_atoms * max_neighbors");
+    if (!s->list_valid)
+        return fail(s, TMD_ESTATE, "get_neighbors: no list built since the state was set");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    Timed t(s, TMD_T_COPY, hs);
+    hipError_t e = launch_export_neighbors(s->g, s->b, s->cur, counts, ids, hs);
+    return e == hipSuccess ? TMD_OK : hip_fail(s, e, "get_neighbors");
+}
+
+tmd_status tmd_sync(tmd_system *s, tmd_stream stream) {
+    tmd_status st = check_ready(s, false);
+    if (st != TMD_OK)
+        return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    int32_t w[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(w, s->b.err, sizeof(w), hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(hs);
+    if (e != hipSuccess)
+        return hip_fail(s, e, "sync");
+    if (w[0] & kErrNonFinite)
+        return fail(s, TMD_ENONFINITE, "a position, velocity or force became NaN/Inf (coincident atoms?)");
+    if (w[0] & kErrOverflow)
+        return fail(s, TMD_ENBR_OVERFLOW, "an atom has " + std::to_string(w[1]) + " list entries, max_neighbors is " +
+                                              std::to_string(s->g.maxnb));
+    if (w[0] & kErrOutOfBox)
+        return fail(s, TMD_EINVAL, "set_state: a coordinate lies outside [-L, 2L)");
+    return TMD_OK;
+}
+
+tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
+    if (!s || !info)
+        return TMD_EINVAL;
+    info->n_atoms = s->g.n;
+    info->n_padded = s->g.np;
+    info->cells_per_axis = s->g.nc;
+    info->max_neighbors = s->g.maxnb;
+    info->n_cells = s->g.ncell;
+    info->workspace_bytes = s->ws_need;
+    info->step = s->step;
+    return TMD_OK;
+}
+
+tmd_status tmd_set_timing(tmd_system *s, int32_t enable) {
+    if (!s)
+        return TMD_EINVAL;
+    s->timing = enable != 0;
+    return TMD_OK;
+}
+
+tmd_status tmd_get_timing(tmd_system *s, double *ms, int64_t *launches) {
+    if (!s || !ms || !launches)
+        return TMD_EINVAL;
+    for (auto &ev : s->pending) {
+        hipError_t e = hipEventSynchronize(ev.b);
+        float t = 0.0f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&t, ev.a, ev.b);
+        if (e != hipSuccess)
+            return hip_fail(s, e, "get_timing");
+        s->t_ms[ev.cls] += t;
+        s->t_n[ev.cls] += 1;
+        s->pool.push_back(ev.a);
+        s->pool.push_back(ev.b);
+    }
+    s->pending.clear();
+    for (int k = 0; k < TMD_T_COUNT; ++k) {
+        ms[k] = s->t_ms[k];
+        launches[k] = s->t_n[k];
+        s->t_ms[k] = 0.0;
+        s->t_n[k] = 0;
+    }
+    return TMD_OK;
+}
+
+void tmd_destroy(tmd_system *s) {
+    if (!s)
+        return;
+    for (auto &ev : s->pending) {
+        (void)hipEventSynchronize(ev.b);
+        (void)hipEventDestroy(ev.a);
+        (void)hipEventDestroy(ev.b);
+    }
+    for (hipEvent_t e : s->pool)
+        (void)hipEventDestroy(e);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point declared in include/tmd.h, and validates arguments synchronously.
+Nothing here launches GPU work."""
+
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_2009_07400_amd import _abi as abi
+from paper_2009_07400_amd.system import make_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tmd_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = abi.load_library()
+    names = _declared("tmd.h")
+    assert "tmd_create" in names and "tmd_integrate" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for st in range(0, -8, -1):
+        s = abi.tmd_status_string(st)
+        assert s and s != "unknown status"
+    assert abi.tmd_status_string(-99) == "unknown status"
+
+
+def _create(n=2048, L=13.43677, **kw):
+    return abi.tmd_create(make_params(**kw), n, L)
+
+
+def test_create_and_info():
+    h = _create()
+    try:
+        info = abi.tmd_get_info(h)
+        assert info["n_atoms"] == 2048
+        assert info["cells_per_axis"] == math.floor(13.43677 / 2.8) == 4
+        assert info["n_cells"] == 64
+        assert info["n_padded"] % 256 == 0 and info["n_padded"] >= 2048
+        assert info["workspace_bytes"] == abi.tmd_workspace_size(h)
+        # the list alone needs max_neighbors int32 per padded atom
+        assert info["workspace_bytes"] > info["n_padded"] * 128 * 4
+    finally:
+        abi.tmd_destroy(h)
+
+
+@pytest.mark.parametrize("kw,n,L,status", [
+    ({}, 0, 13.4, abi.TMD_EINVAL),
+    ({}, -5, 13.4, abi.TMD_EINVAL),
+    ({"epsilon": -1.0}, 10, 13.4, abi.TMD_EINVAL),
+    ({"sigma": 0.0}, 10, 13.4, abi.TMD_EINVAL),
+    ({"dt": float("nan")}, 10, 13.4, abi.TMD_EINVAL),
+    ({"mass": float("inf")}, 10, 13.4, abi.TMD_EINVAL),
+    ({"skin": -0.1}, 10, 13.4, abi.TMD_EINVAL),
+    ({"rebuild_every": 0}, 10, 13.4, abi.TMD_EINVAL),
+    ({"max_neighbors": 0}, 10, 13.4, abi.TMD_EINVAL),
+    ({"max_neighbors": 5000}, 10, 13.4, abi.TMD_EINVAL),
+    ({}, 10, float("nan"), abi.TMD_EINVAL),
+    ({}, 10, 5.6, abi.TMD_EBOX),      # cutoff + skin = 2.8 = L/2
+    ({}, 10, 5.0, abi.TMD_EBOX),
+])
+def test_create_rejects(kw, n, L, status):
+    with pytest.raises(abi.TmdError) as e:
+        _create(n=n, L=L, **kw)
+    assert e.value.status == status
+
+
+def test_smallest_valid_box_and_cell_counts():
+    h = _create(n=10, L=5.6000001)
+    assert abi.tmd_get_info(h)["cells_per_axis"] == 2
+    abi.tmd_destroy(h)
+    h = _create(n=3538944, L=161.24123)
+    info = abi.tmd_get_info(h)
+    assert info["cells_per_axis"] == 57 and info["n_cells"] == 57 ** 3
+    abi.tmd_destroy(h)
+
+
+def test_call_order_and_workspace_checks():
+    h = _create()
+    try:
+        # no workspace bound: every device call is refused before touching the GPU
+        for fn in (lambda: abi.tmd_build_neighbors(h, 0),
+                   lambda: abi.tmd_integrate(h, 10, 0, None, 0),
+                   lambda: abi.tmd_compute_forces(h, None, None, 0),
+                   lambda: abi.tmd_sync(h, 0)):
+            with pytest.raises(abi.TmdError) as e:
+                fn()
+            assert e.value.status == abi.TMD_ESTATE
+        need = abi.tmd_workspace_size(h)
+        with pytest.raises(abi.TmdError) as e:  # misaligned
+            abi.tmd_bind_workspace(h, 0x10000 + 8, need)
+        assert e.value.status == abi.TMD_EWORKSPACE
+        with pytest.raises(abi.TmdError) as e:  # too small
+            abi.tmd_bind_workspace(h, 0x10000, need - 1)
+        assert e.value.status == abi.TMD_EWORKSPACE
+        assert "256-byte" in abi.tmd_last_error(h)
+    finally:
+        abi.tmd_destroy(h)
+
+
+def test_null_arguments():
+    lib = abi.load_library()
+    assert lib.tmd_create(None, 10, 13.4, None) == abi.TMD_EINVAL
+    assert lib.tmd_workspace_size(None, None) == abi.TMD_EINVAL
+    assert lib.tmd_get_info(None, None) == abi.TMD_EINVAL
+    assert lib.tmd_sync(None, None) == abi.TMD_EINVAL
+    lib.tmd_destroy(None)
+    assert abi.tmd_last_error(None) == "NULL system"
+    out = C.c_void_p()
+    p = make_params()
+    assert lib.tmd_create(C.byref(p), 10, 13.4, C.byref(out)) == abi.TMD_OK
+    assert lib.tmd_set_timing(out, 1) == abi.TMD_OK
+    lib.tmd_destroy(out)
