@@ -20,7 +20,7 @@ struct tmd_system {
     size_t ws_need = 0;
     void *ws = nullptr;
     Buffers b{};
-    int cur = 0;
+    Cursor cur;
     bool bound = false, have_state = false, list_valid = false, force_valid = false;
     int64_t step = 0;
     std::string err;
@@ -145,7 +145,8 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "binning");
-    s->cur = 1 - s->cur;
+    s->cur.x = 1 - s->cur.x;
+    s->cur.o = 1 - s->cur.o;
     {
         Timed t(s, TMD_T_NEIGHBOR, st);
         e = launch_build(s->g, s->b, s->cur, st);
@@ -240,7 +241,7 @@ tmd_status tmd_bind_workspace(tmd_system *s, void *dev, size_t bytes) {
     carve(s->g, static_cast<char *>(dev), &s->b);
     s->bound = true;
     s->have_state = s->list_valid = s->force_valid = false;
-    s->cur = 0;
+    s->cur = Cursor{};
     return TMD_OK;
 }
 
@@ -257,11 +258,11 @@ tmd_status tmd_set_state(tmd_system *s, const double *const pos[3], const double
         Timed t(s, TMD_T_COPY, hs);
         e = launch_fill_i32(s->b.err, 0, 16, hs);
         if (e == hipSuccess)
-            e = launch_load_state(s->g, pos, vel, s->b, 0, hs);
+            e = launch_load_state(s->g, pos, vel, s->b, Cursor{}, hs);
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "set_state");
-    s->cur = 0;
+    s->cur = Cursor{};
     s->step = step;
     s->have_state = true;
     s->list_valid = s->force_valid = false;
@@ -298,7 +299,7 @@ tmd_status tmd_compute_forces(tmd_system *s, double *const f[3], double *ev, tmd
     }
     if (f && (f[0] || f[1] || f[2])) {
         Timed t(s, TMD_T_COPY, hs);
-        e = launch_unload(s->g, s->b.fx, s->b.fy, s->b.fz, s->b.orig[s->cur], f, hs);
+        e = launch_unload(s->g, s->b.fx, s->b.fy, s->b.fz, s->b.orig[s->cur.o], f, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "force unload");
     }
@@ -330,7 +331,7 @@ tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, d
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "drift");
-    s->cur = 1 - s->cur;
+    s->cur.x = 1 - s->cur.x;
     s->force_valid = false;
     const int64_t rb = s->p.rebuild_every;
     for (int32_t k = 1; k <= n_steps; ++k) {
@@ -346,7 +347,7 @@ tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, d
         if (e != hipSuccess)
             return hip_fail(s, e, "force");
         if (mode == 2)
-            s->cur = 1 - s->cur;
+            s->cur.x = 1 - s->cur.x;
         if (th) {
             Timed t(s, TMD_T_THERMO, hs);
             e = launch_reduce(s->g, s->b, thermo + int64_t(k / thermo_every - 1) * 5, 5, hs);
@@ -366,15 +367,15 @@ tmd_status tmd_get_state(const tmd_system *cs, double *const pos[3], double *con
     if (st != TMD_OK)
         return st;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    const int c = s->cur;
+    const int c = s->cur.x, o = s->cur.o;
     Timed t(s, TMD_T_COPY, hs);
     if (pos) {
-        hipError_t e = launch_unload(s->g, s->b.x[c], s->b.y[c], s->b.z[c], s->b.orig[c], pos, hs);
+        hipError_t e = launch_unload(s->g, s->b.x[c], s->b.y[c], s->b.z[c], s->b.orig[o], pos, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "get_state");
     }
     if (vel) {
-        hipError_t e = launch_unload(s->g, s->b.vx[c], s->b.vy[c], s->b.vz[c], s->b.orig[c], vel, hs);
+        hipError_t e = launch_unload(s->g, s->b.vx[o], s->b.vy[o], s->b.vz[o], s->b.orig[o], vel, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "get_state");
     }

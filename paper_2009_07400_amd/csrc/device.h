@@ -1,0 +1,99 @@
+// Device-side building blocks shared by the kernels: periodic pair geometry,
+// cell coordinates, the LJ pair force, reciprocal, and deterministic wave /
+// workgroup sums.  Method: tinyMD (arXiv 2009.07400), Sec. 3.2 Eq. 2 and the
+// compute_potential example of Sec. 4.2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace tmd {
+
+// Minimum-image difference along one axis: shift d by one box length when
+// |d| > L/2 (positions are kept in [0, L), so one shift suffices).
+__device__ __forceinline__ double mic(double d, double L, double halfL) {
+    d = (d > halfL) ? d - L : d;
+    d = (d < -halfL) ? d + L : d;
+    return d;
+}
+
+// |d|^2 summed left to right without fused multiply-add, so that the
+// comparison against cutoff^2 and (cutoff + skin)^2 takes the same decision
+// as any other IEEE evaluation of dx*dx + dy*dy + dz*dz in that order.
+__device__ __forceinline__ double dist2(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Pair difference vector with periodic images.  Only atoms near a face of
+// the box have partners across it; for every other pair the raw difference
+// already is the minimum image.  The correction sits behind a branch that a
+// wavefront takes only when one of its lanes needs it, and applies the same
+// per-axis rule as mic(), so the result is bit-identical to it.
+__device__ __forceinline__ double pair_delta(double xi, double yi, double zi, double xj, double yj, double zj,
+                                            double L, double halfL, double &dx, double &dy, double &dz) {
+    dx = xi - xj;
+    dy = yi - yj;
+    dz = zi - zj;
+    const bool wrapped = int(fabs(dx) > halfL) | int(fabs(dy) > halfL) | int(fabs(dz) > halfL);
+    if (wrapped) {
+        dx = mic(dx, L, halfL);
+        dy = mic(dy, L, halfL);
+        dz = mic(dz, L, halfL);
+    }
+    return dist2(dx, dy, dz);
+}
+
+// 1/s for s > 0: hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - s r), each of which roughly squares the relative
+// error; the result is within an ulp or two of the correctly rounded value.
+__device__ __forceinline__ double recip(double s) {
+    double r = __builtin_amdgcn_rcp(s);
+    double e = fma(-s, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-s, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Wrap a coordinate that moved by less than one box length into [0, L).
+__device__ __forceinline__ double wrap(double p, double L) {
+    if (p >= L)
+        p -= L;
+    if (p < 0.0)
+        p += L;
+    return p;
+}
+
+// Cell index along one axis, clamped to [0, nc) (also for NaN input).
+__device__ __forceinline__ int cell_coord(double p, double side, int nc) {
+    double q = floor(p / side);
+    if (!(q >= 0.0))
+        q = 0.0;
+    if (q > double(nc - 1))
+        q = double(nc - 1);
+    return int(q);
+}
+
+// Distinct cells c-1, c, c+1 (periodic) along one axis; fewer when the axis
+// has fewer than three cells, so no cell is visited twice.
+__device__ __forceinline__ int stencil_axis(int c, int nc, int out[3]) {
+    if (nc >= 3) {
+        out[0] = (c == 0) ? nc - 1 : c - 1;
+        out[1] = c;
+        out[2] = (c == nc - 1) ? 0 : c + 1;
+        return 3;
+    }
+    out[0] = 0;
+    out[1] = 1;
+    return nc;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace tmd

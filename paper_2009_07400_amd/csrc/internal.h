@@ -56,21 +56,29 @@ inline int atom_grid(int n) {
 }
 inline int scan_blocks(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
 
+// Which half of each double buffer is current: positions flip on every drift
+// and every binning; velocities and original ids flip only on binning (the
+// kicks update velocities in place).
+struct Cursor {
+    int x = 0;  // positions
+    int o = 0;  // atom order: velocities and original ids
+};
+
 // Launchers (kernels.hip).  All enqueue on `s` and return the launch status.
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_load_state(const Geom &g, const double *const pos[3], const double *const vel[3],
-                             Buffers &b, int cur, hipStream_t s);
+                             Buffers &b, Cursor c, hipStream_t s);
 hipError_t launch_unload(const Geom &g, const double *ax, const double *ay, const double *az,
                          const int32_t *orig, double *const out[3], hipStream_t s);
-hipError_t launch_bin(const Geom &g, Buffers &b, int cur, hipStream_t s);  // cur -> 1 - cur
-hipError_t launch_build(const Geom &g, Buffers &b, int cur, hipStream_t s);
-// mode 0: F only (stored); 1: F + kick (stored, end of integrate); 2: F + kick + kick + drift into 1-cur
-hipError_t launch_force(const Geom &g, Buffers &b, int cur, int mode, bool thermo, hipStream_t s);
-hipError_t launch_drift(const Geom &g, Buffers &b, int cur, hipStream_t s);
+hipError_t launch_bin(const Geom &g, Buffers &b, Cursor c, hipStream_t s);  // both halves flip
+hipError_t launch_build(const Geom &g, Buffers &b, Cursor c, hipStream_t s);
+// mode 0: F only (stored); 1: F + kick (stored, end of integrate); 2: F + kick + kick + drift into 1 - c.x
+hipError_t launch_force(const Geom &g, Buffers &b, Cursor c, int mode, bool thermo, hipStream_t s);
+hipError_t launch_drift(const Geom &g, Buffers &b, Cursor c, hipStream_t s);  // positions into 1 - c.x
 // Deterministic sum of the force kernel's workgroup partials.  Writes
 // (U, W) when row_len == 2 or (KE, T, U, W, E) when row_len == 5.
 hipError_t launch_reduce(const Geom &g, const Buffers &b, double *out, int row_len, hipStream_t s);
-hipError_t launch_export_neighbors(const Geom &g, const Buffers &b, int cur, int32_t *counts, int32_t *ids,
+hipError_t launch_export_neighbors(const Geom &g, const Buffers &b, Cursor c, int32_t *counts, int32_t *ids,
                                    hipStream_t s);
 
 }  // namespace tmd

@@ -534,10 +534,10 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_load_state(const Geom &g, const double *const pos[3], const double *const vel[3], Buffers &b,
-                             int cur, hipStream_t s) {
+                             Cursor c, hipStream_t s) {
     k_load_state<<<blocks_for(g.n, kBlock), kBlock, 0, s>>>(g, pos[0], pos[1], pos[2], vel[0], vel[1], vel[2],
-                                                            b.x[cur], b.y[cur], b.z[cur], b.vx[cur], b.vy[cur],
-                                                            b.vz[cur], b.orig[cur], b.err);
+                                                            b.x[c.x], b.y[c.x], b.z[c.x], b.vx[c.o], b.vy[c.o],
+                                                            b.vz[c.o], b.orig[c.o], b.err);
     return hipGetLastError();
 }
 
@@ -547,8 +547,8 @@ hipError_t launch_unload(const Geom &g, const double *ax, const double *ay, cons
     return hipGetLastError();
 }
 
-hipError_t launch_bin(const Geom &g, Buffers &b, int cur, hipStream_t s) {
-    const int nxt = 1 - cur;
+hipError_t launch_bin(const Geom &g, Buffers &b, Cursor c, hipStream_t s) {
+    const int cur = c.x, nxt = 1 - c.x, o = c.o, on = 1 - c.o;
     hipError_t e = launch_fill_i32(b.cell_count, 0, g.ncell, s);
     if (e != hipSuccess)
         return e;
@@ -559,28 +559,28 @@ hipError_t launch_bin(const Geom &g, Buffers &b, int cur, hipStream_t s) {
     k_scan_sums<<<1, 1024, 0, s>>>(b.scan_sums, nt, b.cell_start, g.ncell);
     k_scan_add<<<blocks_for(g.ncell, 256), 256, 0, s>>>(b.cell_start, b.scan_sums, g.ncell);
     k_scatter<<<blocks_for(g.n, kBlock), kBlock, 0, s>>>(g.n, b.cell_of, b.slot, b.cell_start, b.tmp_idx);
-    k_cell_sort<<<blocks_for(g.ncell, kBlock), kBlock, 0, s>>>(g.ncell, b.cell_start, b.tmp_idx, b.orig[cur]);
-    k_permute<<<blocks_for(g.n, kBlock), kBlock, 0, s>>>(g.n, b.tmp_idx, b.x[cur], b.y[cur], b.z[cur], b.vx[cur],
-                                                         b.vy[cur], b.vz[cur], b.orig[cur], b.x[nxt], b.y[nxt],
-                                                         b.z[nxt], b.vx[nxt], b.vy[nxt], b.vz[nxt], b.orig[nxt]);
+    k_cell_sort<<<blocks_for(g.ncell, kBlock), kBlock, 0, s>>>(g.ncell, b.cell_start, b.tmp_idx, b.orig[o]);
+    k_permute<<<blocks_for(g.n, kBlock), kBlock, 0, s>>>(g.n, b.tmp_idx, b.x[cur], b.y[cur], b.z[cur], b.vx[o],
+                                                         b.vy[o], b.vz[o], b.orig[o], b.x[nxt], b.y[nxt],
+                                                         b.z[nxt], b.vx[on], b.vy[on], b.vz[on], b.orig[on]);
     return hipGetLastError();
 }
 
-hipError_t launch_build(const Geom &g, Buffers &b, int cur, hipStream_t s) {
-    k_build<<<atom_grid(g.n), kBlock, 0, s>>>(g, b.x[cur], b.y[cur], b.z[cur], b.cell_start, b.nbr_count, b.nbr,
+hipError_t launch_build(const Geom &g, Buffers &b, Cursor c, hipStream_t s) {
+    k_build<<<atom_grid(g.n), kBlock, 0, s>>>(g, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.nbr_count, b.nbr,
                                               b.err);
     return hipGetLastError();
 }
 
 template <int MODE, bool THERMO>
-static void force_variant(const Geom &g, Buffers &b, int cur, hipStream_t s) {
-    const int nxt = 1 - cur;
+static void force_variant(const Geom &g, Buffers &b, Cursor c, hipStream_t s) {
+    const int cur = c.x, nxt = 1 - c.x;
     k_force<MODE, THERMO><<<atom_grid(g.n), kBlock, 0, s>>>(
-        g, b.x[cur], b.y[cur], b.z[cur], b.nbr_count, b.nbr, b.vx[cur], b.vy[cur], b.vz[cur], b.fx, b.fy, b.fz,
+        g, b.x[cur], b.y[cur], b.z[cur], b.nbr_count, b.nbr, b.vx[c.o], b.vy[c.o], b.vz[c.o], b.fx, b.fy, b.fz,
         b.x[nxt], b.y[nxt], b.z[nxt], b.partials, b.err);
 }
 
-hipError_t launch_force(const Geom &g, Buffers &b, int cur, int mode, bool thermo, hipStream_t s) {
+hipError_t launch_force(const Geom &g, Buffers &b, Cursor cur, int mode, bool thermo, hipStream_t s) {
     switch (mode * 2 + (thermo ? 1 : 0)) {
     case 0: force_variant<0, false>(g, b, cur, s); break;
     case 1: force_variant<0, true>(g, b, cur, s); break;
@@ -593,10 +593,10 @@ hipError_t launch_force(const Geom &g, Buffers &b, int cur, int mode, bool therm
     return hipGetLastError();
 }
 
-hipError_t launch_drift(const Geom &g, Buffers &b, int cur, hipStream_t s) {
-    const int nxt = 1 - cur;
-    k_drift<<<blocks_for(g.n, kBlock), kBlock, 0, s>>>(g, b.x[cur], b.y[cur], b.z[cur], b.vx[cur], b.vy[cur],
-                                                       b.vz[cur], b.fx, b.fy, b.fz, b.x[nxt], b.y[nxt], b.z[nxt],
+hipError_t launch_drift(const Geom &g, Buffers &b, Cursor c, hipStream_t s) {
+    const int cur = c.x, nxt = 1 - c.x;
+    k_drift<<<blocks_for(g.n, kBlock), kBlock, 0, s>>>(g, b.x[cur], b.y[cur], b.z[cur], b.vx[c.o], b.vy[c.o],
+                                                       b.vz[c.o], b.fx, b.fy, b.fz, b.x[nxt], b.y[nxt], b.z[nxt],
                                                        b.err);
     return hipGetLastError();
 }
@@ -606,9 +606,9 @@ hipError_t launch_reduce(const Geom &g, const Buffers &b, double *out, int row_l
     return hipGetLastError();
 }
 
-hipError_t launch_export_neighbors(const Geom &g, const Buffers &b, int cur, int32_t *counts, int32_t *ids,
+hipError_t launch_export_neighbors(const Geom &g, const Buffers &b, Cursor c, int32_t *counts, int32_t *ids,
                                    hipStream_t s) {
-    k_export_neighbors<<<blocks_for(g.n, kBlock), kBlock, 0, s>>>(g, b.nbr_count, b.nbr, b.orig[cur], counts, ids);
+    k_export_neighbors<<<blocks_for(g.n, kBlock), kBlock, 0, s>>>(g, b.nbr_count, b.nbr, b.orig[c.o], counts, ids);
     return hipGetLastError();
 }
 
