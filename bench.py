@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
 METRIC = "atom-steps/s (FP64 LJ) at 131k & 3.5M atoms; batched, adjoint vs plain"
-KERNEL_SRC = os.path.join(ROOT, "paper_2009_07400_amd", "csrc", "kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2009_07400_amd", "csrc", "engine.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
 
 WORKLOADS = {
@@ -108,7 +108,7 @@ def run_gpu(workload: str, steps: int, warmup: int):
         "kernel_ms": {k: (v[0] / max(v[1], 1), v[1]) for k, v in tm.items() if v[1]},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_force<2,false> (force + kick + kick + drift, fused)",
+            "kernel": "k_force<2,false>: LDS-staged block force + kick + kick + drift",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -146,6 +146,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3.5M-atom secondary workload")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="before the run, copy a 1 GiB buffer 3 times with torch: a kernel of known traffic "
+                         "(1 GiB read + 1 GiB written per launch) to calibrate FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
@@ -158,6 +161,13 @@ def main():
         print(json.dumps({"error": "no GPU available"}))
         sys.exit(1)
     steps = args.steps if args.steps is not None else WORKLOADS[args.workload]["steps"]
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prim = run_gpu(args.workload, steps, args.warmup)
     print(f"# primary {args.workload}: {prim['value']:.4g} atom-steps/s, {prim['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)

@@ -70,13 +70,17 @@ typedef void *tmd_stream;             /* hipStream_t */
 
 /* Read-only facts about a created system (host values). */
 typedef struct {
-    int64_t n_atoms;
+    int64_t n_atoms;         /* all boxes together */
     int64_t n_padded;        /* row stride of the neighbor-major list */
-    int32_t cells_per_axis;  /* floor(L / (cutoff + skin)) */
+    int32_t cells_per_axis;  /* floor(L / (cutoff + skin)) of box 0 */
     int32_t max_neighbors;
-    int64_t n_cells;
+    int64_t n_cells;         /* cells of all boxes */
     size_t workspace_bytes;
     int64_t step;            /* time-step counter of the current state */
+    int32_t n_boxes;
+    int32_t n_blocks;        /* blocks of 2x2x2 cells, one workgroup each */
+    int32_t block_threads;   /* threads per block workgroup */
+    int32_t lds_atoms;       /* atoms of a block neighborhood staged in LDS */
 } tmd_info;
 
 /* Kernel classes reported by tmd_get_timing(). */
@@ -97,6 +101,18 @@ enum {
  * [1, 4096]; TMD_EBOX when cutoff + skin >= box_length / 2.  On success *out
  * owns a handle to release with tmd_destroy(). */
 tmd_status tmd_create(const tmd_params *params, int64_t n_atoms, double box_length, tmd_system **out);
+
+/* Create one system holding n_boxes independent periodic cubes (replicas)
+ * that every later call advances together, in the same kernel launches.
+ * Box k has n_atoms[k] atoms, side box_lengths[k] and parameters params[k];
+ * its atoms occupy the slots [sum_{m<k} n_atoms[m], ...) of every per-atom
+ * array the caller exchanges (concatenated original order).  All boxes must
+ * share rebuild_every and max_neighbors (TMD_EINVAL otherwise); every other
+ * check of tmd_create() applies per box.  Outputs that are per system in
+ * tmd_create() become per box (see tmd_compute_forces, tmd_integrate).
+ * With n_boxes == 1 this is tmd_create(). */
+tmd_status tmd_create_batch(int32_t n_boxes, const int64_t *n_atoms, const double *box_lengths,
+                            const tmd_params *params, tmd_system **out);
 
 /* Bytes of device workspace the system needs (host only). */
 tmd_status tmd_workspace_size(const tmd_system *sys, size_t *bytes);
@@ -127,9 +143,9 @@ tmd_status tmd_build_neighbors(tmd_system *sys, tmd_stream stream);
  *   F_i = sum_{j in list(i), |x_ij|^2 < cutoff^2} f(s) x_ij,
  *   f(s) = 48 eps (sigma^6/s^3) (sigma^6/s^3 - 1/2) / s   (Sec. 3.2 Eq. 2; Sec. 4.2 listing)
  * f[3] (nullable) receives F in original order (device, n_atoms doubles each).
- * energy_virial (nullable, device, 2 doubles) receives
+ * energy_virial (nullable, device, 2 doubles per box, box-major) receives
  *   U = 1/2 sum_i sum_j 4 eps [(sigma^6/s^3)^2 - sigma^6/s^3]  (unshifted) and
- *   W = 1/2 sum_i sum_j s f(s).
+ *   W = 1/2 sum_i sum_j s f(s), summed in a fixed order (bitwise reproducible).
  * TMD_ESTATE if no list has been built since the last tmd_set_state(). */
 tmd_status tmd_compute_forces(tmd_system *sys, double *const f[3], double *energy_virial, tmd_stream stream);
 
@@ -139,9 +155,11 @@ tmd_status tmd_compute_forces(tmd_system *sys, double *const f[3], double *energ
  *   F = F(x);  v += dt/(2m) F
  * where `step` is the absolute step counter (so the schedule survives split
  * calls).  Builds the list first if none is valid.  With thermo_every > 0,
- * thermo (device, nullable) receives one row of 5 doubles (KE, T, U, W, E) for
- * every step that is a multiple of thermo_every within the call, in order;
- * T = 2 KE / (3N - 3), E = KE + U.  n_steps == 0 is a no-op. */
+ * thermo (device, nullable) receives, for every step k (1-based within the
+ * call) that is a multiple of thermo_every, one row of 5 doubles
+ * (KE, T, U, W, E) per box: thermo[((k / thermo_every - 1) * n_boxes + box) * 5
+ * + q]; T = 2 KE / (3N - 3) with N the box's atoms (0 for N = 1), E = KE + U.
+ * n_steps == 0 is a no-op. */
 tmd_status tmd_integrate(tmd_system *sys, int32_t n_steps, int32_t thermo_every, double *thermo,
                          tmd_stream stream);
 
@@ -159,11 +177,28 @@ tmd_status tmd_get_neighbors(const tmd_system *sys, int32_t *counts, int32_t *id
                              tmd_stream stream);
 
 /* Wait for the stream and return the deferred device status (TMD_OK,
- * TMD_ENBR_OVERFLOW or TMD_ENONFINITE), or TMD_EHIP. */
+ * TMD_ENBR_OVERFLOW, TMD_ENONFINITE, or TMD_EINVAL for a coordinate passed to
+ * tmd_set_state() outside [-L, 2L)), or TMD_EHIP. */
 tmd_status tmd_sync(tmd_system *sys, tmd_stream stream);
 
 /* Host-side facts about the system. */
 tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
+
+/* Work schedule of the block kernels; neither value changes any result.
+ * threads: threads per block workgroup, a multiple of 64 in [64, 256] (0
+ * keeps the current value).  lds_atoms: how many atoms of a block's
+ * neighborhood may be staged in LDS, a multiple of 64 in [64, 2560] (0 keeps
+ * the current value); blocks whose neighborhood holds more atoms gather from
+ * global memory instead.  Changing lds_atoms marks the list stale (the next
+ * integrate rebuilds it; compute_forces needs tmd_build_neighbors first).
+ * TMD_EINVAL for other values. */
+tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms);
+
+/* Pick the block_threads value with the shortest force-kernel time for the
+ * current state: times `repeats` force evaluations per candidate on `stream`
+ * with HIP events (synchronises; positions and velocities are not changed;
+ * builds the list first if none is valid). */
+tmd_status tmd_autotune(tmd_system *sys, int32_t repeats, tmd_stream stream);
 
 /* Per-kernel-class timing with HIP events recorded on the launch stream around
  * every kernel (only while enabled).  tmd_get_timing() synchronises, then

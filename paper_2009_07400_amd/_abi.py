@@ -48,6 +48,10 @@ class TmdInfo(C.Structure):
         ("n_cells", C.c_int64),
         ("workspace_bytes", C.c_size_t),
         ("step", C.c_int64),
+        ("n_boxes", C.c_int32),
+        ("n_blocks", C.c_int32),
+        ("block_threads", C.c_int32),
+        ("lds_atoms", C.c_int32),
     ]
 
 
@@ -73,6 +77,8 @@ def load_library():
     lib = C.CDLL(LIB_PATH)
     sig = {
         "tmd_create": (_S, [C.POINTER(TmdParams), C.c_int64, C.c_double, C.POINTER(_P)]),
+        "tmd_create_batch": (_S, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(TmdParams),
+                                  C.POINTER(_P)]),
         "tmd_workspace_size": (_S, [_P, C.POINTER(C.c_size_t)]),
         "tmd_bind_workspace": (_S, [_P, _P, C.c_size_t]),
         "tmd_set_state": (_S, [_P, _P, _P, C.c_int64, _P]),
@@ -83,6 +89,8 @@ def load_library():
         "tmd_get_neighbors": (_S, [_P, _P, _P, C.c_int64, _P]),
         "tmd_sync": (_S, [_P, _P]),
         "tmd_get_info": (_S, [_P, C.POINTER(TmdInfo)]),
+        "tmd_set_schedule": (_S, [_P, C.c_int32, C.c_int32]),
+        "tmd_autotune": (_S, [_P, C.c_int32, _P]),
         "tmd_set_timing": (_S, [_P, C.c_int32]),
         "tmd_get_timing": (_S, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "tmd_status_string": (C.c_char_p, [_S]),
@@ -126,6 +134,17 @@ def tmd_last_error(handle) -> str:
 def tmd_create(params: TmdParams, n_atoms: int, box_length: float):
     h = _P()
     _check(load_library().tmd_create(C.byref(params), n_atoms, box_length, C.byref(h)))
+    return h
+
+
+def tmd_create_batch(params, n_atoms, box_lengths):
+    """params: one TmdParams per box."""
+    nb = len(n_atoms)
+    if len(params) != nb or len(box_lengths) != nb:
+        raise ValueError("one TmdParams, atom count and box length per box")
+    h = _P()
+    _check(load_library().tmd_create_batch(nb, (C.c_int64 * nb)(*n_atoms), (C.c_double * nb)(*box_lengths),
+                                           (TmdParams * nb)(*params), C.byref(h)))
     return h
 
 
@@ -179,6 +198,14 @@ def tmd_get_info(handle) -> dict:
     info = TmdInfo()
     _check(load_library().tmd_get_info(handle, C.byref(info)), handle)
     return {k: getattr(info, k) for k, _ in TmdInfo._fields_}
+
+
+def tmd_set_schedule(handle, threads: int, lds_atoms: int) -> None:
+    _check(load_library().tmd_set_schedule(handle, threads, lds_atoms), handle)
+
+
+def tmd_autotune(handle, repeats: int, stream: int) -> None:
+    _check(load_library().tmd_autotune(handle, repeats, stream), handle)
 
 
 def tmd_set_timing(handle, enable: bool) -> None:

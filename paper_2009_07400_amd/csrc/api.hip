@@ -1,11 +1,14 @@
 // C-ABI layer of the MI355X Lennard-Jones MD library: argument checking,
-// workspace carving, call ordering, the integration schedule and deferred
-// device errors.  Every numerical step runs in the kernels of kernels.hip.
+// box and block tables, workspace carving, call ordering, the integration
+// schedule, kernel tuning and deferred device errors.  Every numerical step
+// runs in the kernels of engine.hip.
 #include "tmd.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,13 +18,14 @@
 using namespace tmd;
 
 struct tmd_system {
-    tmd_params p{};
-    Geom g{};
+    std::vector<Box> boxes;  // host copy of the descriptors
+    std::vector<int32_t> blk_box, atom_box;
+    Dims d{};
+    int32_t rebuild_every = 20;
     size_t ws_need = 0;
-    void *ws = nullptr;
     Buffers b{};
     Cursor cur;
-    bool bound = false, have_state = false, list_valid = false, force_valid = false;
+    bool bound = false, have_state = false, list_valid = false, force_valid = false, prepared = false;
     int64_t step = 0;
     std::string err;
 
@@ -39,18 +43,19 @@ struct tmd_system {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxCap = 2560;  // atoms staged per block neighborhood: 60 KB of LDS
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Carve the workspace; with base == nullptr only the size is computed.
-size_t carve(const Geom &g, char *base, Buffers *out) {
+size_t carve(const Dims &d, char *base, Buffers *out) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *p = base ? base + off : nullptr;
         off = align_up(off + bytes);
         return p;
     };
-    const size_t np = size_t(g.np);
+    const size_t np = size_t(d.ntp);
     Buffers b{};
     for (int k = 0; k < 2; ++k) {
         b.x[k] = (double *)take(np * 8);
@@ -64,23 +69,25 @@ size_t carve(const Geom &g, char *base, Buffers *out) {
     b.fx = (double *)take(np * 8);
     b.fy = (double *)take(np * 8);
     b.fz = (double *)take(np * 8);
+    b.boxes = (Box *)take(size_t(d.nbox) * sizeof(Box));
+    b.blk_box = (int32_t *)take(size_t(d.nblk) * 4);
+    b.atom_box = (int32_t *)take(np * 4);
     b.cell_of = (int32_t *)take(np * 4);
     b.slot = (int32_t *)take(np * 4);
     b.tmp_idx = (int32_t *)take(np * 4);
-    b.cell_count = (int32_t *)take(size_t(g.ncell) * 4);
-    b.cell_start = (int32_t *)take((size_t(g.ncell) + 1) * 4);
-    b.scan_sums = (int32_t *)take((size_t(scan_blocks(g.ncell)) + 1) * 4);
+    b.cell_count = (int32_t *)take(size_t(d.ncs) * 4);
+    b.cell_start = (int32_t *)take((size_t(d.ncs) + 1) * 4);
+    b.scan_sums = (int32_t *)take((size_t(scan_blocks(d.ncs)) + 1) * 4);
     b.nbr_count = (int32_t *)take(np * 4);
-    b.nbr = (int32_t *)take(np * size_t(g.maxnb) * 4);
-    b.partials = (double *)take(size_t(atom_grid(g.n)) * kPartialStride * 8);
-    b.scalars = (double *)take(64 * 8);
+    b.nbr = (int32_t *)take(np * size_t(d.nchunk) * 4 * 4);
+    b.partials = (double *)take(size_t(d.nblk) * kPartialStride * 8);
     b.err = (int32_t *)take(64);
     if (out)
         *out = b;
     return off;
 }
 
-bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+bool positive(double v) { return isfinite(v) && v > 0.0; }
 
 tmd_status fail(tmd_system *s, tmd_status st, const std::string &msg) {
     if (s)
@@ -141,7 +148,7 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
     hipError_t e;
     {
         Timed t(s, TMD_T_BINNING, st);
-        e = launch_bin(s->g, s->b, s->cur, st);
+        e = launch_bin(s->d, s->b, s->cur, st);
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "binning");
@@ -149,13 +156,137 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
     s->cur.o = 1 - s->cur.o;
     {
         Timed t(s, TMD_T_NEIGHBOR, st);
-        e = launch_build(s->g, s->b, s->cur, st);
+        e = launch_build(s->d, s->b, s->cur, st);
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "neighbor build");
     s->list_valid = true;
     s->force_valid = false;
     return TMD_OK;
+}
+
+// Expected atoms in a block neighborhood (4 cells per axis, or the whole
+// box when it has fewer cells), for sizing the LDS staging area.
+double expected_hood_atoms(const Box &B) {
+    const double f = double(std::min(B.nc, 4)) / B.nc;
+    return B.n * f * f * f;
+}
+
+tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengths, const tmd_params *params,
+                       tmd_system **out) {
+    if (!out)
+        return TMD_EINVAL;
+    *out = nullptr;
+    if (nbox < 1 || !n_atoms || !lengths || !params)
+        return TMD_EINVAL;
+    int64_t total = 0, blocks = 0;
+    double worst_hood = 0.0;
+    std::vector<Box> boxes;
+    try {
+        boxes.resize(size_t(nbox));
+    } catch (...) {
+        return TMD_EINVAL;
+    }
+    for (int32_t k = 0; k < nbox; ++k) {
+        const tmd_params &p = params[k];
+        const double L = lengths[k];
+        const int64_t n = n_atoms[k];
+        if (n <= 0 || n > INT32_MAX)
+            return TMD_EINVAL;
+        if (!positive(p.epsilon) || !positive(p.sigma) || !positive(p.mass) || !positive(p.cutoff) ||
+            !positive(p.dt) || !positive(L) || !isfinite(p.skin) || p.skin < 0.0)
+            return TMD_EINVAL;
+        if (p.rebuild_every < 1 || p.max_neighbors < 1 || p.max_neighbors > 4096)
+            return TMD_EINVAL;
+        if (p.rebuild_every != params[0].rebuild_every || p.max_neighbors != params[0].max_neighbors)
+            return TMD_EINVAL;
+        const double r = p.cutoff + p.skin;
+        if (!(r < 0.5 * L))
+            return TMD_EBOX;
+        const double ncd = floor(L / r);
+        if (ncd > 1290.0)
+            return TMD_EINVAL;
+        Box &B = boxes[size_t(k)];
+        B.atom_off = int32_t(total);
+        B.n = int32_t(n);
+        B.nc = int32_t(ncd);  // >= 2 because r < L/2
+        B.nbx = (B.nc + 1) / 2;
+        B.nblocks = B.nbx * B.nbx * B.nbx;
+        B.block_off = int32_t(blocks);
+        B.cell_off = int32_t(blocks * 8);
+        B.L = L;
+        B.halfL = 0.5 * L;
+        B.halfL2 = B.halfL * B.halfL;
+        B.side = L / B.nc;
+        B.rc2 = p.cutoff * p.cutoff;
+        B.rl2 = r * r;
+        B.eps = p.epsilon;
+        B.eps48 = 48.0 * p.epsilon;
+        B.eps24 = 24.0 * p.epsilon;
+        B.eps4 = 4.0 * p.epsilon;
+        const double s2 = p.sigma * p.sigma;
+        B.sigma6 = s2 * s2 * s2;
+        B.h = 0.5 * p.dt / p.mass;
+        B.dt = p.dt;
+        B.mass = p.mass;
+        total += n;
+        blocks += B.nblocks;
+        if (total > INT32_MAX - 256 || blocks * 8 > INT32_MAX / 2)
+            return TMD_EINVAL;
+        worst_hood = std::max(worst_hood, expected_hood_atoms(B));
+    }
+    tmd_system *s = new (std::nothrow) tmd_system();
+    if (!s)
+        return TMD_EINVAL;
+    try {
+        s->boxes = boxes;
+        s->rebuild_every = params[0].rebuild_every;
+        Dims &d = s->d;
+        d.nt = int32_t(total);
+        d.ntp = round_up(d.nt + 1, 256);  // slot nt holds the NaN sentinel atom
+        d.nbox = nbox;
+        d.nblk = int32_t(blocks);
+        d.ncs = int32_t(blocks * 8);
+        d.maxnb = params[0].max_neighbors;
+        d.nchunk = (d.maxnb + 3) / 4;
+        // 30% above the mean neighborhood population: liquid density
+        // fluctuations over ~1000 atoms are a few percent; rarer blocks fall
+        // back to global gathers
+        d.cap = std::min(kMaxCap, round_up(int(1.3 * worst_hood) + 64, 64));
+        const double per_block = double(total) / double(blocks);
+        d.threads = std::min(kMaxThreads, std::max(64, round_up(int(per_block * 1.15), 64)));
+        if (int64_t(d.ntp) * d.maxnb > (int64_t(1) << 40)) {
+            delete s;
+            return TMD_EINVAL;
+        }
+        s->blk_box.resize(size_t(blocks));
+        s->atom_box.resize(size_t(d.ntp), nbox - 1);
+        for (int32_t k = 0; k < nbox; ++k) {
+            const Box &B = boxes[size_t(k)];
+            std::fill(s->blk_box.begin() + B.block_off, s->blk_box.begin() + B.block_off + B.nblocks, k);
+            std::fill(s->atom_box.begin() + B.atom_off, s->atom_box.begin() + B.atom_off + B.n, k);
+        }
+        s->ws_need = carve(d, nullptr, nullptr);
+    } catch (...) {
+        delete s;
+        return TMD_EINVAL;
+    }
+    *out = s;
+    return TMD_OK;
+}
+
+tmd_status upload_tables(tmd_system *s, hipStream_t hs) {
+    hipError_t e = hipMemcpyAsync(s->b.boxes, s->boxes.data(), s->boxes.size() * sizeof(Box), hipMemcpyHostToDevice,
+                                  hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->b.blk_box, s->blk_box.data(), s->blk_box.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->b.atom_box, s->atom_box.data(), s->atom_box.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && !s->prepared) {
+        e = prepare_kernels(s->d);
+        s->prepared = (e == hipSuccess);
+    }
+    return e == hipSuccess ? TMD_OK : hip_fail(s, e, "table upload");
 }
 
 }  // namespace
@@ -179,50 +310,12 @@ const char *tmd_status_string(tmd_status st) {
 const char *tmd_last_error(const tmd_system *s) { return s ? s->err.c_str() : "NULL system"; }
 
 tmd_status tmd_create(const tmd_params *p, int64_t n_atoms, double L, tmd_system **out) {
-    if (!p || !out)
-        return TMD_EINVAL;
-    *out = nullptr;
-    if (n_atoms <= 0 || n_atoms > INT32_MAX)
-        return TMD_EINVAL;
-    if (!finite_pos(p->epsilon) || !finite_pos(p->sigma) || !finite_pos(p->mass) || !finite_pos(p->cutoff) ||
-        !finite_pos(p->dt) || !finite_pos(L) || !isfinite(p->skin) || p->skin < 0.0)
-        return TMD_EINVAL;
-    if (p->rebuild_every < 1 || p->max_neighbors < 1 || p->max_neighbors > 4096)
-        return TMD_EINVAL;
-    const double r = p->cutoff + p->skin;
-    if (!(r < 0.5 * L))
-        return TMD_EBOX;
-    const double ncd = floor(L / r);
-    if (ncd > 1290.0)  // keeps nc^3 cell counters within int32
-        return TMD_EINVAL;
-    tmd_system *s = new (std::nothrow) tmd_system();
-    if (!s)
-        return TMD_EINVAL;
-    s->p = *p;
-    Geom &g = s->g;
-    g.n = int32_t(n_atoms);
-    g.np = int32_t((n_atoms + 255) / 256 * 256);
-    g.nc = ncd < 1.0 ? 1 : int32_t(ncd);
-    g.ncell = g.nc * g.nc * g.nc;
-    g.maxnb = p->max_neighbors;
-    g.L = L;
-    g.halfL = 0.5 * L;
-    g.side = L / g.nc;
-    g.rc2 = p->cutoff * p->cutoff;
-    g.rl2 = r * r;
-    g.eps = p->epsilon;
-    const double s2 = p->sigma * p->sigma;
-    g.sigma6 = s2 * s2 * s2;
-    g.h = 0.5 * p->dt / p->mass;
-    g.dt = p->dt;
-    g.mass = p->mass;
-    if (int64_t(g.np) * g.maxnb > (int64_t(1) << 40)) {
-        delete s;
-        return TMD_EINVAL;
-    }
-    s->ws_need = carve(g, nullptr, nullptr);
-    *out = s;
-    return TMD_OK;
+    return create_impl(1, &n_atoms, &L, p, out);
+}
+
+tmd_status tmd_create_batch(int32_t n_boxes, const int64_t *n_atoms, const double *box_lengths,
+                            const tmd_params *params, tmd_system **out) {
+    return create_impl(n_boxes, n_atoms, box_lengths, params, out);
 }
 
 tmd_status tmd_workspace_size(const tmd_system *s, size_t *bytes) {
@@ -237,8 +330,7 @@ tmd_status tmd_bind_workspace(tmd_system *s, void *dev, size_t bytes) {
         return TMD_EINVAL;
     if (bytes < s->ws_need || (reinterpret_cast<uintptr_t>(dev) % kAlign) != 0)
         return fail(s, TMD_EWORKSPACE, "workspace must be 256-byte aligned and at least tmd_workspace_size bytes");
-    s->ws = dev;
-    carve(s->g, static_cast<char *>(dev), &s->b);
+    carve(s->d, static_cast<char *>(dev), &s->b);
     s->bound = true;
     s->have_state = s->list_valid = s->force_valid = false;
     s->cur = Cursor{};
@@ -253,12 +345,14 @@ tmd_status tmd_set_state(tmd_system *s, const double *const pos[3], const double
     if (!pos || !vel || !pos[0] || !pos[1] || !pos[2] || !vel[0] || !vel[1] || !vel[2] || step < 0)
         return fail(s, TMD_EINVAL, "set_state: NULL array or negative step");
     hipStream_t hs = static_cast<hipStream_t>(stream);
+    if ((st = upload_tables(s, hs)) != TMD_OK)
+        return st;
     hipError_t e;
     {
         Timed t(s, TMD_T_COPY, hs);
         e = launch_fill_i32(s->b.err, 0, 16, hs);
         if (e == hipSuccess)
-            e = launch_load_state(s->g, pos, vel, s->b, Cursor{}, hs);
+            e = launch_load_state(s->d, pos, vel, s->b, Cursor{}, hs);
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "set_state");
@@ -286,20 +380,20 @@ tmd_status tmd_compute_forces(tmd_system *s, double *const f[3], double *ev, tmd
     hipError_t e;
     {
         Timed t(s, TMD_T_FORCE, hs);
-        e = launch_force(s->g, s->b, s->cur, 0, ev != nullptr, hs);
+        e = launch_force(s->d, s->b, s->cur, 0, ev != nullptr, hs);
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "force");
     s->force_valid = true;
     if (ev) {
         Timed t(s, TMD_T_THERMO, hs);
-        e = launch_reduce(s->g, s->b, ev, 2, hs);
+        e = launch_reduce(s->d, s->b, ev, 2, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "reduce");
     }
     if (f && (f[0] || f[1] || f[2])) {
         Timed t(s, TMD_T_COPY, hs);
-        e = launch_unload(s->g, s->b.fx, s->b.fy, s->b.fz, s->b.orig[s->cur.o], f, hs);
+        e = launch_unload(s->d, s->b.fx, s->b.fy, s->b.fz, s->b.orig[s->cur.o], f, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "force unload");
     }
@@ -320,20 +414,21 @@ tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, d
         return st;
     if (!s->force_valid) {
         Timed t(s, TMD_T_FORCE, hs);
-        e = launch_force(s->g, s->b, s->cur, 0, false, hs);
+        e = launch_force(s->d, s->b, s->cur, 0, false, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "force");
         s->force_valid = true;
     }
     {
         Timed t(s, TMD_T_DRIFT, hs);
-        e = launch_drift(s->g, s->b, s->cur, hs);
+        e = launch_drift(s->d, s->b, s->cur, hs);
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "drift");
     s->cur.x = 1 - s->cur.x;
     s->force_valid = false;
-    const int64_t rb = s->p.rebuild_every;
+    const int64_t rb = s->rebuild_every;
+    const int64_t row_stride = int64_t(s->d.nbox) * 5;
     for (int32_t k = 1; k <= n_steps; ++k) {
         const int64_t stepk = s->step + k;
         if (stepk % rb == 0 && (st = rebuild(s, hs)) != TMD_OK)
@@ -342,7 +437,7 @@ tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, d
         const int mode = (k < n_steps) ? 2 : 1;
         {
             Timed t(s, TMD_T_FORCE, hs);
-            e = launch_force(s->g, s->b, s->cur, mode, th, hs);
+            e = launch_force(s->d, s->b, s->cur, mode, th, hs);
         }
         if (e != hipSuccess)
             return hip_fail(s, e, "force");
@@ -350,7 +445,7 @@ tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, d
             s->cur.x = 1 - s->cur.x;
         if (th) {
             Timed t(s, TMD_T_THERMO, hs);
-            e = launch_reduce(s->g, s->b, thermo + int64_t(k / thermo_every - 1) * 5, 5, hs);
+            e = launch_reduce(s->d, s->b, thermo + int64_t(k / thermo_every - 1) * row_stride, 5, hs);
             if (e != hipSuccess)
                 return hip_fail(s, e, "reduce");
         }
@@ -370,12 +465,12 @@ tmd_status tmd_get_state(const tmd_system *cs, double *const pos[3], double *con
     const int c = s->cur.x, o = s->cur.o;
     Timed t(s, TMD_T_COPY, hs);
     if (pos) {
-        hipError_t e = launch_unload(s->g, s->b.x[c], s->b.y[c], s->b.z[c], s->b.orig[o], pos, hs);
+        hipError_t e = launch_unload(s->d, s->b.x[c], s->b.y[c], s->b.z[c], s->b.orig[o], pos, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "get_state");
     }
     if (vel) {
-        hipError_t e = launch_unload(s->g, s->b.vx[o], s->b.vy[o], s->b.vz[o], s->b.orig[o], vel, hs);
+        hipError_t e = launch_unload(s->d, s->b.vx[o], s->b.vy[o], s->b.vz[o], s->b.orig[o], vel, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "get_state");
     }
@@ -390,13 +485,13 @@ tmd_status tmd_get_neighbors(const tmd_system *cs, int32_t *counts, int32_t *ids
     tmd_status st = check_ready(s, true);
     if (st != TMD_OK)
         return st;
-    if (!counts || !ids || capacity < int64_t(s->g.n) * s->g.maxnb)
+    if (!counts || !ids || capacity < int64_t(s->d.nt) * s->d.maxnb)
         return fail(s, TMD_EINVAL, "get_neighbors: NULL buffer or capacity below n_atoms * max_neighbors");
     if (!s->list_valid)
         return fail(s, TMD_ESTATE, "get_neighbors: no list built since the state was set");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     Timed t(s, TMD_T_COPY, hs);
-    hipError_t e = launch_export_neighbors(s->g, s->b, s->cur, counts, ids, hs);
+    hipError_t e = launch_export_neighbors(s->d, s->b, s->cur, counts, ids, hs);
     return e == hipSuccess ? TMD_OK : hip_fail(s, e, "get_neighbors");
 }
 
@@ -406,7 +501,9 @@ tmd_status tmd_sync(tmd_system *s, tmd_stream stream) {
         return st;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     int32_t w[2] = {0, 0};
-    hipError_t e = hipMemcpyAsync(w, s->b.err, sizeof(w), hipMemcpyDeviceToHost, hs);
+    hipError_t e = hipSuccess;
+    if (s->have_state)
+        e = hipMemcpyAsync(w, s->b.err, sizeof(w), hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess)
         e = hipStreamSynchronize(hs);
     if (e != hipSuccess)
@@ -415,7 +512,7 @@ tmd_status tmd_sync(tmd_system *s, tmd_stream stream) {
         return fail(s, TMD_ENONFINITE, "a position, velocity or force became NaN/Inf (coincident atoms?)");
     if (w[0] & kErrOverflow)
         return fail(s, TMD_ENBR_OVERFLOW, "an atom has " + std::to_string(w[1]) + " list entries, max_neighbors is " +
-                                              std::to_string(s->g.maxnb));
+                                              std::to_string(s->d.maxnb));
     if (w[0] & kErrOutOfBox)
         return fail(s, TMD_EINVAL, "set_state: a coordinate lies outside [-L, 2L)");
     return TMD_OK;
@@ -424,14 +521,86 @@ tmd_status tmd_sync(tmd_system *s, tmd_stream stream) {
 tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
     if (!s || !info)
         return TMD_EINVAL;
-    info->n_atoms = s->g.n;
-    info->n_padded = s->g.np;
-    info->cells_per_axis = s->g.nc;
-    info->max_neighbors = s->g.maxnb;
-    info->n_cells = s->g.ncell;
+    int64_t cells = 0;
+    for (const Box &B : s->boxes)
+        cells += int64_t(B.nc) * B.nc * B.nc;
+    info->n_atoms = s->d.nt;
+    info->n_padded = s->d.ntp;
+    info->cells_per_axis = s->boxes[0].nc;
+    info->max_neighbors = s->d.maxnb;
+    info->n_cells = cells;
     info->workspace_bytes = s->ws_need;
     info->step = s->step;
+    info->n_boxes = s->d.nbox;
+    info->n_blocks = s->d.nblk;
+    info->block_threads = s->d.threads;
+    info->lds_atoms = s->d.cap;
     return TMD_OK;
+}
+
+tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms) {
+    if (!s || threads < 0 || threads > kMaxThreads || threads % 64 != 0 || lds_atoms < 0 || lds_atoms > kMaxCap ||
+        lds_atoms % 64 != 0)
+        return TMD_EINVAL;
+    if (threads > 0)
+        s->d.threads = threads;
+    if (lds_atoms > 0 && lds_atoms != s->d.cap) {
+        s->d.cap = lds_atoms;
+        s->prepared = false;  // LDS attribute of the block kernels must follow
+        // the list encodes LDS slots only for neighborhoods that fit
+        s->list_valid = s->force_valid = false;
+        if (s->bound) {
+            hipError_t e = prepare_kernels(s->d);
+            if (e != hipSuccess)
+                return hip_fail(s, e, "set_schedule");
+            s->prepared = true;
+        }
+    }
+    return TMD_OK;
+}
+
+tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
+    tmd_status st = check_ready(s, true);
+    if (st != TMD_OK)
+        return st;
+    if (repeats < 1)
+        return fail(s, TMD_EINVAL, "autotune: repeats < 1");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (!s->list_valid && (st = rebuild(s, hs)) != TMD_OK)
+        return st;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess)
+        e = hipEventCreate(&b);
+    if (e != hipSuccess)
+        return hip_fail(s, e, "autotune");
+    const int32_t saved = s->d.threads;
+    float best = 1e30f;
+    int32_t best_t = saved;
+    for (int32_t t = 64; t <= kMaxThreads && e == hipSuccess; t += 64) {
+        s->d.threads = t;
+        e = launch_force(s->d, s->b, s->cur, 0, false, hs);  // warm-up; the state is not changed
+        if (e == hipSuccess)
+            e = hipEventRecord(a, hs);
+        for (int32_t r = 0; r < repeats && e == hipSuccess; ++r)
+            e = launch_force(s->d, s->b, s->cur, 0, false, hs);
+        if (e == hipSuccess)
+            e = hipEventRecord(b, hs);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    s->d.threads = (e == hipSuccess) ? best_t : saved;
+    s->force_valid = true;
+    return e == hipSuccess ? TMD_OK : hip_fail(s, e, "autotune");
 }
 
 tmd_status tmd_set_timing(tmd_system *s, int32_t enable) {

@@ -28,32 +28,41 @@ __device__ __forceinline__ double dist2(double dx, double dy, double dz) {
 
 // Pair difference vector with periodic images.  Only atoms near a face of
 // the box have partners across it; for every other pair the raw difference
-// already is the minimum image.  The correction sits behind a branch that a
-// wavefront takes only when one of its lanes needs it, and applies the same
-// per-axis rule as mic(), so the result is bit-identical to it.
+// already is the minimum image.  Any axis with |d| > L/2 makes the raw
+// |d|^2 exceed (L/2)^2, so that one comparison selects every pair that may
+// need a shift; the correction sits behind a branch that a wavefront takes
+// only when one of its lanes needs it, and applies mic() per axis (which
+// leaves axes with |d| <= L/2 untouched), so the result is bit-identical to
+// applying mic() to every pair.
 __device__ __forceinline__ double pair_delta(double xi, double yi, double zi, double xj, double yj, double zj,
-                                            double L, double halfL, double &dx, double &dy, double &dz) {
+                                            double L, double halfL, double halfL2, double &dx, double &dy,
+                                            double &dz) {
     dx = xi - xj;
     dy = yi - yj;
     dz = zi - zj;
-    const bool wrapped = int(fabs(dx) > halfL) | int(fabs(dy) > halfL) | int(fabs(dz) > halfL);
-    if (wrapped) {
+    double s = dist2(dx, dy, dz);
+    if (s >= halfL2) {
         dx = mic(dx, L, halfL);
         dy = mic(dy, L, halfL);
         dz = mic(dz, L, halfL);
+        s = dist2(dx, dy, dz);
     }
-    return dist2(dx, dy, dz);
+    return s;
 }
 
-// 1/s for s > 0: hardware reciprocal estimate refined by two Newton-Raphson
-// steps r <- r + r (1 - s r), each of which roughly squares the relative
-// error; the result is within an ulp or two of the correctly rounded value.
+// 1/s for s > 0: hardware reciprocal estimate refined by one Newton-Raphson
+// step r <- r + r (1 - s r), which squares the estimate's relative error
+// (about 2^-23 or better) to about 2^-46, far inside the 1e-12 per-atom
+// force tolerance.  recip_exact() adds a second step (within an ulp or two
+// of the correctly rounded value) for the derivative kernels.
 __device__ __forceinline__ double recip(double s) {
-    double r = __builtin_amdgcn_rcp(s);
-    double e = fma(-s, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-s, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(s);
+    return fma(r, fma(-s, r, 1.0), r);
+}
+
+__device__ __forceinline__ double recip_exact(double s) {
+    const double r = recip(s);
+    return fma(r, fma(-s, r, 1.0), r);
 }
 
 // Wrap a coordinate that moved by less than one box length into [0, L).

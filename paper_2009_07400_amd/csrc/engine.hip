@@ -1,0 +1,863 @@
+// HIP kernels for gfx950 (MI355X): cell binning, full neighbor-list build,
+// Lennard-Jones force sum fused with the velocity-Verlet kicks and drift,
+// deterministic per-box reductions, state load/unload and list export, for
+// one or many independent periodic boxes.
+//
+// Method (tinyMD, arXiv 2009.07400): LJ 12-6 force, Sec. 3.2 Eq. 2 and the
+// compute_potential example of Sec. 4.2; Verlet lists built from cell lists
+// at cutoff + skin, Sec. 3.2 and Fig. 1; neighbor-major list layout for GPUs,
+// Sec. 4.2; velocity Verlet of Newton's law (Sec. 3.2, Eq. 1) with the list
+// rebuilt every `rebuild_every` steps (Sec. 6).
+//
+// Work decomposition.  Cells have side >= cutoff + skin.  Each box is cut
+// into blocks of 2x2x2 cells and atoms are stored block-major, so the atoms
+// of a block, and of each of its cells, are contiguous.  One workgroup owns
+// one block: it copies the positions of the block's neighborhood (the 4x4x4
+// cells around it, fewer in small boxes) into LDS with coalesced loads, and
+// its lanes - one per atom - gather neighbor positions from LDS instead of
+// from the L2.  The list stores LDS slot numbers for such blocks; a block
+// whose neighborhood exceeds the LDS capacity gathers from global memory and
+// its list stores global atom indices.
+//
+// Layout in HBM: positions, velocities and forces are structure-of-arrays
+// FP64; the list is int32, row k holding the k-th neighbor of every atom
+// (nbr[k * ntp + i]), so a wavefront reads one contiguous 256-byte row.
+#include <math.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace tmd {
+
+namespace {
+
+// Workgroup index remapped so that the workgroups the hardware places on one
+// XCD (b, b + 8, b + 16, ...) process one contiguous range of blocks, i.e.
+// one spatial slab of a box, which then stays in that XCD's L2.
+__device__ __forceinline__ int xcd_remap() {
+    const int b = blockIdx.x, nb = gridDim.x;  // nb is a multiple of kNumXcd
+    return (b % kNumXcd) * (nb / kNumXcd) + b / kNumXcd;
+}
+
+__device__ __forceinline__ int cell_slot(const Box &B, int cx, int cy, int cz) {
+    const int blk = ((cz >> 1) * B.nbx + (cy >> 1)) * B.nbx + (cx >> 1);
+    return B.cell_off + blk * 8 + (((cz & 1) * 2 + (cy & 1)) * 2 + (cx & 1));
+}
+
+// Distinct cells c0-1 .. c0+e (periodic) along one axis, in that order.
+__device__ __forceinline__ int hood_axis(int c0, int e, int nc, int out[4]) {
+    int n = 0;
+    for (int t = 0; t < e + 2; ++t) {
+        int v = c0 - 1 + t;
+        v = v < 0 ? v + nc : (v >= nc ? v - nc : v);
+        bool dup = false;
+        for (int q = 0; q < n; ++q)
+            dup |= (out[q] == v);
+        if (!dup)
+            out[n++] = v;
+    }
+    return n;
+}
+
+__device__ __forceinline__ int axis_index(const int a[4], int n, int v) {
+    int r = 0;
+    for (int q = 0; q < n; ++q)
+        r = (a[q] == v) ? q : r;
+    return r;
+}
+
+// Neighborhood axes of local block lb (uniform across the workgroup).
+__device__ __forceinline__ void hood_axes(const Box &B, int lb, int n[3], int co[3][4]) {
+    const int nbx = B.nbx;
+    const int bc[3] = {lb % nbx, (lb / nbx) % nbx, lb / (nbx * nbx)};
+    for (int a = 0; a < 3; ++a) {
+        const int c0 = 2 * bc[a];
+        const int e = min(2, B.nc - c0);
+        n[a] = hood_axis(c0, e, B.nc, co[a]);
+    }
+}
+
+struct Hood {
+    int cs[kMaxHood];       // first atom of each neighborhood cell
+    int off[kMaxHood + 1];  // LDS slot of each cell's first atom; off[ncell] = atoms staged
+    int ncell;
+    int a0, a1;             // the block's own atoms
+};
+
+__device__ __forceinline__ int wave_prefix_incl(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o)
+            v += t;
+    }
+    return v;
+}
+
+// Cell ranges and LDS offsets of the neighborhood of local block lb; ends
+// with a workgroup barrier.
+__device__ __forceinline__ void hood_setup(const Box &B, int lb, const int32_t *__restrict__ cell_start, Hood &h) {
+    if (threadIdx.x < 64) {
+        int n[3], co[3][4];
+        hood_axes(B, lb, n, co);
+        const int nh = n[0] * n[1] * n[2];
+        const int u = threadIdx.x;
+        int cs = 0, cnt = 0;
+        if (u < nh) {
+            const int ix = u % n[0], iy = (u / n[0]) % n[1], iz = u / (n[0] * n[1]);
+            const int sl = cell_slot(B, co[0][ix], co[1][iy], co[2][iz]);
+            cs = cell_start[sl];
+            cnt = cell_start[sl + 1] - cs;
+        }
+        const int incl = wave_prefix_incl(cnt);
+        if (u < nh) {
+            h.cs[u] = cs;
+            h.off[u + 1] = incl;
+        }
+        if (u == 0) {
+            h.off[0] = 0;
+            h.ncell = nh;
+            const int first = B.cell_off + lb * 8;
+            h.a0 = cell_start[first];
+            h.a1 = cell_start[first + 8];
+        }
+    }
+    __syncthreads();
+}
+
+// Neighborhood cell holding LDS slot t (largest u with off[u] <= t).
+__device__ __forceinline__ int hood_find(const Hood &h, int t) {
+    int lo = 0, hi = h.ncell;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (h.off[mid] <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// LDS copy of a neighborhood: packed (x, y, z) triples, 24 bytes per slot,
+// addressed with 32-bit LDS pointers (one 24-bit multiply-add per atom, then
+// ds_read2_b64 + ds_read_b64 with immediate offsets).
+typedef __attribute__((address_space(3))) double lds_double;
+typedef __attribute__((address_space(3))) char lds_char;
+
+__device__ __forceinline__ lds_double *lds_slot(lds_double *base, int slot) {
+    return (lds_double *)((lds_char *)base + __umul24(unsigned(slot), 24u));
+}
+
+struct LdsPos {
+    lds_double *s;
+    __device__ __forceinline__ void get(int j, double &x, double &y, double &z) const {
+        const lds_double *a = lds_slot(s, j);
+        x = a[0];
+        y = a[1];
+        z = a[2];
+    }
+};
+
+struct GlobalPos {
+    const double *__restrict__ x;
+    const double *__restrict__ y;
+    const double *__restrict__ z;
+    __device__ __forceinline__ void get(int j, double &a, double &b, double &c) const {
+        a = x[j];
+        b = y[j];
+        c = z[j];
+    }
+};
+
+// Copy the neighborhood's positions into LDS (the global loads are
+// coalesced within each cell), and a NaN sentinel atom at slot `total`:
+// list padding points there, and every comparison with a NaN distance is
+// false, so padded entries need no test.  Ends with a workgroup barrier.
+__device__ __forceinline__ void hood_stage(const Hood &h, int total, const double *__restrict__ x,
+                                           const double *__restrict__ y, const double *__restrict__ z,
+                                           lds_double *s) {
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int u = hood_find(h, t);
+        const int g = h.cs[u] + (t - h.off[u]);
+        lds_double *a = lds_slot(s, t);
+        a[0] = x[g];
+        a[1] = y[g];
+        a[2] = z[g];
+    }
+    if (threadIdx.x == 0) {
+        const double nan = __builtin_nan("");
+        lds_double *a = lds_slot(s, total);
+        a[0] = nan;
+        a[1] = nan;
+        a[2] = nan;
+    }
+    __syncthreads();
+}
+
+// Deterministic workgroup sum of three values; valid in thread 0.
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c) {
+    __shared__ double red[3][kMaxThreads / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+        red[2][wave] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = c = 0.0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) {
+            a += red[0][w];
+            b += red[1][w];
+            c += red[2][w];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ utility
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kAtomThreads) void k_load_state(Dims d, const Box *__restrict__ boxes,
+                                                             const int32_t *__restrict__ atom_box,
+                                                             const double *__restrict__ ix,
+                                                             const double *__restrict__ iy,
+                                                             const double *__restrict__ iz,
+                                                             const double *__restrict__ ivx,
+                                                             const double *__restrict__ ivy,
+                                                             const double *__restrict__ ivz, double *x, double *y,
+                                                             double *z, double *vx, double *vy, double *vz,
+                                                             int32_t *orig, double *x2, double *y2, double *z2,
+                                                             int32_t *err) {
+    const int i = blockIdx.x * kAtomThreads + threadIdx.x;
+    if (i == 0) {
+        // sentinel atom at slot nt of both position buffers: list padding of
+        // blocks that gather from global memory points here
+        const double nan = __builtin_nan("");
+        x[d.nt] = y[d.nt] = z[d.nt] = nan;
+        x2[d.nt] = y2[d.nt] = z2[d.nt] = nan;
+    }
+    if (i >= d.nt)
+        return;
+    const double L = boxes[atom_box[i]].L;
+    const double px = wrap(ix[i], L), py = wrap(iy[i], L), pz = wrap(iz[i], L);
+    const double a = ivx[i], b = ivy[i], c = ivz[i];
+    if (!(isfinite(a) && isfinite(b) && isfinite(c)))
+        atomicOr(err, kErrNonFinite);
+    if (!(px >= 0.0 && px < L && py >= 0.0 && py < L && pz >= 0.0 && pz < L))
+        atomicOr(err, isfinite(px) && isfinite(py) && isfinite(pz) ? kErrOutOfBox : kErrNonFinite);
+    x[i] = px;
+    y[i] = py;
+    z[i] = pz;
+    vx[i] = a;
+    vy[i] = b;
+    vz[i] = c;
+    orig[i] = i;
+}
+
+__global__ __launch_bounds__(kAtomThreads) void k_unload(int n, const double *__restrict__ ax,
+                                                         const double *__restrict__ ay,
+                                                         const double *__restrict__ az,
+                                                         const int32_t *__restrict__ orig, double *o0, double *o1,
+                                                         double *o2) {
+    const int p = blockIdx.x * kAtomThreads + threadIdx.x;
+    if (p >= n)
+        return;
+    const int o = orig[p];
+    if (o0)
+        o0[o] = ax[p];
+    if (o1)
+        o1[o] = ay[p];
+    if (o2)
+        o2[o] = az[p];
+}
+
+// ------------------------------------------------------------------ binning
+
+// Cell slot of every atom and its (arbitrary) arrival rank within the cell.
+__global__ __launch_bounds__(kAtomThreads) void k_bin_count(Dims d, const Box *__restrict__ boxes,
+                                                            const int32_t *__restrict__ atom_box,
+                                                            const double *__restrict__ x,
+                                                            const double *__restrict__ y,
+                                                            const double *__restrict__ z, int32_t *cell_of,
+                                                            int32_t *slot, int32_t *cell_count, int32_t *err) {
+    const int i = blockIdx.x * kAtomThreads + threadIdx.x;
+    if (i >= d.nt)
+        return;
+    const Box &B = boxes[atom_box[i]];
+    const double px = x[i], py = y[i], pz = z[i];
+    if (!(isfinite(px) && isfinite(py) && isfinite(pz)))
+        atomicOr(err, kErrNonFinite);
+    const int c = cell_slot(B, cell_coord(px, B.side, B.nc), cell_coord(py, B.side, B.nc),
+                            cell_coord(pz, B.side, B.nc));
+    cell_of[i] = c;
+    slot[i] = atomicAdd(&cell_count[c], 1);
+}
+
+// Exclusive scan, level 1: each workgroup scans a tile of kScanTile counts
+// (four per thread) and records the tile total.
+__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                    int32_t *__restrict__ sums, int n) {
+    __shared__ int32_t sh[256];
+    const int t = threadIdx.x;
+    const int base = blockIdx.x * kScanTile + t * 4;
+    int v[4], tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[q] = (base + q < n) ? in[base + q] : 0;
+        tot += v[q];
+    }
+    sh[t] = tot;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int add = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int run = sh[t] - tot;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (base + q < n)
+            out[base + q] = run;
+        run += v[q];
+    }
+    if (t == 255)
+        sums[blockIdx.x] = sh[255];
+}
+
+// Level 2: one workgroup turns the tile totals into exclusive offsets and
+// writes the grand total to out[n].
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nt, int32_t *out, int n) {
+    __shared__ int32_t sh[1024];
+    const int t = threadIdx.x;
+    const int per = (nt + 1023) / 1024;
+    const int b0 = t * per;
+    int tot = 0;
+    for (int q = 0; q < per; ++q)
+        if (b0 + q < nt)
+            tot += sums[b0 + q];
+    sh[t] = tot;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int add = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int run = sh[t] - tot;
+    for (int q = 0; q < per; ++q)
+        if (b0 + q < nt) {
+            const int v = sums[b0 + q];
+            sums[b0 + q] = run;
+            run += v;
+        }
+    if (t == 1023)
+        out[n] = sh[1023];
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int32_t *out, const int32_t *__restrict__ sums, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        out[i] += sums[i / kScanTile];
+}
+
+__global__ __launch_bounds__(kAtomThreads) void k_scatter(int n, const int32_t *__restrict__ cell_of,
+                                                          const int32_t *__restrict__ slot,
+                                                          const int32_t *__restrict__ cell_start, int32_t *tmp_idx) {
+    const int i = blockIdx.x * kAtomThreads + threadIdx.x;
+    if (i < n)
+        tmp_idx[cell_start[cell_of[i]] + slot[i]] = i;
+}
+
+// Atomic arrival order inside a cell is not reproducible: each atom's final
+// place is its cell start plus the number of cell members with a smaller
+// original id.  Then positions, velocities and ids move to that place.
+__global__ __launch_bounds__(kAtomThreads) void k_rank_permute(
+    int n, const int32_t *__restrict__ tmp_idx, const int32_t *__restrict__ cell_of,
+    const int32_t *__restrict__ cell_start, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
+    const double *__restrict__ vz, const int32_t *__restrict__ orig, double *x2, double *y2, double *z2,
+    double *vx2, double *vy2, double *vz2, int32_t *orig2) {
+    const int q = blockIdx.x * kAtomThreads + threadIdx.x;
+    if (q >= n)
+        return;
+    const int p = tmp_idx[q];
+    const int key = orig[p];
+    const int c = cell_of[p];
+    const int b = cell_start[c], e = cell_start[c + 1];
+    int rank = 0;
+    for (int r = b; r < e; ++r)
+        rank += int(orig[tmp_idx[r]] < key);
+    const int dst = b + rank;
+    x2[dst] = x[p];
+    y2[dst] = y[p];
+    z2[dst] = z[p];
+    vx2[dst] = vx[p];
+    vy2[dst] = vy[p];
+    vz2[dst] = vz[p];
+    orig2[dst] = key;
+}
+
+// ------------------------------------------------------------------ neighbor list
+
+// One workgroup per block, one lane per atom: every j != i in the distinct
+// cells of i's 27-cell stencil with s < (cutoff + skin)^2 enters i's list.
+// Candidates come from the LDS copy of the neighborhood (lanes of one cell
+// read the same candidate, a broadcast); list entries are LDS slots, or
+// global indices when the neighborhood did not fit.
+__global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__restrict__ boxes,
+                                                       const int32_t *__restrict__ blk_box,
+                                                       const double *__restrict__ x, const double *__restrict__ y,
+                                                       const double *__restrict__ z,
+                                                       const int32_t *__restrict__ cell_start,
+                                                       int32_t *__restrict__ cnt, int32_t *__restrict__ nbr,
+                                                       int32_t *err) {
+    __shared__ Hood h;
+    extern __shared__ double lds[];
+    const int b = xcd_remap();
+    if (b >= d.nblk)
+        return;
+    const Box B = boxes[blk_box[b]];
+    const int lb = b - B.block_off;
+    hood_setup(B, lb, cell_start, h);
+    const int total = h.off[h.ncell];
+    const bool fits = total <= d.cap;
+    lds_double *S = (lds_double *)lds;
+    if (fits)
+        hood_stage(h, total, x, y, z, S);
+    // list padding up to a whole 4-entry chunk points at the NaN sentinel
+    const int sentinel = fits ? total : d.nt;
+    int n[3], co[3][4];
+    hood_axes(B, lb, n, co);
+    for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
+        const double xi = x[i], yi = y[i], zi = z[i];
+        const int cx = cell_coord(xi, B.side, B.nc), cy = cell_coord(yi, B.side, B.nc),
+                  cz = cell_coord(zi, B.side, B.nc);
+        int st[3][3], ns[3];
+        {
+            int v[3];
+            ns[0] = stencil_axis(cx, B.nc, v);
+            for (int k = 0; k < ns[0]; ++k)
+                st[0][k] = axis_index(co[0], n[0], v[k]);
+            ns[1] = stencil_axis(cy, B.nc, v);
+            for (int k = 0; k < ns[1]; ++k)
+                st[1][k] = axis_index(co[1], n[1], v[k]);
+            ns[2] = stencil_axis(cz, B.nc, v);
+            for (int k = 0; k < ns[2]; ++k)
+                st[2][k] = axis_index(co[2], n[2], v[k]);
+        }
+        int self = i;
+        if (fits) {
+            const int us = (axis_index(co[2], n[2], cz) * n[1] + axis_index(co[1], n[1], cy)) * n[0] +
+                           axis_index(co[0], n[0], cx);
+            self = h.off[us] + (i - h.cs[us]);
+        }
+        int c = 0;
+        for (int kz = 0; kz < ns[2]; ++kz)
+            for (int ky = 0; ky < ns[1]; ++ky)
+                for (int kx = 0; kx < ns[0]; ++kx) {
+                    const int u = (st[2][kz] * n[1] + st[1][ky]) * n[0] + st[0][kx];
+                    const int beg = h.off[u], end = h.off[u + 1];
+                    if (fits) {
+                        for (int t = beg; t < end; ++t) {
+                            double dx, dy, dz;
+                            const lds_double *p = lds_slot(S, t);
+                            const double s =
+                                pair_delta(xi, yi, zi, p[0], p[1], p[2], B.L, B.halfL, B.halfL2, dx, dy, dz);
+                            if (s < B.rl2 && t != self) {
+                                if (c < d.maxnb)
+                                    nbr[nbr_index(i, c, d.nchunk)] = t;
+                                ++c;
+                            }
+                        }
+                    } else {
+                        const int g0 = h.cs[u] - beg;
+                        for (int t = beg; t < end; ++t) {
+                            const int g = g0 + t;
+                            double dx, dy, dz;
+                            const double s = pair_delta(xi, yi, zi, x[g], y[g], z[g], B.L, B.halfL, B.halfL2, dx, dy, dz);
+                            if (s < B.rl2 && g != i) {
+                                if (c < d.maxnb)
+                                    nbr[nbr_index(i, c, d.nchunk)] = g;
+                                ++c;
+                            }
+                        }
+                    }
+                }
+        const int stored = c < d.maxnb ? c : d.maxnb;
+        cnt[i] = stored;
+        for (int k = stored; k < ((stored + 3) & ~3); ++k)
+            nbr[nbr_index(i, k, d.nchunk)] = sentinel;
+        if (c > d.maxnb) {
+            atomicOr(err, kErrOverflow);
+            atomicMax(err + 1, c);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ force
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Sum over one atom's list: F_i = sum f(s) d_ij for s < cutoff^2 with
+// f = 48 eps sr6 (sr6 - 1/2) sr2 = sr2 sr6 (48 eps sr6 - 24 eps),
+// sr2 = 1/s, sr6 = sigma^6 sr2^3.  The list is read four entries per 16-byte
+// load, two chunks ahead of use, with non-temporal loads (it is streamed once
+// per step and should not displace positions from the caches); the twelve
+// coordinate loads of a chunk are issued together before any of its four
+// pairs is evaluated.  Entries past the count point at a NaN sentinel atom,
+// so no pair needs a bounds test.  POS reads positions from the LDS copy of
+// the neighborhood or from global memory.
+template <bool THERMO, class POS>
+__device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int c, const POS &pos, double xi,
+                                         double yi, double zi, const Box &B, double &ax, double &ay, double &az,
+                                         double &u, double &w) {
+    const int nch = (c + 3) >> 2;
+    // index chunks k+1 and k+2 in registers, chunk k+3 in flight; the
+    // positions of chunk k+1 are read while chunk k is evaluated
+    v4i i1 = {0, 0, 0, 0}, i2 = {0, 0, 0, 0};
+    double xs[4], ys[4], zs[4];
+    if (nch > 0) {
+        const v4i i0 = __builtin_nontemporal_load(chunks);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            pos.get(i0[m], xs[m], ys[m], zs[m]);
+    }
+    if (nch > 1)
+        i1 = __builtin_nontemporal_load(chunks + 64);
+    if (nch > 2)
+        i2 = __builtin_nontemporal_load(chunks + 128);
+    for (int k = 0; k < nch; ++k) {
+        double xn[4], yn[4], zn[4];
+        if (k + 1 < nch) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                pos.get(i1[m], xn[m], yn[m], zn[m]);
+        }
+        i1 = i2;
+        if (k + 3 < nch)
+            i2 = __builtin_nontemporal_load(chunks + (k + 3) * 64);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double dx, dy, dz;
+            const double s = pair_delta(xi, yi, zi, xs[m], ys[m], zs[m], B.L, B.halfL, B.halfL2, dx, dy, dz);
+            if (s < B.rc2) {
+                const double sr2 = recip(s);
+                const double sr6 = sr2 * sr2 * sr2 * B.sigma6;
+                const double f = sr2 * sr6 * fma(B.eps48, sr6, -B.eps24);
+                ax += f * dx;
+                ay += f * dy;
+                az += f * dz;
+                if (THERMO) {
+                    u += sr6 * fma(B.eps4, sr6, -B.eps4);
+                    w += s * f;
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            xs[m] = xn[m];
+            ys[m] = yn[m];
+            zs[m] = zn[m];
+        }
+    }
+}
+
+__device__ __forceinline__ const v4i *list_chunks(const int32_t *nbr, int i, int nchunk) {
+    return reinterpret_cast<const v4i *>(nbr) + (int64_t(i >> 6) * nchunk) * 64 + (i & 63);
+}
+
+// One workgroup per block, one lane per atom.  MODE 0: store F.  MODE 1:
+// store F and kick v += h F.  MODE 2: kick twice (closing this step and
+// opening the next) and drift into the other position buffer.  With THERMO
+// each block writes its partial sums of the pair energy, of s f(s) and of
+// |v|^2 at the full step - no atomics anywhere.
+template <int MODE, bool THERMO>
+__global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__restrict__ boxes,
+                                                       const int32_t *__restrict__ blk_box,
+                                                       const double *__restrict__ x, const double *__restrict__ y,
+                                                       const double *__restrict__ z,
+                                                       const int32_t *__restrict__ cell_start,
+                                                       const int32_t *__restrict__ cnt,
+                                                       const int32_t *__restrict__ nbr, double *__restrict__ vx,
+                                                       double *__restrict__ vy, double *__restrict__ vz,
+                                                       double *__restrict__ fx, double *__restrict__ fy,
+                                                       double *__restrict__ fz, double *__restrict__ xo,
+                                                       double *__restrict__ yo, double *__restrict__ zo,
+                                                       double *__restrict__ partials, int32_t *err) {
+    __shared__ Hood h;
+    extern __shared__ double lds[];
+    const int b = xcd_remap();
+    if (b >= d.nblk)
+        return;
+    const Box B = boxes[blk_box[b]];
+    hood_setup(B, b - B.block_off, cell_start, h);
+    const int total = h.off[h.ncell];
+    const bool fits = total <= d.cap;
+    const LdsPos spos{(lds_double *)lds};
+    const GlobalPos gpos{x, y, z};
+    if (fits)
+        hood_stage(h, total, x, y, z, spos.s);
+    double u = 0.0, w = 0.0, ke = 0.0;
+    for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
+        const double xi = x[i], yi = y[i], zi = z[i];
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        const v4i *chunks = list_chunks(nbr, i, d.nchunk);
+        if (fits)
+            pair_sum<THERMO>(chunks, cnt[i], spos, xi, yi, zi, B, ax, ay, az, u, w);
+        else
+            pair_sum<THERMO>(chunks, cnt[i], gpos, xi, yi, zi, B, ax, ay, az, u, w);
+        if (MODE == 0 || MODE == 1) {
+            fx[i] = ax;
+            fy[i] = ay;
+            fz[i] = az;
+            if (!(isfinite(ax) && isfinite(ay) && isfinite(az)))
+                atomicOr(err, kErrNonFinite);
+        }
+        if (MODE >= 1) {
+            double a = vx[i] + B.h * ax, bb = vy[i] + B.h * ay, c = vz[i] + B.h * az;
+            if (THERMO)
+                ke += a * a + bb * bb + c * c;
+            if (MODE == 2) {
+                a = a + B.h * ax;
+                bb = bb + B.h * ay;
+                c = c + B.h * az;
+                const double nx = wrap(xi + B.dt * a, B.L), ny = wrap(yi + B.dt * bb, B.L),
+                             nz = wrap(zi + B.dt * c, B.L);
+                xo[i] = nx;
+                yo[i] = ny;
+                zo[i] = nz;
+                if (!(isfinite(nx) && isfinite(ny) && isfinite(nz)))
+                    atomicOr(err, kErrNonFinite);
+            }
+            vx[i] = a;
+            vy[i] = bb;
+            vz[i] = c;
+        }
+    }
+    if (THERMO) {
+        block_sum3(u, w, ke);
+        if (threadIdx.x == 0) {
+            partials[b * kPartialStride + 0] = u;
+            partials[b * kPartialStride + 1] = w;
+            partials[b * kPartialStride + 2] = ke;
+        }
+    }
+}
+
+// First half of a step when F of the current positions is already stored.
+__global__ __launch_bounds__(kAtomThreads) void k_drift(Dims d, const Box *__restrict__ boxes,
+                                                        const int32_t *__restrict__ atom_box,
+                                                        const double *__restrict__ x, const double *__restrict__ y,
+                                                        const double *__restrict__ z, double *__restrict__ vx,
+                                                        double *__restrict__ vy, double *__restrict__ vz,
+                                                        const double *__restrict__ fx,
+                                                        const double *__restrict__ fy,
+                                                        const double *__restrict__ fz, double *__restrict__ xo,
+                                                        double *__restrict__ yo, double *__restrict__ zo,
+                                                        int32_t *err) {
+    const int i = blockIdx.x * kAtomThreads + threadIdx.x;
+    if (i >= d.nt)
+        return;
+    const Box &B = boxes[atom_box[i]];
+    const double a = vx[i] + B.h * fx[i], b = vy[i] + B.h * fy[i], c = vz[i] + B.h * fz[i];
+    vx[i] = a;
+    vy[i] = b;
+    vz[i] = c;
+    const double nx = wrap(x[i] + B.dt * a, B.L), ny = wrap(y[i] + B.dt * b, B.L), nz = wrap(z[i] + B.dt * c, B.L);
+    xo[i] = nx;
+    yo[i] = ny;
+    zo[i] = nz;
+    if (!(isfinite(nx) && isfinite(ny) && isfinite(nz)))
+        atomicOr(err, kErrNonFinite);
+}
+
+// One wavefront per box sums that box's block partials in a fixed order.
+__global__ __launch_bounds__(64) void k_reduce(const Box *__restrict__ boxes, const double *__restrict__ partials,
+                                               double *out, int row_len) {
+    const Box &B = boxes[blockIdx.x];
+    double u = 0.0, w = 0.0, k = 0.0;
+    for (int q = threadIdx.x; q < B.nblocks; q += 64) {
+        const int blk = B.block_off + q;
+        u += partials[blk * kPartialStride + 0];
+        w += partials[blk * kPartialStride + 1];
+        k += partials[blk * kPartialStride + 2];
+    }
+    u = wave_sum(u);
+    w = wave_sum(w);
+    k = wave_sum(k);
+    if (threadIdx.x == 0) {
+        const double U = 0.5 * u, W = 0.5 * w, KE = 0.5 * B.mass * k;
+        double *row = out + int64_t(blockIdx.x) * row_len;
+        if (row_len == 2) {
+            row[0] = U;
+            row[1] = W;
+        } else {
+            row[0] = KE;
+            row[1] = B.n > 1 ? 2.0 * KE / (3.0 * B.n - 3.0) : 0.0;
+            row[2] = U;
+            row[3] = W;
+            row[4] = KE + U;
+        }
+    }
+}
+
+// Current list in original ids, rows sorted ascending, unused slots -1.
+__global__ __launch_bounds__(kMaxThreads) void k_export_neighbors(Dims d, const Box *__restrict__ boxes,
+                                                                  const int32_t *__restrict__ blk_box,
+                                                                  const int32_t *__restrict__ cell_start,
+                                                                  const int32_t *__restrict__ cnt,
+                                                                  const int32_t *__restrict__ nbr,
+                                                                  const int32_t *__restrict__ orig,
+                                                                  int32_t *counts, int32_t *ids) {
+    __shared__ Hood h;
+    const int b = xcd_remap();
+    if (b >= d.nblk)
+        return;
+    const Box B = boxes[blk_box[b]];
+    hood_setup(B, b - B.block_off, cell_start, h);
+    const bool fits = h.off[h.ncell] <= d.cap;
+    for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
+        const int o = orig[i], c = cnt[i];
+        int32_t *row = ids + int64_t(o) * d.maxnb;
+        for (int k = 0; k < c; ++k) {
+            int g = nbr[nbr_index(i, k, d.nchunk)];
+            if (fits) {
+                const int uu = hood_find(h, g);
+                g = h.cs[uu] + (g - h.off[uu]);
+            }
+            const int v = orig[g];
+            int q = k - 1;
+            while (q >= 0 && row[q] > v) {
+                row[q + 1] = row[q];
+                --q;
+            }
+            row[q + 1] = v;
+        }
+        for (int k = c; k < d.maxnb; ++k)
+            row[k] = -1;
+        counts[o] = c;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t prepare_kernels(const Dims &d) {
+    const int bytes = int(hood_lds_bytes(d.cap));
+    const void *fns[] = {
+        reinterpret_cast<const void *>(&k_build),
+        reinterpret_cast<const void *>(&k_force<0, false>),
+        reinterpret_cast<const void *>(&k_force<0, true>),
+        reinterpret_cast<const void *>(&k_force<1, false>),
+        reinterpret_cast<const void *>(&k_force<1, true>),
+        reinterpret_cast<const void *>(&k_force<2, false>),
+        reinterpret_cast<const void *>(&k_force<2, true>),
+    };
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0)
+        return hipSuccess;
+    k_fill_i32<<<int((n + 255) / 256), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_state(const Dims &d, const double *const pos[3], const double *const vel[3], Buffers &b,
+                             Cursor c, hipStream_t s) {
+    k_load_state<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, pos[0], pos[1], pos[2], vel[0],
+                                                             vel[1], vel[2], b.x[c.x], b.y[c.x], b.z[c.x],
+                                                             b.vx[c.o], b.vy[c.o], b.vz[c.o], b.orig[c.o],
+                                                             b.x[1 - c.x], b.y[1 - c.x], b.z[1 - c.x], b.err);
+    return hipGetLastError();
+}
+
+hipError_t launch_unload(const Dims &d, const double *ax, const double *ay, const double *az, const int32_t *orig,
+                         double *const out[3], hipStream_t s) {
+    k_unload<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, ax, ay, az, orig, out[0], out[1], out[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
+    const int xc = c.x, xn = 1 - c.x, o = c.o, on = 1 - c.o;
+    hipError_t e = launch_fill_i32(b.cell_count, 0, d.ncs, s);
+    if (e != hipSuccess)
+        return e;
+    k_bin_count<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, b.x[xc], b.y[xc], b.z[xc],
+                                                            b.cell_of, b.slot, b.cell_count, b.err);
+    const int nt = scan_blocks(d.ncs);
+    k_scan_tiles<<<nt, 256, 0, s>>>(b.cell_count, b.cell_start, b.scan_sums, d.ncs);
+    k_scan_sums<<<1, 1024, 0, s>>>(b.scan_sums, nt, b.cell_start, d.ncs);
+    k_scan_add<<<(d.ncs + 255) / 256, 256, 0, s>>>(b.cell_start, b.scan_sums, d.ncs);
+    k_scatter<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.cell_of, b.slot, b.cell_start, b.tmp_idx);
+    k_rank_permute<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.tmp_idx, b.cell_of, b.cell_start, b.x[xc],
+                                                               b.y[xc], b.z[xc], b.vx[o], b.vy[o], b.vz[o],
+                                                               b.orig[o], b.x[xn], b.y[xn], b.z[xn], b.vx[on],
+                                                               b.vy[on], b.vz[on], b.orig[on]);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
+    k_build<<<block_grid(d.nblk), d.threads, hood_lds_bytes(d.cap), s>>>(
+        d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.nbr_count, b.nbr, b.err);
+    return hipGetLastError();
+}
+
+template <int MODE, bool THERMO>
+static void force_variant(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
+    const int xc = c.x, xn = 1 - c.x;
+    k_force<MODE, THERMO><<<block_grid(d.nblk), d.threads, hood_lds_bytes(d.cap), s>>>(
+        d, b.boxes, b.blk_box, b.x[xc], b.y[xc], b.z[xc], b.cell_start, b.nbr_count, b.nbr, b.vx[c.o], b.vy[c.o],
+        b.vz[c.o], b.fx, b.fy, b.fz, b.x[xn], b.y[xn], b.z[xn], b.partials, b.err);
+}
+
+hipError_t launch_force(const Dims &d, Buffers &b, Cursor c, int mode, bool thermo, hipStream_t s) {
+    switch (mode * 2 + (thermo ? 1 : 0)) {
+    case 0: force_variant<0, false>(d, b, c, s); break;
+    case 1: force_variant<0, true>(d, b, c, s); break;
+    case 2: force_variant<1, false>(d, b, c, s); break;
+    case 3: force_variant<1, true>(d, b, c, s); break;
+    case 4: force_variant<2, false>(d, b, c, s); break;
+    case 5: force_variant<2, true>(d, b, c, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_drift(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
+    const int xc = c.x, xn = 1 - c.x;
+    k_drift<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, b.x[xc], b.y[xc], b.z[xc], b.vx[c.o],
+                                                        b.vy[c.o], b.vz[c.o], b.fx, b.fy, b.fz, b.x[xn], b.y[xn],
+                                                        b.z[xn], b.err);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Dims &d, const Buffers &b, double *out, int row_len, hipStream_t s) {
+    k_reduce<<<d.nbox, 64, 0, s>>>(b.boxes, b.partials, out, row_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_neighbors(const Dims &d, const Buffers &b, Cursor c, int32_t *counts, int32_t *ids,
+                                   hipStream_t s) {
+    k_export_neighbors<<<block_grid(d.nblk), d.threads, 0, s>>>(d, b.boxes, b.blk_box, b.cell_start, b.nbr_count,
+                                                                b.nbr, b.orig[c.o], counts, ids);
+    return hipGetLastError();
+}
+
+}  // namespace tmd

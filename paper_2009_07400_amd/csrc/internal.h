@@ -1,5 +1,5 @@
-// Internal declarations shared by the C-ABI layer (api.hip) and the kernels.
-// Not part of the public interface.
+// Internal declarations shared by the C-ABI layer (api.hip) and the kernels
+// (engine.hip).  Not part of the public interface.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,78 +7,109 @@
 
 namespace tmd {
 
-constexpr int kBlock = 256;      // threads per workgroup for per-atom kernels (4 wave64)
-constexpr int kScanTile = 1024;  // elements per workgroup in the cell-count scan
-constexpr int kPartialStride = 4;  // doubles per workgroup partial: U, W, KE, pad
-constexpr int kNumXcd = 8;       // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kScanTile = 1024;    // elements per workgroup in the cell-count scan
+constexpr int kPartialStride = 4;  // doubles per block partial: U, W, KE, pad
+constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kMaxHood = 64;       // cells in a block neighborhood (at most 4 per axis)
+constexpr int kMaxThreads = 256;   // threads per block workgroup (upper bound)
+constexpr int kAtomThreads = 256;  // threads per workgroup of per-atom kernels
 
 // Bits of the device error word err[0].
 constexpr int kErrOverflow = 1;
 constexpr int kErrNonFinite = 2;
 constexpr int kErrOutOfBox = 4;  // set_state got a coordinate outside [-L, 2L)
 
-// Everything a kernel needs to know about one periodic box.
-struct Geom {
-    int32_t n;       // atoms
-    int32_t np;      // padded stride of per-atom arrays and neighbor-major rows
-    int32_t nc;      // cells per axis
-    int32_t ncell;   // nc^3
-    int32_t maxnb;   // list capacity per atom
-    int32_t pad_;
-    double L, halfL, side;  // box, half box, cell side L / nc
-    double rc2, rl2;        // cutoff^2, (cutoff + skin)^2
-    double eps, sigma6;     // LJ parameters
-    double h, dt;           // half kick dt / (2 m), time step
-    double mass;
+// One periodic cubic box.  Cells are numbered block-major: a block is 2x2x2
+// cells (1 cell thick at the high face when the cell count is odd), each
+// block owns 8 consecutive cell slots, so the atoms of a block and of each
+// of its cells are contiguous after binning.
+struct Box {
+    int32_t atom_off, n;     // atoms [atom_off, atom_off + n) of the concatenated arrays
+    int32_t cell_off, nc;    // first cell slot; cells per axis
+    int32_t nbx, block_off;  // blocks per axis (ceil(nc / 2)); first block
+    int32_t nblocks, pad_;
+    double L, halfL, side;   // box, half box, cell side L / nc
+    double halfL2;           // (L/2)^2
+    double rc2, rl2;         // cutoff^2, (cutoff + skin)^2
+    double eps, sigma6;      // LJ parameters
+    double eps48, eps24;     // 48 eps and 24 eps: f = sr2 sr6 (48 eps sr6 - 24 eps)
+    double eps4;             // 4 eps: pair energy sr6 (4 eps sr6 - 4 eps)
+    double h, dt, mass;      // half kick dt / (2 m), time step, mass
 };
 
-// Device pointers carved from the caller's workspace.  Positions, velocities
-// and original ids are double-buffered: binning permutes buffer `cur` into
-// the other one, and the fused force/drift kernel writes new positions there.
+// Sizes shared by all kernels of one system.
+struct Dims {
+    int32_t nt;       // atoms in all boxes
+    int32_t ntp;      // padded stride of the neighbor-major list
+    int32_t nbox;     // boxes
+    int32_t nblk;     // blocks in all boxes
+    int32_t ncs;      // cell slots in all boxes (8 per block)
+    int32_t maxnb;    // list capacity per atom
+    int32_t cap;      // atoms a block neighborhood may stage in LDS
+    int32_t threads;  // threads per block workgroup (64..kMaxThreads, multiple of 64)
+    int32_t nchunk;   // 4-entry list chunks per atom: ceil(maxnb / 4)
+};
+
+// Neighbor list layout: neighbor-major within tiles of 64 atoms (one
+// wavefront) and chunks of 4 entries.  Entry k of atom i lives at
+//   ((tile(i) * nchunk + k / 4) * 64 + lane(i)) * 4 + k % 4,
+// so one 16-byte load gives a lane four consecutive entries, a wavefront's
+// chunk is one contiguous 1 KB row, and a tile's whole list is one
+// contiguous stretch of nchunk KB that a wavefront streams through in order.
+__host__ __device__ inline int64_t nbr_index(int i, int k, int nchunk) {
+    return ((int64_t((i >> 6)) * nchunk + (k >> 2)) * 64 + (i & 63)) * 4 + (k & 3);
+}
+
+// Device pointers carved from the caller's workspace.
 struct Buffers {
     double *x[2], *y[2], *z[2];
     double *vx[2], *vy[2], *vz[2];
     int32_t *orig[2];
     double *fx, *fy, *fz;
+    Box *boxes;            // [nbox]  (uploaded at set_state)
+    int32_t *blk_box;      // [nblk]  box of each block
+    int32_t *atom_box;     // [nt]    box of each atom slot (boxes keep fixed slot ranges)
     int32_t *cell_of, *slot, *tmp_idx;
     int32_t *cell_count, *cell_start, *scan_sums;
     int32_t *nbr_count, *nbr;
-    double *partials;
-    double *scalars;  // small scratch for reductions
-    int32_t *err;     // [0] flags, [1] largest list length requested on overflow
+    double *partials;      // [nblk][kPartialStride]
+    int32_t *err;          // [0] flags, [1] largest list length requested on overflow
 };
-
-// Grid size for per-atom kernels: a multiple of the XCD count so the
-// blockIdx remap below gives every XCD one contiguous range of atoms.
-inline int atom_grid(int n) {
-    int g = (n + kBlock - 1) / kBlock;
-    return ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
-}
-inline int scan_blocks(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
 
 // Which half of each double buffer is current: positions flip on every drift
 // and every binning; velocities and original ids flip only on binning (the
 // kicks update velocities in place).
 struct Cursor {
-    int x = 0;  // positions
-    int o = 0;  // atom order: velocities and original ids
+    int x = 0;
+    int o = 0;
 };
 
-// Launchers (kernels.hip).  All enqueue on `s` and return the launch status.
+inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+inline int atom_blocks(int n) { return (n + kAtomThreads - 1) / kAtomThreads; }
+inline int scan_blocks(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
+// Grid of block workgroups: a multiple of the XCD count so the remap in the
+// kernels gives every XCD one contiguous range of blocks.
+inline int block_grid(int nblk) { return round_up(nblk, kNumXcd); }
+// LDS bytes of a block workgroup staging `cap` atoms plus the NaN sentinel.
+inline size_t hood_lds_bytes(int cap) { return size_t(cap + 1) * 3 * sizeof(double); }
+
+// Launchers (engine.hip).  All enqueue on `s` and return the launch status.
+hipError_t prepare_kernels(const Dims &d);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
-hipError_t launch_load_state(const Geom &g, const double *const pos[3], const double *const vel[3],
-                             Buffers &b, Cursor c, hipStream_t s);
-hipError_t launch_unload(const Geom &g, const double *ax, const double *ay, const double *az,
-                         const int32_t *orig, double *const out[3], hipStream_t s);
-hipError_t launch_bin(const Geom &g, Buffers &b, Cursor c, hipStream_t s);  // both halves flip
-hipError_t launch_build(const Geom &g, Buffers &b, Cursor c, hipStream_t s);
-// mode 0: F only (stored); 1: F + kick (stored, end of integrate); 2: F + kick + kick + drift into 1 - c.x
-hipError_t launch_force(const Geom &g, Buffers &b, Cursor c, int mode, bool thermo, hipStream_t s);
-hipError_t launch_drift(const Geom &g, Buffers &b, Cursor c, hipStream_t s);  // positions into 1 - c.x
-// Deterministic sum of the force kernel's workgroup partials.  Writes
-// (U, W) when row_len == 2 or (KE, T, U, W, E) when row_len == 5.
-hipError_t launch_reduce(const Geom &g, const Buffers &b, double *out, int row_len, hipStream_t s);
-hipError_t launch_export_neighbors(const Geom &g, const Buffers &b, Cursor c, int32_t *counts, int32_t *ids,
+hipError_t launch_load_state(const Dims &d, const double *const pos[3], const double *const vel[3], Buffers &b,
+                             Cursor c, hipStream_t s);
+hipError_t launch_unload(const Dims &d, const double *ax, const double *ay, const double *az, const int32_t *orig,
+                         double *const out[3], hipStream_t s);
+hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s);  // both halves flip
+hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s);
+// mode 0: F only (stored); 1: F + kick (stored, end of integrate);
+// 2: F + kick + kick + drift into positions 1 - c.x
+hipError_t launch_force(const Dims &d, Buffers &b, Cursor c, int mode, bool thermo, hipStream_t s);
+hipError_t launch_drift(const Dims &d, Buffers &b, Cursor c, hipStream_t s);  // positions into 1 - c.x
+// Per-box deterministic sums of the block partials: rows of (U, W) when
+// row_len == 2, (KE, T, U, W, E) when row_len == 5; out holds nbox rows.
+hipError_t launch_reduce(const Dims &d, const Buffers &b, double *out, int row_len, hipStream_t s);
+hipError_t launch_export_neighbors(const Dims &d, const Buffers &b, Cursor c, int32_t *counts, int32_t *ids,
                                    hipStream_t s);
 
 }  // namespace tmd

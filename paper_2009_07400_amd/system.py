@@ -1,4 +1,4 @@
-"""Python front end of one periodic LJ box on one GPU.
+"""Python front end of one or many periodic LJ boxes on one GPU.
 
 PyTorch provides device memory (the library's workspace and the caller's
 arrays) and the stream (torch's current stream); every step of the method
@@ -6,6 +6,8 @@ runs in the HIP library through the C ABI in ``_abi``.
 """
 
 from __future__ import annotations
+
+from typing import Sequence
 
 import torch
 
@@ -21,7 +23,7 @@ def _require_cuda():
         raise RuntimeError("paper_2009_07400_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
 
 
-def _soa(t: torch.Tensor, n: int, device) -> torch.Tensor:
+def _soa(t, n: int, device) -> torch.Tensor:
     """[N,3] or [3,N] -> contiguous float64 [3,N] on the device."""
     t = torch.as_tensor(t, dtype=torch.float64, device=device)
     if t.shape == (n, 3):
@@ -41,19 +43,28 @@ def make_params(epsilon=1.0, sigma=1.0, mass=1.0, cutoff=2.5, skin=0.3, dt=0.005
 
 
 class System:
-    """A periodic cubic LJ box advanced by the HIP library.
+    """Periodic cubic LJ box(es) advanced by the HIP library.
 
-    Positions and velocities are exchanged as float64 tensors of shape [N, 3]
-    in original atom order.  All calls enqueue work on torch's current stream;
+    ``System(n_atoms, box_length, **params)`` holds one box;
+    ``System.batch(n_atoms, box_lengths, params)`` holds independent boxes
+    advanced together in the same kernel launches.  Positions and velocities
+    are float64 tensors of shape [N, 3] in original atom order (boxes
+    concatenated).  All calls enqueue work on torch's current stream;
     ``sync()`` waits and raises on deferred device errors.
     """
 
-    def __init__(self, n_atoms: int, box_length: float, device="cuda", **params):
+    def __init__(self, n_atoms: int, box_length: float, device="cuda", _handle=None, _boxes=None, **params):
         abi.load_library()
-        self.params = make_params(**params)
-        self.n = int(n_atoms)
-        self.box_length = float(box_length)
-        self._h = abi.tmd_create(self.params, self.n, self.box_length)
+        if _handle is None:
+            self.params = [make_params(**params)]
+            self.box_atoms = [int(n_atoms)]
+            self.box_lengths = [float(box_length)]
+            self._h = abi.tmd_create(self.params[0], self.box_atoms[0], self.box_lengths[0])
+        else:
+            self.params, self.box_atoms, self.box_lengths = _boxes
+            self._h = _handle
+        self.n = sum(self.box_atoms)
+        self.nbox = len(self.box_atoms)
         _require_cuda()
         self.device = torch.device(device)
         nbytes = abi.tmd_workspace_size(self._h)
@@ -62,6 +73,18 @@ class System:
         self._ws = ws
         abi.tmd_bind_workspace(self._h, int(ws.data_ptr()) + off, nbytes)
         self._keep = []  # inputs kept alive until the next sync
+
+    @classmethod
+    def batch(cls, n_atoms: Sequence[int], box_lengths: Sequence[float], params=None, device="cuda"):
+        """params: None (defaults), one dict for all boxes, or one dict per box."""
+        nb = len(n_atoms)
+        if params is None or isinstance(params, dict):
+            plist = [make_params(**(params or {})) for _ in range(nb)]
+        else:
+            plist = [make_params(**p) for p in params]
+        h = abi.tmd_create_batch(plist, [int(v) for v in n_atoms], [float(v) for v in box_lengths])
+        return cls(0, 0.0, device=device, _handle=h,
+                   _boxes=(plist, [int(v) for v in n_atoms], [float(v) for v in box_lengths]))
 
     # -- state -----------------------------------------------------------
     def set_state(self, pos, vel, step: int = 0) -> None:
@@ -81,26 +104,31 @@ class System:
         abi.tmd_build_neighbors(self._h, _stream())
 
     def compute_forces(self, energy: bool = True):
-        """Returns (F [N,3], tensor([U, W]) or None)."""
+        """Returns (F [N,3], energy/virial or None): [U, W] for one box,
+        [n_boxes, 2] for a batch."""
         f = torch.empty(3, self.n, dtype=torch.float64, device=self.device)
-        ev = torch.empty(2, dtype=torch.float64, device=self.device) if energy else None
+        ev = torch.empty(self.nbox, 2, dtype=torch.float64, device=self.device) if energy else None
         abi.tmd_compute_forces(self._h, _ptrs(f), int(ev.data_ptr()) if ev is not None else None, _stream())
+        if ev is not None and self.nbox == 1:
+            ev = ev[0]
         return f.t(), ev
 
     def integrate(self, n_steps: int, thermo_every: int = 0):
-        """Advance n_steps; returns thermo rows [n_steps // thermo_every, 5]
-        (KE, T, U, W, E) when thermo_every > 0, else None."""
+        """Advance n_steps; with thermo_every > 0 returns rows (KE, T, U, W, E):
+        [n_steps // thermo_every, 5] for one box, [rows, n_boxes, 5] for a batch."""
         th = None
         rows = n_steps // thermo_every if thermo_every > 0 else 0
         if rows > 0:
-            th = torch.empty(rows, 5, dtype=torch.float64, device=self.device)
+            th = torch.empty(rows, self.nbox, 5, dtype=torch.float64, device=self.device)
         abi.tmd_integrate(self._h, int(n_steps), int(thermo_every) if rows > 0 else 0,
                           int(th.data_ptr()) if th is not None else None, _stream())
+        if th is not None and self.nbox == 1:
+            th = th[:, 0, :]
         return th
 
     def get_neighbors(self):
         """Returns (counts [N] int32, ids [N, max_neighbors] int32 sorted rows, -1 padded)."""
-        m = self.params.max_neighbors
+        m = self.params[0].max_neighbors
         counts = torch.empty(self.n, dtype=torch.int32, device=self.device)
         ids = torch.empty(self.n, m, dtype=torch.int32, device=self.device)
         abi.tmd_get_neighbors(self._h, int(counts.data_ptr()), int(ids.data_ptr()), self.n * m, _stream())
@@ -112,6 +140,16 @@ class System:
 
     def info(self) -> dict:
         return abi.tmd_get_info(self._h)
+
+    def set_schedule(self, threads: int = 0, lds_atoms: int = 0) -> None:
+        """Threads per block workgroup and LDS staging capacity (0 = keep)."""
+        abi.tmd_set_schedule(self._h, threads, lds_atoms)
+
+    def autotune(self, repeats: int = 5) -> int:
+        """Times the force kernel per schedule and keeps the fastest; returns
+        the chosen threads per block workgroup."""
+        abi.tmd_autotune(self._h, repeats, _stream())
+        return self.info()["block_threads"]
 
     def set_timing(self, enable: bool) -> None:
         abi.tmd_set_timing(self._h, enable)

@@ -109,6 +109,35 @@ def test_call_order_and_workspace_checks():
         abi.tmd_destroy(h)
 
 
+def test_batch_create_and_validation():
+    ps = [make_params(), make_params(epsilon=1.05, sigma=0.98), make_params()]
+    h = abi.tmd_create_batch(ps, [256, 500, 6912], [6.72, 8.4, 20.9])
+    try:
+        info = abi.tmd_get_info(h)
+        assert info["n_boxes"] == 3 and info["n_atoms"] == 256 + 500 + 6912
+        # 2 cells per axis -> 1 block; 3 -> 2^3 blocks (the last one cell thick); 7 -> 4^3 blocks
+        assert info["n_blocks"] == 1 + 8 + 64
+        assert info["n_cells"] == 8 + 27 + 343
+        assert info["block_threads"] % 64 == 0 and 64 <= info["block_threads"] <= 256
+        assert info["lds_atoms"] % 64 == 0 and 64 <= info["lds_atoms"] <= 2560
+        abi.tmd_set_schedule(h, 128, 512)
+        info = abi.tmd_get_info(h)
+        assert (info["block_threads"], info["lds_atoms"]) == (128, 512)
+        for bad in ((100, 0), (320, 0), (0, 100), (0, 4096), (-64, 0)):
+            with pytest.raises(abi.TmdError):
+                abi.tmd_set_schedule(h, *bad)
+    finally:
+        abi.tmd_destroy(h)
+    with pytest.raises(abi.TmdError) as e:  # rebuild interval must be shared
+        abi.tmd_create_batch([make_params(), make_params(rebuild_every=10)], [100, 100], [10.0, 10.0])
+    assert e.value.status == abi.TMD_EINVAL
+    with pytest.raises(abi.TmdError) as e:  # one box too small for the cutoff
+        abi.tmd_create_batch([make_params(), make_params()], [100, 100], [10.0, 5.0])
+    assert e.value.status == abi.TMD_EBOX
+    with pytest.raises(ValueError):
+        abi.tmd_create_batch([make_params()], [100, 100], [10.0, 10.0])
+
+
 def test_null_arguments():
     lib = abi.load_library()
     assert lib.tmd_create(None, 10, 13.4, None) == abi.TMD_EINVAL
