@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -122,6 +124,95 @@ def run_gpu(workload: str, steps: int, warmup: int):
     return res
 
 
+def run_batched(steps: int = 200, warmup: int = 20, n_boxes: int = 512):
+    """512 replica boxes (FCC n^3, n in 4..12, rho in [0.75, 0.90], T in
+    [0.7, 1.5], own seeds) advanced together, against the same boxes run one
+    after another as separate single-box systems on the same stream."""
+    import torch
+
+    from paper_2009_07400_amd import System
+    from workloads import batched_box_specs, md_system
+
+    boxes = [md_system(n, rho, T, seed=seed) for n, rho, T, seed in batched_box_specs(n_boxes)]
+    total = sum(b.n for b in boxes)
+    g = System.batch([b.n for b in boxes], [b.L for b in boxes], dict(max_neighbors=128))
+    g.set_state(torch.from_numpy(np.concatenate([b.pos() for b in boxes])),
+                torch.from_numpy(np.concatenate([b.vel() for b in boxes])))
+    threads = g.autotune(repeats=3)
+    g.integrate(warmup)
+    g.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.integrate(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    g.sync()
+    info = g.info()
+    g.close()
+    seq = []
+    for b in boxes:
+        s = System(b.n, b.L, max_neighbors=128)
+        s.set_state(torch.from_numpy(b.pos()), torch.from_numpy(b.vel()))
+        s.integrate(warmup)
+        seq.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in seq:
+        s.integrate(steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for s in seq:
+        s.sync()
+        s.close()
+    return {"workload": f"{n_boxes} LJ boxes, FCC n^3 with n in 4..12 ({total:,} atoms), rho 0.75-0.90, T 0.7-1.5, "
+                        "rc 2.5 + skin 0.3, dt 0.005, rebuild 20",
+            "value": total * steps / t_batch, "unit": "atom-steps/s", "steps": steps,
+            "ms_per_step": t_batch / steps * 1e3, "sequential_value": total * steps / t_seq,
+            "sequential_ms_per_step": t_seq / steps * 1e3, "speedup_vs_sequential": t_seq / t_batch,
+            "block_threads": threads, "n_blocks": info["n_blocks"], "lds_atoms": info["lds_atoms"]}
+
+
+def run_adjoint(steps: int = 200, replicas: int = 64):
+    """64 replicas of FCC 10^3 = 4,000 atoms (rho 0.8442, T 1.0): forward with
+    checkpoints plus the reverse sweep, against the plain forward run."""
+    import torch
+
+    from paper_2009_07400_amd import System
+    from workloads import md_system
+
+    reps = [md_system(10, 0.8442, 1.0, seed=3000 + r) for r in range(replicas)]
+    total = sum(r.n for r in reps)
+    x0 = torch.from_numpy(np.concatenate([r.pos() for r in reps]))
+    v0 = torch.from_numpy(np.concatenate([r.vel() for r in reps]))
+    g = System.batch([r.n for r in reps], [r.L for r in reps], dict(max_neighbors=128))
+    lam = torch.randn(total, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(5))
+    for _ in range(2):  # second pass is the timed one
+        g.set_state(x0, v0)
+        g.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.integrate(steps)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        g.set_state(x0, v0)
+        g.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.adjoint_forward(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.adjoint_backward(lam)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g.sync()
+    g.close()
+    return {"workload": f"{replicas} x LJ FCC 10^3 = {total:,} atoms, rho 0.8442, T 1.0, {steps} steps, "
+                        "checkpoints at every rebuild (20)",
+            "value": total * steps / (t2 - t0), "unit": "atom-steps/s (forward + reverse per step)",
+            "plain_value": total * steps / t_plain, "adjoint_over_plain_time": (t2 - t0) / t_plain,
+            "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3, "plain_ms": t_plain * 1e3}
+
+
 def run_cpu_baseline(workload: str, sample_steps: int):
     import oracle
     from workloads import md_system
@@ -197,6 +288,14 @@ def main():
                                    "ms_per_step": sec["ms_per_step"], "steps": sec["steps"],
                                    "roofline": sec["roofline"], "kernel_avg_ms": sec["kernel_ms"],
                                    "mean_list_length": sec["mean_list_length"]}}
+        bat = run_batched()
+        print(f"# secondary batched: {bat['value']:.4g} atom-steps/s, {bat['speedup_vs_sequential']:.1f}x "
+              "sequential", file=sys.stderr, flush=True)
+        out["secondary"]["batched"] = bat
+        adj = run_adjoint()
+        print(f"# secondary adjoint: {adj['value']:.4g} atom-steps/s, {adj['adjoint_over_plain_time']:.2f}x plain "
+              "time", file=sys.stderr, flush=True)
+        out["secondary"]["adjoint"] = adj
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_steps)
     print(json.dumps(out), flush=True)

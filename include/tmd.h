@@ -200,6 +200,45 @@ tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms)
  * builds the list first if none is valid). */
 tmd_status tmd_autotune(tmd_system *sys, int32_t repeats, tmd_stream stream);
 
+/* Replace epsilon and sigma of every box (host arrays of n_boxes values, each
+ * finite and positive); the copy to the device is enqueued on `stream`.  The
+ * list is kept; forces are recomputed at the next step. */
+tmd_status tmd_set_lj_params(tmd_system *sys, const double *epsilon, const double *sigma, tmd_stream stream);
+
+/* --- Gradients through the discrete trajectory (reverse mode) ------------
+ * The map from (x_0, v_0, epsilon, sigma) to the state after n_steps
+ * velocity-Verlet steps, differentiated exactly with every neighbor list and
+ * every cutoff indicator [s < cutoff^2] held as in the forward run (the
+ * derivative almost everywhere; the force is discontinuous at the cutoff).
+ * Going backward with h = dt / (2m), each force evaluation F(x_k) adds
+ *   lam_x += c J(x_k) lam_v,   grad_theta += c lam_v . dF(x_k)/dtheta,
+ * c = h at k = 0 and k = n_steps and 2h in between (the two half kicks at
+ * x_k), J = dF/dx the LJ Hessian block matrix applied to lam_v as a
+ * Hessian-vector product, and each drift adds lam_v += dt lam_x. */
+
+/* Bytes of adjoint workspace for an n_steps run: (x, v) checkpoints at each
+ * rebuild, one rebuild interval of recomputed positions, cotangents. */
+tmd_status tmd_adjoint_workspace_size(const tmd_system *sys, int32_t n_steps, size_t *bytes);
+
+/* Integrate n_steps like tmd_integrate() while recording checkpoints in `ws`
+ * (device, 256-byte aligned, at least tmd_adjoint_workspace_size bytes,
+ * borrowed until the backward pass).  The step counter must be a multiple of
+ * rebuild_every (TMD_ESTATE otherwise); the run starts from a list built at
+ * the current positions. */
+tmd_status tmd_adjoint_forward(tmd_system *sys, int32_t n_steps, void *ws, size_t bytes, tmd_stream stream);
+
+/* Given the cotangents of the final state lam_x[3] (required) and lam_v[3]
+ * (nullable = zero), device arrays in original order, write
+ * grad_x0[3] = dL/dx_0, grad_v0[3] = dL/dv_0 (nullable), and per box
+ * grad_eps[n_boxes], grad_sigma[n_boxes] (device, nullable).  Needs the run
+ * recorded by tmd_adjoint_forward() in the same workspace with no
+ * state-changing call in between (TMD_ESTATE otherwise).  Recomputes each
+ * rebuild interval from its checkpoint (bit-identical to the recorded run)
+ * and leaves the system in the run's final state. */
+tmd_status tmd_adjoint_backward(tmd_system *sys, void *ws, size_t bytes, const double *const lam_x[3],
+                                const double *const lam_v[3], double *const grad_x0[3], double *const grad_v0[3],
+                                double *grad_eps, double *grad_sigma, tmd_stream stream);
+
 /* Per-kernel-class timing with HIP events recorded on the launch stream around
  * every kernel (only while enabled).  tmd_get_timing() synchronises, then
  * returns accumulated milliseconds and launch counts for the TMD_T_* classes

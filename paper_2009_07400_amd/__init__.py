@@ -10,6 +10,7 @@ the built library.
 
 from . import _abi  # noqa: F401
 from ._abi import TmdError, TmdParams, load_library  # noqa: F401
+from .autograd import LJMDFunction, lj_md  # noqa: F401
 from .system import System, make_params  # noqa: F401
 
-__all__ = ["System", "make_params", "TmdError", "TmdParams", "load_library"]
+__all__ = ["System", "make_params", "TmdError", "TmdParams", "load_library", "LJMDFunction", "lj_md"]

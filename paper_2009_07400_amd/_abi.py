@@ -90,6 +90,10 @@ def load_library():
         "tmd_sync": (_S, [_P, _P]),
         "tmd_get_info": (_S, [_P, C.POINTER(TmdInfo)]),
         "tmd_set_schedule": (_S, [_P, C.c_int32, C.c_int32]),
+        "tmd_set_lj_params": (_S, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]),
+        "tmd_adjoint_workspace_size": (_S, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
+        "tmd_adjoint_forward": (_S, [_P, C.c_int32, _P, C.c_size_t, _P]),
+        "tmd_adjoint_backward": (_S, [_P, _P, C.c_size_t, _P, _P, _P, _P, _P, _P, _P]),
         "tmd_autotune": (_S, [_P, C.c_int32, _P]),
         "tmd_set_timing": (_S, [_P, C.c_int32]),
         "tmd_get_timing": (_S, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -202,6 +206,30 @@ def tmd_get_info(handle) -> dict:
 
 def tmd_set_schedule(handle, threads: int, lds_atoms: int) -> None:
     _check(load_library().tmd_set_schedule(handle, threads, lds_atoms), handle)
+
+
+def tmd_set_lj_params(handle, epsilon, sigma, stream: int) -> None:
+    nb = len(epsilon)
+    _check(load_library().tmd_set_lj_params(handle, (C.c_double * nb)(*epsilon), (C.c_double * nb)(*sigma),
+                                             stream), handle)
+
+
+def tmd_adjoint_workspace_size(handle, n_steps: int) -> int:
+    n = C.c_size_t()
+    _check(load_library().tmd_adjoint_workspace_size(handle, n_steps, C.byref(n)), handle)
+    return int(n.value)
+
+
+def tmd_adjoint_forward(handle, n_steps: int, ws_ptr: int, nbytes: int, stream: int) -> None:
+    _check(load_library().tmd_adjoint_forward(handle, n_steps, ws_ptr, nbytes, stream), handle)
+
+
+def tmd_adjoint_backward(handle, ws_ptr: int, nbytes: int, lam_x, lam_v, grad_x0, grad_v0, grad_eps_ptr,
+                         grad_sigma_ptr, stream: int) -> None:
+    arrs = [_p3(a) for a in (lam_x, lam_v, grad_x0, grad_v0)]
+    ptrs = [C.cast(a, _P) if a is not None else None for a in arrs]
+    _check(load_library().tmd_adjoint_backward(handle, ws_ptr, nbytes, *ptrs, grad_eps_ptr, grad_sigma_ptr, stream),
+           handle)
 
 
 def tmd_autotune(handle, repeats: int, stream: int) -> None:

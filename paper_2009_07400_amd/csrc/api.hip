@@ -28,6 +28,16 @@ struct tmd_system {
     bool bound = false, have_state = false, list_valid = false, force_valid = false, prepared = false;
     int64_t step = 0;
     std::string err;
+    uint64_t gen = 0;  // bumped by every call that changes the state or the parameters
+
+    // recorded forward run for the adjoint
+    struct Adj {
+        bool recorded = false;
+        int64_t step0 = 0;
+        int32_t nsteps = 0, nseg = 0;
+        void *ws = nullptr;
+        uint64_t gen = 0;
+    } adj;
 
     struct Ev {
         int cls;
@@ -162,6 +172,7 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
         return hip_fail(s, e, "neighbor build");
     s->list_valid = true;
     s->force_valid = false;
+    s->gen++;
     return TMD_OK;
 }
 
@@ -224,6 +235,7 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
         B.eps48 = 48.0 * p.epsilon;
         B.eps24 = 24.0 * p.epsilon;
         B.eps4 = 4.0 * p.epsilon;
+        B.eps_over_sigma = p.epsilon / p.sigma;
         const double s2 = p.sigma * p.sigma;
         B.sigma6 = s2 * s2 * s2;
         B.h = 0.5 * p.dt / p.mass;
@@ -275,6 +287,45 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
     return TMD_OK;
 }
 
+// Adjoint workspace: checkpoints of (x, v) in original order at every
+// rebuild step of the recorded run plus its final state, one segment of
+// recomputed positions in sorted order, the cotangents and the parameter
+// gradient accumulators.
+struct AdjBuf {
+    double *ckpt;   // [(nseg + 1) * 6 * nt]
+    double *traj;   // [(R + 1) * 3 * ntp]
+    Pos lx, wa, wb; // sorted order, ntp each
+    double *lo;     // [6 * nt] cotangents in original order
+    double *partials;
+    double *acc;    // [2 * nbox]
+};
+
+size_t carve_adj(const Dims &d, int32_t R, int32_t nsteps, char *base, AdjBuf *out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    const size_t nt = size_t(d.nt), np = size_t(d.ntp);
+    const int32_t nseg = (nsteps + R - 1) / R;
+    AdjBuf a{};
+    a.ckpt = (double *)take(size_t(nseg + 1) * 6 * nt * 8);
+    a.traj = (double *)take(size_t(R + 1) * 3 * np * 8);
+    Pos *ps[3] = {&a.lx, &a.wa, &a.wb};
+    for (Pos *p : ps) {
+        p->x = (double *)take(np * 8);
+        p->y = (double *)take(np * 8);
+        p->z = (double *)take(np * 8);
+    }
+    a.lo = (double *)take(6 * nt * 8);
+    a.partials = (double *)take(size_t(d.nblk) * kPartialStride * 8);
+    a.acc = (double *)take(size_t(d.nbox) * 2 * 8);
+    if (out)
+        *out = a;
+    return off;
+}
+
 tmd_status upload_tables(tmd_system *s, hipStream_t hs) {
     hipError_t e = hipMemcpyAsync(s->b.boxes, s->boxes.data(), s->boxes.size() * sizeof(Box), hipMemcpyHostToDevice,
                                   hs);
@@ -283,7 +334,19 @@ tmd_status upload_tables(tmd_system *s, hipStream_t hs) {
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->b.atom_box, s->atom_box.data(), s->atom_box.size() * 4, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && !s->prepared) {
-        e = prepare_kernels(s->d);
+        // the adjoint kernel stages 48 bytes per atom: keep within the
+        // device's per-workgroup LDS limit (static LDS needs < 1 KB)
+        int dev = 0, max_lds = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e == hipSuccess && 2 * hood_lds_bytes(s->d.cap) + 1024 > size_t(max_lds)) {
+            const int fit = int((size_t(max_lds) - 1024) / 48) - 1;
+            s->d.cap = std::max(64, fit / 64 * 64);
+            s->list_valid = s->force_valid = false;
+        }
+        if (e == hipSuccess)
+            e = prepare_kernels(s->d);
         s->prepared = (e == hipSuccess);
     }
     return e == hipSuccess ? TMD_OK : hip_fail(s, e, "table upload");
@@ -332,6 +395,7 @@ tmd_status tmd_bind_workspace(tmd_system *s, void *dev, size_t bytes) {
         return fail(s, TMD_EWORKSPACE, "workspace must be 256-byte aligned and at least tmd_workspace_size bytes");
     carve(s->d, static_cast<char *>(dev), &s->b);
     s->bound = true;
+    s->gen++;
     s->have_state = s->list_valid = s->force_valid = false;
     s->cur = Cursor{};
     return TMD_OK;
@@ -359,6 +423,7 @@ tmd_status tmd_set_state(tmd_system *s, const double *const pos[3], const double
     s->cur = Cursor{};
     s->step = step;
     s->have_state = true;
+    s->gen++;
     s->list_valid = s->force_valid = false;
     return TMD_OK;
 }
@@ -452,6 +517,7 @@ tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, d
     }
     s->force_valid = true;
     s->step += n_steps;
+    s->gen++;
     return TMD_OK;
 }
 
@@ -547,6 +613,7 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms) {
     if (lds_atoms > 0 && lds_atoms != s->d.cap) {
         s->d.cap = lds_atoms;
         s->prepared = false;  // LDS attribute of the block kernels must follow
+        s->gen++;
         // the list encodes LDS slots only for neighborhoods that fit
         s->list_valid = s->force_valid = false;
         if (s->bound) {
@@ -601,6 +668,182 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     s->d.threads = (e == hipSuccess) ? best_t : saved;
     s->force_valid = true;
     return e == hipSuccess ? TMD_OK : hip_fail(s, e, "autotune");
+}
+
+tmd_status tmd_set_lj_params(tmd_system *s, const double *epsilon, const double *sigma, tmd_stream stream) {
+    tmd_status st = check_ready(s, false);
+    if (st != TMD_OK)
+        return st;
+    if (!epsilon || !sigma)
+        return fail(s, TMD_EINVAL, "set_lj_params: NULL array");
+    for (int32_t k = 0; k < s->d.nbox; ++k)
+        if (!positive(epsilon[k]) || !positive(sigma[k]))
+            return fail(s, TMD_EINVAL, "set_lj_params: epsilon and sigma must be finite and positive");
+    for (int32_t k = 0; k < s->d.nbox; ++k) {
+        Box &B = s->boxes[size_t(k)];
+        const double e = epsilon[k], s2 = sigma[k] * sigma[k];
+        B.eps = e;
+        B.sigma6 = s2 * s2 * s2;
+        B.eps48 = 48.0 * e;
+        B.eps24 = 24.0 * e;
+        B.eps4 = 4.0 * e;
+        B.eps_over_sigma = e / sigma[k];
+    }
+    hipError_t e = hipMemcpyAsync(s->b.boxes, s->boxes.data(), s->boxes.size() * sizeof(Box), hipMemcpyHostToDevice,
+                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(s, e, "set_lj_params");
+    s->force_valid = false;
+    s->gen++;
+    return TMD_OK;
+}
+
+tmd_status tmd_adjoint_workspace_size(const tmd_system *s, int32_t n_steps, size_t *bytes) {
+    if (!s || !bytes || n_steps < 1)
+        return TMD_EINVAL;
+    *bytes = carve_adj(s->d, s->rebuild_every, n_steps, nullptr, nullptr);
+    return TMD_OK;
+}
+
+tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t bytes, tmd_stream stream) {
+    tmd_status st = check_ready(s, true);
+    if (st != TMD_OK)
+        return st;
+    if (n_steps < 1 || !ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 ||
+        bytes < carve_adj(s->d, s->rebuild_every, n_steps, nullptr, nullptr))
+        return fail(s, TMD_EINVAL, "adjoint_forward: n_steps < 1 or workspace missing, misaligned or too small");
+    const int32_t R = s->rebuild_every;
+    if (s->step % R != 0)
+        return fail(s, TMD_ESTATE, "adjoint_forward: the step counter must be a multiple of rebuild_every");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    AdjBuf a{};
+    carve_adj(s->d, R, n_steps, static_cast<char *>(ws), &a);
+    const int32_t nseg = (n_steps + R - 1) / R;
+    const size_t nt = size_t(s->d.nt);
+    s->list_valid = s->force_valid = false;  // the run starts from a list built at its first positions
+    const int64_t step0 = s->step;
+    for (int32_t m = 0; m <= nseg; ++m) {
+        double *c = a.ckpt + size_t(m) * 6 * nt;
+        double *const po[3] = {c, c + nt, c + 2 * nt};
+        double *const vo[3] = {c + 3 * nt, c + 4 * nt, c + 5 * nt};
+        if ((st = tmd_get_state(s, po, vo, nullptr, stream)) != TMD_OK)
+            return st;
+        if (m < nseg) {
+            const int32_t k = std::min(R, n_steps - m * R);
+            if ((st = tmd_integrate(s, k, 0, nullptr, stream)) != TMD_OK)
+                return st;
+        }
+    }
+    (void)hs;
+    s->adj.recorded = true;
+    s->adj.step0 = step0;
+    s->adj.nsteps = n_steps;
+    s->adj.nseg = nseg;
+    s->adj.ws = ws;
+    s->adj.gen = ++s->gen;
+    return TMD_OK;
+}
+
+tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const double *const lam_x[3],
+                                const double *const lam_v[3], double *const grad_x0[3], double *const grad_v0[3],
+                                double *grad_eps, double *grad_sigma, tmd_stream stream) {
+    tmd_status st = check_ready(s, true);
+    if (st != TMD_OK)
+        return st;
+    if (!s->adj.recorded || ws != s->adj.ws || s->gen != s->adj.gen)
+        return fail(s, TMD_ESTATE, "adjoint_backward: no forward run recorded in this workspace, or the state "
+                                   "changed since");
+    if (bytes < carve_adj(s->d, s->rebuild_every, s->adj.nsteps, nullptr, nullptr) || !lam_x || !lam_x[0] ||
+        !lam_x[1] || !lam_x[2] || !grad_x0 || !grad_x0[0] || !grad_x0[1] || !grad_x0[2])
+        return fail(s, TMD_EINVAL, "adjoint_backward: workspace too small or NULL cotangent / gradient array");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int32_t R = s->rebuild_every, T = s->adj.nsteps, nseg = s->adj.nseg;
+    const size_t nt = size_t(s->d.nt);
+    AdjBuf a{};
+    carve_adj(s->d, R, T, static_cast<char *>(ws), &a);
+    Buffers &b = s->b;
+    hipError_t e = launch_fill_f64(a.acc, 0.0, 2 * s->d.nbox, hs);
+    double *const lo_x[3] = {a.lo, a.lo + nt, a.lo + 2 * nt};
+    double *const lo_v[3] = {a.lo + 3 * nt, a.lo + 4 * nt, a.lo + 5 * nt};
+    Pos wa = a.wa, wb = a.wb;
+    auto hvp = [&](const Pos &x, double mult, bool drift_adj) {
+        if (e == hipSuccess)
+            e = launch_hvp(s->d, b, x, wa, a.lx, wb, mult, drift_adj, a.partials, hs);
+        if (e == hipSuccess)
+            e = launch_grad_reduce(s->d, b, a.partials, mult, a.acc, hs);
+        if (drift_adj)
+            std::swap(wa, wb);
+    };
+    // the system holds x_T with the list of force evaluation T
+    if (e == hipSuccess)
+        e = launch_gather(s->d, lam_x, b.orig[s->cur.o], a.lx, hs);
+    if (e == hipSuccess)
+        e = launch_gather(s->d, (lam_v && lam_v[0] && lam_v[1] && lam_v[2]) ? lam_v : nullptr, b.orig[s->cur.o], wa,
+                          hs);
+    hvp(b.pos(s->cur.x), 1.0, true);
+    if (e == hipSuccess)
+        e = launch_unload(s->d, a.lx.x, a.lx.y, a.lx.z, b.orig[s->cur.o], lo_x, hs);
+    if (e == hipSuccess)
+        e = launch_unload(s->d, wa.x, wa.y, wa.z, b.orig[s->cur.o], lo_v, hs);
+    for (int32_t m = nseg - 1; m >= 0 && e == hipSuccess; --m) {
+        const int32_t k_lo = m * R, k_hi = std::min((m + 1) * R, T) - 1;
+        // restore the checkpoint, rebuild the same list, recompute positions
+        const double *c = a.ckpt + size_t(m) * 6 * nt;
+        const double *const po[3] = {c, c + nt, c + 2 * nt};
+        const double *const vo[3] = {c + 3 * nt, c + 4 * nt, c + 5 * nt};
+        e = launch_load_state(s->d, po, vo, b, Cursor{}, hs);
+        s->cur = Cursor{};
+        if (e == hipSuccess && (st = rebuild(s, hs)) != TMD_OK)
+            return st;
+        const size_t np = size_t(s->d.ntp);
+        auto traj = [&](int32_t j) {
+            if (j == 0)
+                return b.pos(s->cur.x);
+            double *t = a.traj + size_t(j) * 3 * np;
+            return Pos{t, t + np, t + 2 * np};
+        };
+        const int o = s->cur.o;
+        if (k_hi > k_lo) {
+            if (e == hipSuccess)
+                e = launch_force_at(s->d, b, traj(0), traj(0), o, 0, false, hs);
+            if (e == hipSuccess)
+                e = launch_drift_at(s->d, b, traj(0), traj(1), o, hs);
+            for (int32_t j = 1; j < k_hi - k_lo && e == hipSuccess; ++j)
+                e = launch_force_at(s->d, b, traj(j), traj(j + 1), o, 2, false, hs);
+        }
+        if (e == hipSuccess)
+            e = launch_gather(s->d, lo_x, b.orig[o], a.lx, hs);
+        if (e == hipSuccess)
+            e = launch_gather(s->d, lo_v, b.orig[o], wa, hs);
+        for (int32_t k = k_hi; k >= k_lo; --k)
+            hvp(traj(k - k_lo), k == 0 ? 1.0 : 2.0, k > 0);
+        double *const *ox = (m == 0) ? grad_x0 : lo_x;
+        if (e == hipSuccess)
+            e = launch_unload(s->d, a.lx.x, a.lx.y, a.lx.z, b.orig[o], ox, hs);
+        if (m > 0) {
+            if (e == hipSuccess)
+                e = launch_unload(s->d, wa.x, wa.y, wa.z, b.orig[o], lo_v, hs);
+        } else if (grad_v0 && grad_v0[0] && grad_v0[1] && grad_v0[2]) {
+            if (e == hipSuccess)
+                e = launch_unload(s->d, wa.x, wa.y, wa.z, b.orig[o], grad_v0, hs);
+        }
+    }
+    if (e == hipSuccess && (grad_eps || grad_sigma))
+        e = launch_split_pairs(a.acc, s->d.nbox, grad_eps, grad_sigma, hs);
+    // leave the system in the recorded final state
+    if (e == hipSuccess) {
+        const double *c = a.ckpt + size_t(nseg) * 6 * nt;
+        const double *const po[3] = {c, c + nt, c + 2 * nt};
+        const double *const vo[3] = {c + 3 * nt, c + 4 * nt, c + 5 * nt};
+        e = launch_load_state(s->d, po, vo, b, Cursor{}, hs);
+    }
+    if (e != hipSuccess)
+        return hip_fail(s, e, "adjoint_backward");
+    s->cur = Cursor{};
+    s->list_valid = s->force_valid = false;
+    s->step = s->adj.step0 + T;
+    s->adj.gen = ++s->gen;  // a second backward over the same run stays valid
+    return TMD_OK;
 }
 
 tmd_status tmd_set_timing(tmd_system *s, int32_t enable) {

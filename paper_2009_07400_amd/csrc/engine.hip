@@ -749,6 +749,175 @@ __global__ __launch_bounds__(kMaxThreads) void k_export_neighbors(Dims d, const 
     }
 }
 
+// ------------------------------------------------------------------ adjoint
+
+// Neighborhood staged with positions and one vector field w: 48 bytes per
+// LDS slot (x, y, z, wx, wy, wz); the sentinel slot has NaN positions.
+__device__ __forceinline__ lds_double *lds_slot6(lds_double *base, int slot) {
+    return (lds_double *)((lds_char *)base + __umul24(unsigned(slot), 48u));
+}
+
+__device__ __forceinline__ void hood_stage6(const Hood &h, int total, const Pos &x, const Pos &w, lds_double *s) {
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int u = hood_find(h, t);
+        const int g = h.cs[u] + (t - h.off[u]);
+        lds_double *a = lds_slot6(s, t);
+        a[0] = x.x[g];
+        a[1] = x.y[g];
+        a[2] = x.z[g];
+        a[3] = w.x[g];
+        a[4] = w.y[g];
+        a[5] = w.z[g];
+    }
+    if (threadIdx.x == 0) {
+        lds_double *a = lds_slot6(s, total);
+        a[0] = a[1] = a[2] = __builtin_nan("");
+        a[3] = a[4] = a[5] = 0.0;
+    }
+    __syncthreads();
+}
+
+// Reverse-mode step at one force evaluation of the velocity-Verlet map,
+// with the list and the cutoff indicators of the forward run held fixed.
+// For w = lam_v (one lane per atom, one workgroup per block):
+//   (J w)_i = sum_{j in list(i), s < rc^2} [ f(s) (w_i - w_j) + 2 f'(s) ((w_i - w_j) . d_ij) d_ij ]
+// with f' = df/ds = sr2^2 sr6 (96 eps - 336 eps sr6);  lam_x_i += c (J w)_i,
+// c = mult * dt / (2 m).  The block's partial sums of w_i . dF_i/deps
+// (df/deps = f / eps) and w_i . dF_i/dsigma (df/dsigma = (eps / sigma) sr2
+// sr6 (576 sr6 - 144)) go to `partials`.  With drift_adj the adjoint of the
+// drift before this force evaluation follows: wout_i = w_i + dt lam_x_i.
+__global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restrict__ boxes,
+                                                     const int32_t *__restrict__ blk_box, Pos x,
+                                                     const int32_t *__restrict__ cell_start,
+                                                     const int32_t *__restrict__ cnt,
+                                                     const int32_t *__restrict__ nbr, Pos w, Pos lam, Pos wout,
+                                                     double mult, int drift_adj, double *__restrict__ partials) {
+    __shared__ Hood h;
+    extern __shared__ double lds[];
+    const int b = xcd_remap();
+    if (b >= d.nblk)
+        return;
+    const Box B = boxes[blk_box[b]];
+    hood_setup(B, b - B.block_off, cell_start, h);
+    const int total = h.off[h.ncell];
+    const bool fits = total <= d.cap;
+    lds_double *S = (lds_double *)lds;
+    if (fits)
+        hood_stage6(h, total, x, w, S);
+    const int sentinel = fits ? total : d.nt;
+    double pe = 0.0, ps = 0.0, unused = 0.0;
+    for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
+        const double xi = x.x[i], yi = x.y[i], zi = x.z[i];
+        const double wxi = w.x[i], wyi = w.y[i], wzi = w.z[i];
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        const int c = cnt[i];
+        const int32_t *nb = nbr;
+        for (int k = 0; k < c; ++k) {
+            const int j = nb[nbr_index(i, k, d.nchunk)];
+            double xj, yj, zj, wxj, wyj, wzj;
+            if (fits) {
+                const lds_double *a = lds_slot6(S, j);
+                xj = a[0];
+                yj = a[1];
+                zj = a[2];
+                wxj = a[3];
+                wyj = a[4];
+                wzj = a[5];
+            } else {
+                xj = x.x[j];
+                yj = x.y[j];
+                zj = x.z[j];
+                wxj = w.x[j];
+                wyj = w.y[j];
+                wzj = w.z[j];
+            }
+            double dx, dy, dz;
+            const double s = pair_delta(xi, yi, zi, xj, yj, zj, B.L, B.halfL, B.halfL2, dx, dy, dz);
+            if (s < B.rc2) {
+                const double sr2 = recip_exact(s);
+                const double sr6 = sr2 * sr2 * sr2 * B.sigma6;
+                const double q = sr2 * sr6;
+                const double fe = q * (48.0 * sr6 - 24.0);  // f / eps
+                const double f = B.eps * fe;
+                const double fp = sr2 * q * B.eps * (96.0 - 336.0 * sr6);
+                const double ux = wxi - wxj, uy = wyi - wyj, uz = wzi - wzj;
+                const double t2 = 2.0 * fp * (dx * ux + dy * uy + dz * uz);
+                gx += f * ux + t2 * dx;
+                gy += f * uy + t2 * dy;
+                gz += f * uz + t2 * dz;
+                const double wd = wxi * dx + wyi * dy + wzi * dz;
+                pe += fe * wd;
+                ps += B.eps_over_sigma * q * (576.0 * sr6 - 144.0) * wd;
+            }
+        }
+        (void)sentinel;
+        const double cc = mult * B.h;
+        const double lx = lam.x[i] + cc * gx, ly = lam.y[i] + cc * gy, lz = lam.z[i] + cc * gz;
+        lam.x[i] = lx;
+        lam.y[i] = ly;
+        lam.z[i] = lz;
+        if (drift_adj) {
+            wout.x[i] = wxi + B.dt * lx;
+            wout.y[i] = wyi + B.dt * ly;
+            wout.z[i] = wzi + B.dt * lz;
+        }
+    }
+    block_sum3(pe, ps, unused);
+    if (threadIdx.x == 0) {
+        partials[b * kPartialStride + 0] = pe;
+        partials[b * kPartialStride + 1] = ps;
+    }
+}
+
+// acc[2 box + q] += mult * h * (sum over the box's blocks of partial q), one
+// wavefront per box, fixed order.
+__global__ __launch_bounds__(64) void k_grad_reduce(const Box *__restrict__ boxes,
+                                                    const double *__restrict__ partials, double mult,
+                                                    double *acc) {
+    const Box &B = boxes[blockIdx.x];
+    double e = 0.0, s = 0.0;
+    for (int q = threadIdx.x; q < B.nblocks; q += 64) {
+        const int blk = B.block_off + q;
+        e += partials[blk * kPartialStride + 0];
+        s += partials[blk * kPartialStride + 1];
+    }
+    e = wave_sum(e);
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+        acc[2 * blockIdx.x] += mult * B.h * e;
+        acc[2 * blockIdx.x + 1] += mult * B.h * s;
+    }
+}
+
+__global__ __launch_bounds__(kAtomThreads) void k_gather(int n, const double *__restrict__ s0,
+                                                         const double *__restrict__ s1,
+                                                         const double *__restrict__ s2,
+                                                         const int32_t *__restrict__ orig, Pos dst) {
+    const int p = blockIdx.x * kAtomThreads + threadIdx.x;
+    if (p >= n)
+        return;
+    const int o = orig[p];
+    dst.x[p] = s0 ? s0[o] : 0.0;
+    dst.y[p] = s1 ? s1[o] : 0.0;
+    dst.z[p] = s2 ? s2[o] : 0.0;
+}
+
+__global__ void k_fill_f64(double *p, double v, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+__global__ void k_split_pairs(const double *__restrict__ acc, int n, double *a, double *b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        if (a)
+            a[i] = acc[2 * i];
+        if (b)
+            b[i] = acc[2 * i + 1];
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -769,7 +938,41 @@ hipError_t prepare_kernels(const Dims &d) {
         if (e != hipSuccess)
             return e;
     }
-    return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hvp), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               2 * bytes);
+}
+
+hipError_t launch_gather(const Dims &d, const double *const src[3], const int32_t *orig, const Pos &dst,
+                         hipStream_t s) {
+    k_gather<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, src ? src[0] : nullptr, src ? src[1] : nullptr,
+                                                         src ? src[2] : nullptr, orig, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_hvp(const Dims &d, Buffers &b, const Pos &x, const Pos &w, const Pos &lam_x, const Pos &wout,
+                      double mult, bool drift_adj, double *partials, hipStream_t s) {
+    k_hvp<<<block_grid(d.nblk), d.threads, 2 * hood_lds_bytes(d.cap), s>>>(
+        d, b.boxes, b.blk_box, x, b.cell_start, b.nbr_count, b.nbr, w, lam_x, wout, mult, drift_adj ? 1 : 0,
+        partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const Dims &d, const Buffers &b, const double *partials, double mult, double *acc,
+                              hipStream_t s) {
+    k_grad_reduce<<<d.nbox, 64, 0, s>>>(b.boxes, partials, mult, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
+    if (n <= 0)
+        return hipSuccess;
+    k_fill_f64<<<int((n + 255) / 256), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_pairs(const double *acc, int n, double *a, double *b, hipStream_t s) {
+    k_split_pairs<<<(n + 63) / 64, 64, 0, s>>>(acc, n, a, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
@@ -820,32 +1023,38 @@ hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
 }
 
 template <int MODE, bool THERMO>
-static void force_variant(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
-    const int xc = c.x, xn = 1 - c.x;
+static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
     k_force<MODE, THERMO><<<block_grid(d.nblk), d.threads, hood_lds_bytes(d.cap), s>>>(
-        d, b.boxes, b.blk_box, b.x[xc], b.y[xc], b.z[xc], b.cell_start, b.nbr_count, b.nbr, b.vx[c.o], b.vy[c.o],
-        b.vz[c.o], b.fx, b.fy, b.fz, b.x[xn], b.y[xn], b.z[xn], b.partials, b.err);
+        d, b.boxes, b.blk_box, in.x, in.y, in.z, b.cell_start, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
+        b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
 }
 
-hipError_t launch_force(const Dims &d, Buffers &b, Cursor c, int mode, bool thermo, hipStream_t s) {
+hipError_t launch_force_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, int mode, bool thermo,
+                           hipStream_t s) {
     switch (mode * 2 + (thermo ? 1 : 0)) {
-    case 0: force_variant<0, false>(d, b, c, s); break;
-    case 1: force_variant<0, true>(d, b, c, s); break;
-    case 2: force_variant<1, false>(d, b, c, s); break;
-    case 3: force_variant<1, true>(d, b, c, s); break;
-    case 4: force_variant<2, false>(d, b, c, s); break;
-    case 5: force_variant<2, true>(d, b, c, s); break;
+    case 0: force_variant<0, false>(d, b, in, out, o, s); break;
+    case 1: force_variant<0, true>(d, b, in, out, o, s); break;
+    case 2: force_variant<1, false>(d, b, in, out, o, s); break;
+    case 3: force_variant<1, true>(d, b, in, out, o, s); break;
+    case 4: force_variant<2, false>(d, b, in, out, o, s); break;
+    case 5: force_variant<2, true>(d, b, in, out, o, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_drift(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
-    const int xc = c.x, xn = 1 - c.x;
-    k_drift<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, b.x[xc], b.y[xc], b.z[xc], b.vx[c.o],
-                                                        b.vy[c.o], b.vz[c.o], b.fx, b.fy, b.fz, b.x[xn], b.y[xn],
-                                                        b.z[xn], b.err);
+hipError_t launch_force(const Dims &d, Buffers &b, Cursor c, int mode, bool thermo, hipStream_t s) {
+    return launch_force_at(d, b, b.pos(c.x), b.pos(1 - c.x), c.o, mode, thermo, s);
+}
+
+hipError_t launch_drift_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
+    k_drift<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, in.x, in.y, in.z, b.vx[o], b.vy[o],
+                                                        b.vz[o], b.fx, b.fy, b.fz, out.x, out.y, out.z, b.err);
     return hipGetLastError();
+}
+
+hipError_t launch_drift(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
+    return launch_drift_at(d, b, b.pos(c.x), b.pos(1 - c.x), c.o, s);
 }
 
 hipError_t launch_reduce(const Dims &d, const Buffers &b, double *out, int row_len, hipStream_t s) {

@@ -34,6 +34,7 @@ struct Box {
     double eps, sigma6;      // LJ parameters
     double eps48, eps24;     // 48 eps and 24 eps: f = sr2 sr6 (48 eps sr6 - 24 eps)
     double eps4;             // 4 eps: pair energy sr6 (4 eps sr6 - 4 eps)
+    double eps_over_sigma;   // d f / d sigma = (eps / sigma) sr2 sr6 (576 sr6 - 144)
     double h, dt, mass;      // half kick dt / (2 m), time step, mass
 };
 
@@ -60,8 +61,14 @@ __host__ __device__ inline int64_t nbr_index(int i, int k, int nchunk) {
     return ((int64_t((i >> 6)) * nchunk + (k >> 2)) * 64 + (i & 63)) * 4 + (k & 3);
 }
 
+// Three SoA coordinate arrays.
+struct Pos {
+    double *x, *y, *z;
+};
+
 // Device pointers carved from the caller's workspace.
 struct Buffers {
+    Pos pos(int k) const { return Pos{x[k], y[k], z[k]}; }
     double *x[2], *y[2], *z[2];
     double *vx[2], *vy[2], *vz[2];
     int32_t *orig[2];
@@ -106,6 +113,28 @@ hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s);
 // 2: F + kick + kick + drift into positions 1 - c.x
 hipError_t launch_force(const Dims &d, Buffers &b, Cursor c, int mode, bool thermo, hipStream_t s);
 hipError_t launch_drift(const Dims &d, Buffers &b, Cursor c, hipStream_t s);  // positions into 1 - c.x
+// The same with explicit position arrays (in: current, out: drifted) and
+// velocity half o; used to recompute a trajectory segment into storage.
+hipError_t launch_force_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, int mode, bool thermo,
+                           hipStream_t s);
+hipError_t launch_drift_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s);
+
+// Adjoint support.
+// Gather a vector field from original order into the current sorted order
+// (dst[p] = src[orig[p]]) or scatter it back (launch_unload does that).
+hipError_t launch_gather(const Dims &d, const double *const src[3], const int32_t *orig, const Pos &dst,
+                         hipStream_t s);
+// One reverse step at force point x: lam_x += c J(x) w with c = mult * h
+// (per box), w = lam_v; per-block partials of w . dF/deps and w . dF/dsigma;
+// with drift_adj, wout = w + dt lam_x (the adjoint of the preceding drift).
+hipError_t launch_hvp(const Dims &d, Buffers &b, const Pos &x, const Pos &w, const Pos &lam_x, const Pos &wout,
+                      double mult, bool drift_adj, double *partials, hipStream_t s);
+// acc[2 box + {0, 1}] += mult * h_box * (sum of the box's partials), in a fixed order.
+hipError_t launch_grad_reduce(const Dims &d, const Buffers &b, const double *partials, double mult, double *acc,
+                              hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+// a[i] = acc[2 i], b[i] = acc[2 i + 1] for i < n (either output nullable).
+hipError_t launch_split_pairs(const double *acc, int n, double *a, double *b, hipStream_t s);
 // Per-box deterministic sums of the block partials: rows of (U, W) when
 // row_len == 2, (KE, T, U, W, E) when row_len == 5; out holds nbox rows.
 hipError_t launch_reduce(const Dims &d, const Buffers &b, double *out, int row_len, hipStream_t s);

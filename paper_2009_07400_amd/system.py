@@ -151,6 +151,38 @@ class System:
         abi.tmd_autotune(self._h, repeats, _stream())
         return self.info()["block_threads"]
 
+    def set_lj_params(self, epsilon, sigma) -> None:
+        """Per-box epsilon and sigma (sequences of n_boxes floats, or scalars)."""
+        eps = [float(epsilon)] * self.nbox if isinstance(epsilon, (int, float)) else [float(v) for v in epsilon]
+        sig = [float(sigma)] * self.nbox if isinstance(sigma, (int, float)) else [float(v) for v in sigma]
+        abi.tmd_set_lj_params(self._h, eps, sig, _stream())
+        for p, e, s in zip(self.params, eps, sig):
+            p.epsilon, p.sigma = e, s
+
+    def adjoint_forward(self, n_steps: int) -> None:
+        """Integrate n_steps, recording checkpoints for adjoint_backward()."""
+        nbytes = abi.tmd_adjoint_workspace_size(self._h, int(n_steps))
+        if getattr(self, "_adj_ws", None) is None or self._adj_ws.numel() < nbytes + 256:
+            self._adj_ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self._adj_ptr = int(self._adj_ws.data_ptr()) + (-int(self._adj_ws.data_ptr())) % 256
+        self._adj_bytes = nbytes
+        abi.tmd_adjoint_forward(self._h, int(n_steps), self._adj_ptr, nbytes, _stream())
+
+    def adjoint_backward(self, lam_x, lam_v=None):
+        """Cotangents of the final (x, v) -> (dL/dx0 [N,3], dL/dv0 [N,3],
+        dL/deps [n_boxes], dL/dsigma [n_boxes])."""
+        lx = _soa(lam_x, self.n, self.device)
+        lv = _soa(lam_v, self.n, self.device) if lam_v is not None else None
+        gx = torch.empty(3, self.n, dtype=torch.float64, device=self.device)
+        gv = torch.empty(3, self.n, dtype=torch.float64, device=self.device)
+        ge = torch.empty(self.nbox, dtype=torch.float64, device=self.device)
+        gs = torch.empty(self.nbox, dtype=torch.float64, device=self.device)
+        abi.tmd_adjoint_backward(self._h, self._adj_ptr, self._adj_bytes, _ptrs(lx),
+                                 _ptrs(lv) if lv is not None else None, _ptrs(gx), _ptrs(gv), int(ge.data_ptr()),
+                                 int(gs.data_ptr()), _stream())
+        self._keep = [lx, lv]
+        return gx.t(), gv.t(), ge, gs
+
     def set_timing(self, enable: bool) -> None:
         abi.tmd_set_timing(self._h, enable)
 
