@@ -78,9 +78,11 @@ typedef struct {
     size_t workspace_bytes;
     int64_t step;            /* time-step counter of the current state */
     int32_t n_boxes;
-    int32_t n_blocks;        /* blocks of 2x2x2 cells, one workgroup each */
+    int32_t n_blocks;        /* blocks of cells, one workgroup each */
     int32_t block_threads;   /* threads per block workgroup */
     int32_t lds_atoms;       /* atoms of a block neighborhood staged in LDS */
+    int32_t block_edge;      /* cells per block edge (2 or 3) */
+    int32_t reserved_;
 } tmd_info;
 
 /* Kernel classes reported by tmd_get_timing(). */
@@ -184,20 +186,28 @@ tmd_status tmd_sync(tmd_system *sys, tmd_stream stream);
 /* Host-side facts about the system. */
 tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
 
-/* Work schedule of the block kernels; neither value changes any result.
- * threads: threads per block workgroup, a multiple of 64 in [64, 256] (0
+/* Work schedule of the block kernels; no value changes any result.
+ * block_edge: cells per edge of the blocks of cells that one workgroup owns
+ * and whose neighborhood it stages in LDS, 2 or 3 (0 keeps the current
+ * value; a new edge resets the other two to that edge's defaults).
+ * threads: threads per block workgroup, a multiple of 64 in [64, 1024] (0
  * keeps the current value).  lds_atoms: how many atoms of a block's
- * neighborhood may be staged in LDS, a multiple of 64 in [64, 2560] (0 keeps
- * the current value); blocks whose neighborhood holds more atoms gather from
- * global memory instead.  Changing lds_atoms marks the list stale (the next
- * integrate rebuilds it; compute_forces needs tmd_build_neighbors first).
- * TMD_EINVAL for other values. */
-tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms);
+ * neighborhood may be staged in LDS, a multiple of 64 in [64, 4096] (0 keeps
+ * the current value; lowered at the next state upload if the device's
+ * per-workgroup LDS cannot hold twice that many 24-byte slots); blocks whose
+ * neighborhood holds more atoms gather from global memory instead.  A new
+ * edge or capacity marks the list stale (the next integrate rebuilds it;
+ * compute_forces needs tmd_build_neighbors first).  TMD_EINVAL for other
+ * values. */
+tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms, int32_t block_edge);
 
-/* Pick the block_threads value with the shortest force-kernel time for the
- * current state: times `repeats` force evaluations per candidate on `stream`
- * with HIP events (synchronises; positions and velocities are not changed;
- * builds the list first if none is valid). */
+/* Pick the schedule (block edge 2 or 3, threads per block workgroup) with the
+ * shortest force-kernel time for the current positions: times `repeats`
+ * force evaluations per candidate on `stream` with HIP events
+ * (synchronises).  Positions and velocities are not changed, but the list is
+ * rebuilt at the current positions, as by tmd_build_neighbors(); call it
+ * right after tmd_set_state() or at a rebuild step to keep the fixed
+ * rebuild schedule. */
 tmd_status tmd_autotune(tmd_system *sys, int32_t repeats, tmd_stream stream);
 
 /* Replace epsilon and sigma of every box (host arrays of n_boxes values, each

@@ -21,6 +21,8 @@ struct tmd_system {
     std::vector<Box> boxes;  // host copy of the descriptors
     std::vector<int32_t> blk_box, atom_box;
     Dims d{};
+    Dims dmax{};               // sizes the workspace for either block edge
+    bool tables_dirty = true;  // box / block tables changed since the last upload
     int32_t rebuild_every = 20;
     size_t ws_need = 0;
     Buffers b{};
@@ -53,7 +55,9 @@ struct tmd_system {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxCap = 2560;  // atoms staged per block neighborhood: 60 KB of LDS
+constexpr int kMaxCap = 4096;       // atoms staged per block neighborhood (96 KB of LDS at most)
+constexpr int kLdsPerCu = 163840;   // gfx950: 160 KB of LDS per compute unit
+constexpr int kStaticLds = 1536;    // static LDS of a block kernel (neighborhood tables, reductions), rounded up
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -154,7 +158,14 @@ tmd_status check_ready(tmd_system *s, bool need_state) {
     return TMD_OK;
 }
 
+tmd_status upload_tables(tmd_system *s, hipStream_t hs);
+
 tmd_status rebuild(tmd_system *s, hipStream_t st) {
+    if (s->tables_dirty || !s->prepared) {
+        const tmd_status u = upload_tables(s, st);
+        if (u != TMD_OK)
+            return u;
+    }
     hipError_t e;
     {
         Timed t(s, TMD_T_BINNING, st);
@@ -176,11 +187,85 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
     return TMD_OK;
 }
 
-// Expected atoms in a block neighborhood (4 cells per axis, or the whole
+// LJ 12-6 constants of one box (Sec. 3.2, Eq. 2) in the forms the kernels use.
+void set_lj(Box &B, double eps, double sigma) {
+    const double s2 = sigma * sigma;
+    B.eps = eps;
+    B.sigma6 = s2 * s2 * s2;
+    B.eps48 = 48.0 * eps;
+    B.eps24 = 24.0 * eps;
+    B.eps4 = 4.0 * eps;
+    B.eps_over_sigma = eps / sigma;
+    B.f12 = B.eps48 * B.sigma6 * B.sigma6;
+    B.f6 = B.eps24 * B.sigma6;
+    B.u12 = B.eps4 * B.sigma6 * B.sigma6;
+    B.u6 = B.eps4 * B.sigma6;
+}
+
+// Expected atoms in a block neighborhood (E + 2 cells per axis, or the whole
 // box when it has fewer cells), for sizing the LDS staging area.
-double expected_hood_atoms(const Box &B) {
-    const double f = double(std::min(B.nc, 4)) / B.nc;
+double expected_hood_atoms(const Box &B, int E) {
+    const double f = double(std::min(B.nc, E + 2)) / B.nc;
     return B.n * f * f * f;
+}
+
+// Cut every box into blocks of E x E x E cells and size the schedule for
+// it: the LDS capacity is the largest per-workgroup share of a CU's LDS that
+// still holds at least 15% more atoms than the largest mean neighborhood
+// population (liquid density fluctuations over ~1000 atoms are a few
+// percent; rarer blocks fall back to global gathers), threads ~15% above the
+// mean block population.  Returns false when the cell slots overflow int32.
+bool layout_blocks(tmd_system *s, int E) {
+    int64_t blocks = 0;
+    double worst = 0.0;
+    for (Box &B : s->boxes) {
+        B.edge = E;
+        B.nbx = (B.nc + E - 1) / E;
+        B.nblocks = B.nbx * B.nbx * B.nbx;
+        B.block_off = int32_t(blocks);
+        B.cell_off = int32_t(blocks * E * E * E);
+        blocks += B.nblocks;
+        worst = std::max(worst, expected_hood_atoms(B, E));
+        if (blocks * E * E * E > INT32_MAX / 2)
+            return false;
+    }
+    Dims &d = s->d;
+    d.edge = E;
+    d.cpb = E * E * E;
+    d.nblk = int32_t(blocks);
+    d.ncs = int32_t(blocks * d.cpb);
+    // Most workgroups per CU (gfx950: 160 KB of LDS per CU) whose share of
+    // LDS still stages at least 15% more atoms than the largest mean
+    // neighborhood; the capacity then takes that whole share.
+    const int need = int(1.15 * worst) + 32;
+    d.cap = std::min(kMaxCap, round_up(int(1.3 * worst) + 64, 64));
+    for (int wg = 8; wg >= 1; --wg) {
+        const int c = ((kLdsPerCu / wg - kStaticLds) / 24 - 1) / 64 * 64;
+        if (c >= need) {
+            d.cap = std::min(kMaxCap, c);
+            break;
+        }
+    }
+    const double per_block = double(d.nt) / double(blocks);
+    d.threads = std::min(kMaxThreads, std::max(64, round_up(int(per_block * 1.15), 64)));
+    s->blk_box.assign(size_t(blocks), 0);
+    for (int32_t k = 0; k < d.nbox; ++k) {
+        const Box &B = s->boxes[size_t(k)];
+        std::fill(s->blk_box.begin() + B.block_off, s->blk_box.begin() + B.block_off + B.nblocks, k);
+    }
+    s->tables_dirty = true;
+    s->prepared = false;
+    return true;
+}
+
+// Default block edge: 3 when that still gives every CU several blocks.
+int default_edge(tmd_system *s) {
+    int64_t b3 = 0;
+    for (const Box &B : s->boxes) {
+        const int64_t n = (B.nc + 2) / 3;
+        b3 += n * n * n;
+    }
+    return b3 >= 4 * 256 ? 3 : 2;
 }
 
 tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengths, const tmd_params *params,
@@ -190,8 +275,7 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
     *out = nullptr;
     if (nbox < 1 || !n_atoms || !lengths || !params)
         return TMD_EINVAL;
-    int64_t total = 0, blocks = 0;
-    double worst_hood = 0.0;
+    int64_t total = 0;
     std::vector<Box> boxes;
     try {
         boxes.resize(size_t(nbox));
@@ -221,31 +305,19 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
         B.atom_off = int32_t(total);
         B.n = int32_t(n);
         B.nc = int32_t(ncd);  // >= 2 because r < L/2
-        B.nbx = (B.nc + 1) / 2;
-        B.nblocks = B.nbx * B.nbx * B.nbx;
-        B.block_off = int32_t(blocks);
-        B.cell_off = int32_t(blocks * 8);
         B.L = L;
         B.halfL = 0.5 * L;
         B.halfL2 = B.halfL * B.halfL;
         B.side = L / B.nc;
         B.rc2 = p.cutoff * p.cutoff;
         B.rl2 = r * r;
-        B.eps = p.epsilon;
-        B.eps48 = 48.0 * p.epsilon;
-        B.eps24 = 24.0 * p.epsilon;
-        B.eps4 = 4.0 * p.epsilon;
-        B.eps_over_sigma = p.epsilon / p.sigma;
-        const double s2 = p.sigma * p.sigma;
-        B.sigma6 = s2 * s2 * s2;
+        set_lj(B, p.epsilon, p.sigma);
         B.h = 0.5 * p.dt / p.mass;
         B.dt = p.dt;
         B.mass = p.mass;
         total += n;
-        blocks += B.nblocks;
-        if (total > INT32_MAX - 256 || blocks * 8 > INT32_MAX / 2)
+        if (total > INT32_MAX - 256)
             return TMD_EINVAL;
-        worst_hood = std::max(worst_hood, expected_hood_atoms(B));
     }
     tmd_system *s = new (std::nothrow) tmd_system();
     if (!s)
@@ -257,28 +329,34 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
         d.nt = int32_t(total);
         d.ntp = round_up(d.nt + 1, 256);  // slot nt holds the NaN sentinel atom
         d.nbox = nbox;
-        d.nblk = int32_t(blocks);
-        d.ncs = int32_t(blocks * 8);
         d.maxnb = params[0].max_neighbors;
         d.nchunk = (d.maxnb + 3) / 4;
-        // 30% above the mean neighborhood population: liquid density
-        // fluctuations over ~1000 atoms are a few percent; rarer blocks fall
-        // back to global gathers
-        d.cap = std::min(kMaxCap, round_up(int(1.3 * worst_hood) + 64, 64));
-        const double per_block = double(total) / double(blocks);
-        d.threads = std::min(kMaxThreads, std::max(64, round_up(int(per_block * 1.15), 64)));
         if (int64_t(d.ntp) * d.maxnb > (int64_t(1) << 40)) {
             delete s;
             return TMD_EINVAL;
         }
-        s->blk_box.resize(size_t(blocks));
         s->atom_box.resize(size_t(d.ntp), nbox - 1);
         for (int32_t k = 0; k < nbox; ++k) {
             const Box &B = boxes[size_t(k)];
-            std::fill(s->blk_box.begin() + B.block_off, s->blk_box.begin() + B.block_off + B.nblocks, k);
             std::fill(s->atom_box.begin() + B.atom_off, s->atom_box.begin() + B.atom_off + B.n, k);
         }
-        s->ws_need = carve(d, nullptr, nullptr);
+        // the workspace holds the tables of either block edge
+        if (!layout_blocks(s, 3)) {
+            delete s;
+            return TMD_EINVAL;
+        }
+        Dims big = d;
+        if (!layout_blocks(s, 2)) {
+            delete s;
+            return TMD_EINVAL;
+        }
+        big.nblk = std::max(big.nblk, d.nblk);
+        big.ncs = std::max(big.ncs, d.ncs);
+        s->dmax = big;
+        const int E = default_edge(s);
+        if (E != 2)
+            layout_blocks(s, E);
+        s->ws_need = carve(s->dmax, nullptr, nullptr);
     } catch (...) {
         delete s;
         return TMD_EINVAL;
@@ -333,6 +411,8 @@ tmd_status upload_tables(tmd_system *s, hipStream_t hs) {
         e = hipMemcpyAsync(s->b.blk_box, s->blk_box.data(), s->blk_box.size() * 4, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->b.atom_box, s->atom_box.data(), s->atom_box.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        s->tables_dirty = false;
     if (e == hipSuccess && !s->prepared) {
         // the adjoint kernel stages 48 bytes per atom: keep within the
         // device's per-workgroup LDS limit (static LDS needs < 1 KB)
@@ -393,7 +473,8 @@ tmd_status tmd_bind_workspace(tmd_system *s, void *dev, size_t bytes) {
         return TMD_EINVAL;
     if (bytes < s->ws_need || (reinterpret_cast<uintptr_t>(dev) % kAlign) != 0)
         return fail(s, TMD_EWORKSPACE, "workspace must be 256-byte aligned and at least tmd_workspace_size bytes");
-    carve(s->d, static_cast<char *>(dev), &s->b);
+    carve(s->dmax, static_cast<char *>(dev), &s->b);
+    s->tables_dirty = true;
     s->bound = true;
     s->gen++;
     s->have_state = s->list_valid = s->force_valid = false;
@@ -601,29 +682,47 @@ tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
     info->n_blocks = s->d.nblk;
     info->block_threads = s->d.threads;
     info->lds_atoms = s->d.cap;
+    info->block_edge = s->d.edge;
+    info->reserved_ = 0;
     return TMD_OK;
 }
 
-tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms) {
+tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, int32_t block_edge) {
     if (!s || threads < 0 || threads > kMaxThreads || threads % 64 != 0 || lds_atoms < 0 || lds_atoms > kMaxCap ||
-        lds_atoms % 64 != 0)
+        lds_atoms % 64 != 0 || (block_edge != 0 && block_edge != 2 && block_edge != 3))
         return TMD_EINVAL;
+    if (block_edge != 0 && block_edge != s->d.edge) {
+        layout_blocks(s, block_edge);  // resets threads and capacity to that edge's defaults
+        s->list_valid = s->force_valid = false;
+        s->gen++;
+    }
     if (threads > 0)
         s->d.threads = threads;
     if (lds_atoms > 0 && lds_atoms != s->d.cap) {
         s->d.cap = lds_atoms;
         s->prepared = false;  // LDS attribute of the block kernels must follow
-        s->gen++;
         // the list encodes LDS slots only for neighborhoods that fit
         s->list_valid = s->force_valid = false;
-        if (s->bound) {
-            hipError_t e = prepare_kernels(s->d);
-            if (e != hipSuccess)
-                return hip_fail(s, e, "set_schedule");
-            s->prepared = true;
-        }
+        s->gen++;
     }
     return TMD_OK;
+}
+
+// Mean duration (ms) of `repeats` force evaluations on the current list.
+static hipError_t time_force(tmd_system *s, int32_t repeats, hipStream_t hs, hipEvent_t a, hipEvent_t b, float &ms) {
+    hipError_t e = launch_force(s->d, s->b, s->cur, 0, false, hs);  // warm-up; the state is not changed
+    if (e == hipSuccess)
+        e = hipEventRecord(a, hs);
+    for (int32_t r = 0; r < repeats && e == hipSuccess; ++r)
+        e = launch_force(s->d, s->b, s->cur, 0, false, hs);
+    if (e == hipSuccess)
+        e = hipEventRecord(b, hs);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(b);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, a, b);
+    ms /= float(repeats);
+    return e;
 }
 
 tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
@@ -633,41 +732,41 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     if (repeats < 1)
         return fail(s, TMD_EINVAL, "autotune: repeats < 1");
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    if (!s->list_valid && (st = rebuild(s, hs)) != TMD_OK)
-        return st;
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess)
         e = hipEventCreate(&b);
     if (e != hipSuccess)
         return hip_fail(s, e, "autotune");
-    const int32_t saved = s->d.threads;
     float best = 1e30f;
-    int32_t best_t = saved;
-    for (int32_t t = 64; t <= kMaxThreads && e == hipSuccess; t += 64) {
-        s->d.threads = t;
-        e = launch_force(s->d, s->b, s->cur, 0, false, hs);  // warm-up; the state is not changed
-        if (e == hipSuccess)
-            e = hipEventRecord(a, hs);
-        for (int32_t r = 0; r < repeats && e == hipSuccess; ++r)
-            e = launch_force(s->d, s->b, s->cur, 0, false, hs);
-        if (e == hipSuccess)
-            e = hipEventRecord(b, hs);
-        if (e == hipSuccess)
-            e = hipEventSynchronize(b);
-        float ms = 0.0f;
-        if (e == hipSuccess)
-            e = hipEventElapsedTime(&ms, a, b);
-        if (e == hipSuccess && ms < best) {
-            best = ms;
-            best_t = t;
+    int32_t best_edge = s->d.edge, best_t = s->d.threads;
+    for (int32_t E = 2; E <= kMaxEdge && e == hipSuccess; ++E) {
+        layout_blocks(s, E);
+        s->list_valid = s->force_valid = false;
+        if ((st = rebuild(s, hs)) != TMD_OK)
+            break;
+        const int32_t t0 = s->d.threads;
+        for (int32_t t = std::max(64, t0 - 192); t <= std::min(kMaxThreads, t0 + 192) && e == hipSuccess; t += 64) {
+            s->d.threads = t;
+            float ms = 0.0f;
+            e = time_force(s, repeats, hs, a, b, ms);
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                best_edge = E;
+                best_t = t;
+            }
         }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    s->d.threads = (e == hipSuccess) ? best_t : saved;
-    s->force_valid = true;
-    return e == hipSuccess ? TMD_OK : hip_fail(s, e, "autotune");
+    if (st != TMD_OK)
+        return st;
+    if (e != hipSuccess)
+        return hip_fail(s, e, "autotune");
+    layout_blocks(s, best_edge);
+    s->d.threads = best_t;
+    s->list_valid = s->force_valid = false;
+    return rebuild(s, hs);
 }
 
 tmd_status tmd_set_lj_params(tmd_system *s, const double *epsilon, const double *sigma, tmd_stream stream) {
@@ -679,16 +778,8 @@ tmd_status tmd_set_lj_params(tmd_system *s, const double *epsilon, const double 
     for (int32_t k = 0; k < s->d.nbox; ++k)
         if (!positive(epsilon[k]) || !positive(sigma[k]))
             return fail(s, TMD_EINVAL, "set_lj_params: epsilon and sigma must be finite and positive");
-    for (int32_t k = 0; k < s->d.nbox; ++k) {
-        Box &B = s->boxes[size_t(k)];
-        const double e = epsilon[k], s2 = sigma[k] * sigma[k];
-        B.eps = e;
-        B.sigma6 = s2 * s2 * s2;
-        B.eps48 = 48.0 * e;
-        B.eps24 = 24.0 * e;
-        B.eps4 = 4.0 * e;
-        B.eps_over_sigma = e / sigma[k];
-    }
+    for (int32_t k = 0; k < s->d.nbox; ++k)
+        set_lj(s->boxes[size_t(k)], epsilon[k], sigma[k]);
     hipError_t e = hipMemcpyAsync(s->b.boxes, s->boxes.data(), s->boxes.size() * sizeof(Box), hipMemcpyHostToDevice,
                                   static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
@@ -701,7 +792,7 @@ tmd_status tmd_set_lj_params(tmd_system *s, const double *epsilon, const double 
 tmd_status tmd_adjoint_workspace_size(const tmd_system *s, int32_t n_steps, size_t *bytes) {
     if (!s || !bytes || n_steps < 1)
         return TMD_EINVAL;
-    *bytes = carve_adj(s->d, s->rebuild_every, n_steps, nullptr, nullptr);
+    *bytes = carve_adj(s->dmax,s->rebuild_every, n_steps, nullptr, nullptr);
     return TMD_OK;
 }
 
@@ -710,14 +801,14 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
     if (st != TMD_OK)
         return st;
     if (n_steps < 1 || !ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 ||
-        bytes < carve_adj(s->d, s->rebuild_every, n_steps, nullptr, nullptr))
+        bytes < carve_adj(s->dmax,s->rebuild_every, n_steps, nullptr, nullptr))
         return fail(s, TMD_EINVAL, "adjoint_forward: n_steps < 1 or workspace missing, misaligned or too small");
     const int32_t R = s->rebuild_every;
     if (s->step % R != 0)
         return fail(s, TMD_ESTATE, "adjoint_forward: the step counter must be a multiple of rebuild_every");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     AdjBuf a{};
-    carve_adj(s->d, R, n_steps, static_cast<char *>(ws), &a);
+    carve_adj(s->dmax,R, n_steps, static_cast<char *>(ws), &a);
     const int32_t nseg = (n_steps + R - 1) / R;
     const size_t nt = size_t(s->d.nt);
     s->list_valid = s->force_valid = false;  // the run starts from a list built at its first positions
@@ -753,14 +844,14 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
     if (!s->adj.recorded || ws != s->adj.ws || s->gen != s->adj.gen)
         return fail(s, TMD_ESTATE, "adjoint_backward: no forward run recorded in this workspace, or the state "
                                    "changed since");
-    if (bytes < carve_adj(s->d, s->rebuild_every, s->adj.nsteps, nullptr, nullptr) || !lam_x || !lam_x[0] ||
+    if (bytes < carve_adj(s->dmax,s->rebuild_every, s->adj.nsteps, nullptr, nullptr) || !lam_x || !lam_x[0] ||
         !lam_x[1] || !lam_x[2] || !grad_x0 || !grad_x0[0] || !grad_x0[1] || !grad_x0[2])
         return fail(s, TMD_EINVAL, "adjoint_backward: workspace too small or NULL cotangent / gradient array");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const int32_t R = s->rebuild_every, T = s->adj.nsteps, nseg = s->adj.nseg;
     const size_t nt = size_t(s->d.nt);
     AdjBuf a{};
-    carve_adj(s->d, R, T, static_cast<char *>(ws), &a);
+    carve_adj(s->dmax,R, T, static_cast<char *>(ws), &a);
     Buffers &b = s->b;
     hipError_t e = launch_fill_f64(a.acc, 0.0, 2 * s->d.nbox, hs);
     double *const lo_x[3] = {a.lo, a.lo + nt, a.lo + 2 * nt};

@@ -39,13 +39,26 @@ __device__ __forceinline__ int xcd_remap() {
     return (b % kNumXcd) * (nb / kNumXcd) + b / kNumXcd;
 }
 
-__device__ __forceinline__ int cell_slot(const Box &B, int cx, int cy, int cz) {
-    const int blk = ((cz >> 1) * B.nbx + (cy >> 1)) * B.nbx + (cx >> 1);
-    return B.cell_off + blk * 8 + (((cz & 1) * 2 + (cy & 1)) * 2 + (cx & 1));
+// Block coordinate and offset inside the block of cell coordinate c.
+__device__ __forceinline__ void split_edge(int c, int E, int &blk, int &loc) {
+    blk = (E == 2) ? (c >> 1) : (c / 3);
+    loc = c - blk * E;
 }
 
+__device__ __forceinline__ int cell_slot(const Box &B, int cx, int cy, int cz) {
+    const int E = B.edge;
+    int bx, lx, by, ly, bz, lz;
+    split_edge(cx, E, bx, lx);
+    split_edge(cy, E, by, ly);
+    split_edge(cz, E, bz, lz);
+    const int blk = (bz * B.nbx + by) * B.nbx + bx;
+    return B.cell_off + blk * (E * E * E) + (lz * E + ly) * E + lx;
+}
+
+constexpr int kAxis = kMaxEdge + 2;  // neighborhood cells per axis, at most
+
 // Distinct cells c0-1 .. c0+e (periodic) along one axis, in that order.
-__device__ __forceinline__ int hood_axis(int c0, int e, int nc, int out[4]) {
+__device__ __forceinline__ int hood_axis(int c0, int e, int nc, int out[kAxis]) {
     int n = 0;
     for (int t = 0; t < e + 2; ++t) {
         int v = c0 - 1 + t;
@@ -59,7 +72,7 @@ __device__ __forceinline__ int hood_axis(int c0, int e, int nc, int out[4]) {
     return n;
 }
 
-__device__ __forceinline__ int axis_index(const int a[4], int n, int v) {
+__device__ __forceinline__ int axis_index(const int a[kAxis], int n, int v) {
     int r = 0;
     for (int q = 0; q < n; ++q)
         r = (a[q] == v) ? q : r;
@@ -67,12 +80,12 @@ __device__ __forceinline__ int axis_index(const int a[4], int n, int v) {
 }
 
 // Neighborhood axes of local block lb (uniform across the workgroup).
-__device__ __forceinline__ void hood_axes(const Box &B, int lb, int n[3], int co[3][4]) {
+__device__ __forceinline__ void hood_axes(const Box &B, int lb, int n[3], int co[3][kAxis]) {
     const int nbx = B.nbx;
     const int bc[3] = {lb % nbx, (lb / nbx) % nbx, lb / (nbx * nbx)};
     for (int a = 0; a < 3; ++a) {
-        const int c0 = 2 * bc[a];
-        const int e = min(2, B.nc - c0);
+        const int c0 = B.edge * bc[a];
+        const int e = min(B.edge, B.nc - c0);
         n[a] = hood_axis(c0, e, B.nc, co[a]);
     }
 }
@@ -95,32 +108,37 @@ __device__ __forceinline__ int wave_prefix_incl(int v) {
     return v;
 }
 
-// Cell ranges and LDS offsets of the neighborhood of local block lb; ends
-// with a workgroup barrier.
+// Cell ranges and LDS offsets of the neighborhood of local block lb (the
+// first wavefront handles cells u and u + 64); ends with a workgroup barrier.
 __device__ __forceinline__ void hood_setup(const Box &B, int lb, const int32_t *__restrict__ cell_start, Hood &h) {
     if (threadIdx.x < 64) {
-        int n[3], co[3][4];
+        int n[3], co[3][kAxis];
         hood_axes(B, lb, n, co);
         const int nh = n[0] * n[1] * n[2];
-        const int u = threadIdx.x;
-        int cs = 0, cnt = 0;
-        if (u < nh) {
-            const int ix = u % n[0], iy = (u / n[0]) % n[1], iz = u / (n[0] * n[1]);
-            const int sl = cell_slot(B, co[0][ix], co[1][iy], co[2][iz]);
-            cs = cell_start[sl];
-            cnt = cell_start[sl + 1] - cs;
+        int base = 0;
+        for (int half = 0; half < 2; ++half) {
+            const int u = threadIdx.x + 64 * half;
+            int cs = 0, cnt = 0;
+            if (u < nh) {
+                const int ix = u % n[0], iy = (u / n[0]) % n[1], iz = u / (n[0] * n[1]);
+                const int sl = cell_slot(B, co[0][ix], co[1][iy], co[2][iz]);
+                cs = cell_start[sl];
+                cnt = cell_start[sl + 1] - cs;
+            }
+            const int incl = base + wave_prefix_incl(cnt);
+            if (u < nh) {
+                h.cs[u] = cs;
+                h.off[u + 1] = incl;
+            }
+            base = __shfl(incl, 63, 64);
         }
-        const int incl = wave_prefix_incl(cnt);
-        if (u < nh) {
-            h.cs[u] = cs;
-            h.off[u + 1] = incl;
-        }
-        if (u == 0) {
+        if (threadIdx.x == 0) {
             h.off[0] = 0;
             h.ncell = nh;
-            const int first = B.cell_off + lb * 8;
+            const int cpb = B.edge * B.edge * B.edge;
+            const int first = B.cell_off + lb * cpb;
             h.a0 = cell_start[first];
-            h.a1 = cell_start[first + 8];
+            h.a1 = cell_start[first + cpb];
         }
     }
     __syncthreads();
@@ -436,7 +454,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
         hood_stage(h, total, x, y, z, S);
     // list padding up to a whole 4-entry chunk points at the NaN sentinel
     const int sentinel = fits ? total : d.nt;
-    int n[3], co[3][4];
+    int n[3], co[3][kAxis];
     hood_axes(B, lb, n, co);
     for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
         const double xi = x[i], yi = y[i], zi = z[i];
@@ -495,7 +513,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                 }
         const int stored = c < d.maxnb ? c : d.maxnb;
         cnt[i] = stored;
-        for (int k = stored; k < ((stored + 3) & ~3); ++k)
+        // pad to a whole chunk (a whole sentinel chunk for an empty list)
+        for (int k = stored; k < (stored > 0 ? (stored + 3) & ~3 : 4); ++k)
             nbr[nbr_index(i, k, d.nchunk)] = sentinel;
         if (c > d.maxnb) {
             atomicOr(err, kErrOverflow);
@@ -508,68 +527,107 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-// Sum over one atom's list: F_i = sum f(s) d_ij for s < cutoff^2 with
-// f = 48 eps sr6 (sr6 - 1/2) sr2 = sr2 sr6 (48 eps sr6 - 24 eps),
-// sr2 = 1/s, sr6 = sigma^6 sr2^3.  The list is read four entries per 16-byte
-// load, two chunks ahead of use, with non-temporal loads (it is streamed once
-// per step and should not displace positions from the caches); the twelve
-// coordinate loads of a chunk are issued together before any of its four
-// pairs is evaluated.  Entries past the count point at a NaN sentinel atom,
-// so no pair needs a bounds test.  POS reads positions from the LDS copy of
-// the neighborhood or from global memory.
-template <bool THERMO, class POS>
-__device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int c, const POS &pos, double xi,
-                                         double yi, double zi, const Box &B, double &ax, double &ay, double &az,
-                                         double &u, double &w) {
-    const int nch = (c + 3) >> 2;
-    // index chunks k+1 and k+2 in registers, chunk k+3 in flight; the
-    // positions of chunk k+1 are read while chunk k is evaluated
-    v4i i1 = {0, 0, 0, 0}, i2 = {0, 0, 0, 0};
-    double xs[4], ys[4], zs[4];
-    if (nch > 0) {
-        const v4i i0 = __builtin_nontemporal_load(chunks);
+// Positions of the four atoms of one list chunk.
+struct Quad {
+    double x[4], y[4], z[4];
+};
+
+template <class POS>
+__device__ __forceinline__ void fetch4(const POS &pos, const v4i &n, Quad &q) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-            pos.get(i0[m], xs[m], ys[m], zs[m]);
-    }
-    if (nch > 1)
-        i1 = __builtin_nontemporal_load(chunks + 64);
-    if (nch > 2)
-        i2 = __builtin_nontemporal_load(chunks + 128);
-    for (int k = 0; k < nch; ++k) {
-        double xn[4], yn[4], zn[4];
-        if (k + 1 < nch) {
+    for (int m = 0; m < 4; ++m)
+        pos.get(n[m], q.x[m], q.y[m], q.z[m]);
+}
+
+// Four pairs of the sum F_i = sum f(s) d_ij over s < cutoff^2, with
+// f = 48 eps sr6 (sr6 - 1/2) sr2 written as sr2 q (f12 q - f6), q = sr2^3,
+// f12 = 48 eps sigma^12, f6 = 24 eps sigma^6 (Sec. 3.2, Eq. 2).  |d|^2 may
+// use fused multiply-adds here: it decides only the cutoff test, whose pairs
+// at s within an ulp of cutoff^2 have a vanishing share (the neighbor sets
+// themselves come from the build's unfused sum).  mf6 and mu6 are -f6 and
+// -u6.
+template <bool THERMO>
+__device__ __forceinline__ void eval4(const Quad &q, double xi, double yi, double zi, const Box &B, double mf6,
+                                      double mu6, double &ax, double &ay, double &az, double &u, double &w) {
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-                pos.get(i1[m], xn[m], yn[m], zn[m]);
+    for (int m = 0; m < 4; ++m) {
+        double dx = xi - q.x[m], dy = yi - q.y[m], dz = zi - q.z[m];
+        double s = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (s >= B.halfL2) {
+            dx = mic(dx, B.L, B.halfL);
+            dy = mic(dy, B.L, B.halfL);
+            dz = mic(dz, B.L, B.halfL);
+            s = fma(dz, dz, fma(dy, dy, dx * dx));
         }
-        i1 = i2;
-        if (k + 3 < nch)
-            i2 = __builtin_nontemporal_load(chunks + (k + 3) * 64);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            double dx, dy, dz;
-            const double s = pair_delta(xi, yi, zi, xs[m], ys[m], zs[m], B.L, B.halfL, B.halfL2, dx, dy, dz);
-            if (s < B.rc2) {
-                const double sr2 = recip(s);
-                const double sr6 = sr2 * sr2 * sr2 * B.sigma6;
-                const double f = sr2 * sr6 * fma(B.eps48, sr6, -B.eps24);
-                ax += f * dx;
-                ay += f * dy;
-                az += f * dz;
-                if (THERMO) {
-                    u += sr6 * fma(B.eps4, sr6, -B.eps4);
-                    w += s * f;
-                }
+        if (s < B.rc2) {
+            const double sr2 = recip(s);
+            const double q3 = sr2 * sr2 * sr2;
+            const double f = (sr2 * q3) * fma(B.f12, q3, mf6);
+            ax = fma(f, dx, ax);
+            ay = fma(f, dy, ay);
+            az = fma(f, dz, az);
+            if (THERMO) {
+                u = fma(q3, fma(B.u12, q3, mu6), u);
+                w = fma(s, f, w);
             }
         }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            xs[m] = xn[m];
-            ys[m] = yn[m];
-            zs[m] = zn[m];
-        }
     }
+}
+
+// Sum over one atom's list (c entries, chunks of four).  Index chunks are
+// read with 16-byte non-temporal loads (the list is streamed once per step
+// and should not displace positions from the caches) four chunks ahead of
+// use; the positions of a chunk are read one chunk ahead.  The loop body
+// covers four chunks so that every in-flight value lands in the register
+// that consumes it, and it issues its loads unconditionally (straight-line
+// memory operations keep the wait counters exact, with no copy or branch
+// forcing an early wait): a chunk index past the atom's last chunk is
+// clamped to that chunk, which holds valid slots, and the pairs of such
+// chunks are not evaluated.  Entries past the count inside the last chunk
+// point at a NaN sentinel atom, so no pair needs a bounds test; the build
+// writes a sentinel chunk for an empty list.  POS reads positions from the
+// LDS copy of the neighborhood or from global memory.
+template <bool THERMO, class POS>
+__device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int c, const POS &pos, double xi,
+                                         double yi, double zi, const Box &B, double mf6, double mu6, double &ax,
+                                         double &ay, double &az, double &u, double &w) {
+    const int nch = (c + 3) >> 2;
+    const int lastc = nch > 0 ? nch - 1 : 0;
+    auto ld = [&](int k) { return __builtin_nontemporal_load(chunks + (k < lastc ? k : lastc) * 64); };
+    Quad P, Q;
+    fetch4(pos, ld(0), P);
+    // issue the four look-ahead loads in chunk order (the loop consumes them
+    // oldest first)
+    v4i n1 = ld(1);
+    __builtin_amdgcn_sched_barrier(0);
+    v4i n2 = ld(2);
+    __builtin_amdgcn_sched_barrier(0);
+    v4i n3 = ld(3);
+    __builtin_amdgcn_sched_barrier(0);
+    v4i n4 = ld(4);
+    for (int k = 0; k < nch; k += 4) {
+        fetch4(pos, n1, Q);
+        n1 = ld(k + 5);
+        eval4<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch4(pos, n2, P);
+        n2 = ld(k + 6);
+        if (k + 1 < nch)
+            eval4<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch4(pos, n3, Q);
+        n3 = ld(k + 7);
+        if (k + 2 < nch)
+            eval4<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch4(pos, n4, P);
+        n4 = ld(k + 8);
+        if (k + 3 < nch)
+            eval4<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        // Q's reads are done on every path (not only where Q was evaluated);
+        // the eight reads of P stay in flight into the next iteration
+        __builtin_amdgcn_s_waitcnt(0xC87F);  // lgkmcnt(8)
+    }
+    // retire the unused look-ahead reads here, so the next atom's loop
+    // starts from an exactly known set of outstanding operations
+    __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) expcnt(7) lgkmcnt(0)
 }
 
 __device__ __forceinline__ const v4i *list_chunks(const int32_t *nbr, int i, int nchunk) {
@@ -600,6 +658,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     if (b >= d.nblk)
         return;
     const Box B = boxes[blk_box[b]];
+    // -f6 and -u6 live in vector registers: each fma of the pair loop that
+    // uses them already reads one scalar operand
+    double mf6 = -B.f6, mu6 = -B.u6;
+    asm volatile("" : "+v"(mf6), "+v"(mu6));
     hood_setup(B, b - B.block_off, cell_start, h);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
@@ -613,9 +675,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
         double ax = 0.0, ay = 0.0, az = 0.0;
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
         if (fits)
-            pair_sum<THERMO>(chunks, cnt[i], spos, xi, yi, zi, B, ax, ay, az, u, w);
+            pair_sum<THERMO>(chunks, cnt[i], spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         else
-            pair_sum<THERMO>(chunks, cnt[i], gpos, xi, yi, zi, B, ax, ay, az, u, w);
+            pair_sum<THERMO>(chunks, cnt[i], gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         if (MODE == 0 || MODE == 1) {
             fx[i] = ax;
             fy[i] = ay;

@@ -10,8 +10,9 @@ namespace tmd {
 constexpr int kScanTile = 1024;    // elements per workgroup in the cell-count scan
 constexpr int kPartialStride = 4;  // doubles per block partial: U, W, KE, pad
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, each with its own L2
-constexpr int kMaxHood = 64;       // cells in a block neighborhood (at most 4 per axis)
-constexpr int kMaxThreads = 256;   // threads per block workgroup (upper bound)
+constexpr int kMaxEdge = 3;        // cells per block edge: 2 or 3
+constexpr int kMaxHood = 125;      // cells in a block neighborhood (at most edge + 2 per axis)
+constexpr int kMaxThreads = 1024;  // threads per block workgroup (upper bound)
 constexpr int kAtomThreads = 256;  // threads per workgroup of per-atom kernels
 
 // Bits of the device error word err[0].
@@ -19,15 +20,15 @@ constexpr int kErrOverflow = 1;
 constexpr int kErrNonFinite = 2;
 constexpr int kErrOutOfBox = 4;  // set_state got a coordinate outside [-L, 2L)
 
-// One periodic cubic box.  Cells are numbered block-major: a block is 2x2x2
-// cells (1 cell thick at the high face when the cell count is odd), each
-// block owns 8 consecutive cell slots, so the atoms of a block and of each
-// of its cells are contiguous after binning.
+// One periodic cubic box.  Cells are numbered block-major: a block is E x E x
+// E cells (E = 2 or 3; thinner at the high faces when E does not divide the
+// cell count), each block owns E^3 consecutive cell slots, so the atoms of a
+// block and of each of its cells are contiguous after binning.
 struct Box {
     int32_t atom_off, n;     // atoms [atom_off, atom_off + n) of the concatenated arrays
     int32_t cell_off, nc;    // first cell slot; cells per axis
-    int32_t nbx, block_off;  // blocks per axis (ceil(nc / 2)); first block
-    int32_t nblocks, pad_;
+    int32_t nbx, block_off;  // blocks per axis (ceil(nc / E)); first block
+    int32_t nblocks, edge;   // blocks of this box; E
     double L, halfL, side;   // box, half box, cell side L / nc
     double halfL2;           // (L/2)^2
     double rc2, rl2;         // cutoff^2, (cutoff + skin)^2
@@ -35,6 +36,8 @@ struct Box {
     double eps48, eps24;     // 48 eps and 24 eps: f = sr2 sr6 (48 eps sr6 - 24 eps)
     double eps4;             // 4 eps: pair energy sr6 (4 eps sr6 - 4 eps)
     double eps_over_sigma;   // d f / d sigma = (eps / sigma) sr2 sr6 (576 sr6 - 144)
+    double f12, f6;          // 48 eps sigma^12, 24 eps sigma^6: f = sr2 q (f12 q - f6) with q = sr2^3
+    double u12, u6;          // 4 eps sigma^12, 4 eps sigma^6: pair energy q (u12 q - u6)
     double h, dt, mass;      // half kick dt / (2 m), time step, mass
 };
 
@@ -44,11 +47,14 @@ struct Dims {
     int32_t ntp;      // padded stride of the neighbor-major list
     int32_t nbox;     // boxes
     int32_t nblk;     // blocks in all boxes
-    int32_t ncs;      // cell slots in all boxes (8 per block)
+    int32_t ncs;      // cell slots in all boxes (E^3 per block)
+    int32_t edge;     // E, cells per block edge
+    int32_t cpb;      // E^3, cell slots per block
     int32_t maxnb;    // list capacity per atom
     int32_t cap;      // atoms a block neighborhood may stage in LDS
     int32_t threads;  // threads per block workgroup (64..kMaxThreads, multiple of 64)
     int32_t nchunk;   // 4-entry list chunks per atom: ceil(maxnb / 4)
+    int32_t pad_;
 };
 
 // Neighbor list layout: neighbor-major within tiles of 64 atoms (one

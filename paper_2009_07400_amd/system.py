@@ -141,15 +141,18 @@ class System:
     def info(self) -> dict:
         return abi.tmd_get_info(self._h)
 
-    def set_schedule(self, threads: int = 0, lds_atoms: int = 0) -> None:
-        """Threads per block workgroup and LDS staging capacity (0 = keep)."""
-        abi.tmd_set_schedule(self._h, threads, lds_atoms)
+    def set_schedule(self, threads: int = 0, lds_atoms: int = 0, block_edge: int = 0) -> None:
+        """Threads per block workgroup, LDS staging capacity and cells per
+        block edge (0 = keep)."""
+        abi.tmd_set_schedule(self._h, threads, lds_atoms, block_edge)
 
-    def autotune(self, repeats: int = 5) -> int:
-        """Times the force kernel per schedule and keeps the fastest; returns
-        the chosen threads per block workgroup."""
+    def autotune(self, repeats: int = 5):
+        """Times the force kernel per schedule (block edge, threads) and keeps
+        the fastest; returns (block_edge, block_threads).  Rebuilds the list
+        at the current positions."""
         abi.tmd_autotune(self._h, repeats, _stream())
-        return self.info()["block_threads"]
+        info = self.info()
+        return info["block_edge"], info["block_threads"]
 
     def set_lj_params(self, epsilon, sigma) -> None:
         """Per-box epsilon and sigma (sequences of n_boxes floats, or scalars)."""

@@ -118,12 +118,16 @@ def test_batch_create_and_validation():
         # 2 cells per axis -> 1 block; 3 -> 2^3 blocks (the last one cell thick); 7 -> 4^3 blocks
         assert info["n_blocks"] == 1 + 8 + 64
         assert info["n_cells"] == 8 + 27 + 343
-        assert info["block_threads"] % 64 == 0 and 64 <= info["block_threads"] <= 256
-        assert info["lds_atoms"] % 64 == 0 and 64 <= info["lds_atoms"] <= 2560
+        assert info["block_threads"] % 64 == 0 and 64 <= info["block_threads"] <= 1024
+        assert info["lds_atoms"] % 64 == 0 and 64 <= info["lds_atoms"] <= 4096
+        assert info["block_edge"] == 2  # too few 3x3x3 blocks to fill the GPU
         abi.tmd_set_schedule(h, 128, 512)
         info = abi.tmd_get_info(h)
         assert (info["block_threads"], info["lds_atoms"]) == (128, 512)
-        for bad in ((100, 0), (320, 0), (0, 100), (0, 4096), (-64, 0)):
+        abi.tmd_set_schedule(h, 0, 0, 3)  # 3 cells per edge: 1 + 1 + 3^3 blocks
+        info = abi.tmd_get_info(h)
+        assert (info["block_edge"], info["n_blocks"]) == (3, 1 + 1 + 27)
+        for bad in ((100, 0, 0), (1088, 0, 0), (0, 100, 0), (0, 4160, 0), (-64, 0, 0), (0, 0, 4), (0, 0, 1)):
             with pytest.raises(abi.TmdError):
                 abi.tmd_set_schedule(h, *bad)
     finally:

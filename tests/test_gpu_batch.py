@@ -117,15 +117,16 @@ def test_batch_equals_single_box_runs_bitwise():
         off += n
 
 
-@pytest.mark.parametrize("threads,lds", [(64, 0), (128, 0), (192, 0), (256, 0), (0, 64)])
-def test_schedule_does_not_change_trajectory(threads, lds):
-    s = md_system(9, seed=21)
+@pytest.mark.parametrize("threads,lds,edge", [(64, 0, 2), (128, 0, 2), (192, 0, 2), (256, 0, 2), (0, 64, 2),
+                                              (0, 0, 3), (384, 0, 3), (1024, 0, 3), (0, 64, 3)])
+def test_schedule_does_not_change_trajectory(threads, lds, edge):
+    s = md_system(9, seed=21)  # 5 cells per axis: edge blocks 1 (E = 2) or 2 (E = 3) cells thick
     ref = System(s.n, s.L)
     ref.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
     ref.integrate(30)
     p0, v0, _ = ref.get_state()
     g = System(s.n, s.L)
-    g.set_schedule(threads=threads, lds_atoms=lds)
+    g.set_schedule(threads=threads, lds_atoms=lds, block_edge=edge)
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
     g.integrate(30)
     p1, v1, _ = g.get_state()
@@ -140,10 +141,10 @@ def test_autotune_keeps_state():
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
     g.integrate(5)
     p0, v0, _ = g.get_state()
-    t = g.autotune(repeats=2)
+    edge, t = g.autotune(repeats=2)
     p1, v1, _ = g.get_state()
     g.sync()
-    assert t in (64, 128, 192, 256)
+    assert edge in (2, 3) and t % 64 == 0 and 64 <= t <= 1024
     assert torch.equal(p0, p1) and torch.equal(v0, v1)
 
 
