@@ -61,7 +61,7 @@ def _traffic(workload: str):
     return ent.get("bytes_per_launch")
 
 
-def run_gpu(workload: str, steps: int, warmup: int):
+def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     import torch
 
     from paper_2009_07400_amd import System
@@ -71,7 +71,11 @@ def run_gpu(workload: str, steps: int, warmup: int):
     s = md_system(w["ncell"], w["rho"], w["T"], seed=w["seed"], jitter=w["jitter"])
     g = System(s.n, s.L, max_neighbors=128)
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
-    edge, threads = g.autotune(repeats=3)  # schedule chosen before the warmup, outside the timed region
+    if schedule:  # fixed (block edge, threads), e.g. for profiling runs
+        g.set_schedule(threads=schedule[1], block_edge=schedule[0])
+        edge, threads = schedule
+    else:  # schedule chosen before the warmup, outside the timed region
+        edge, threads = g.autotune(repeats=3)
     g.integrate(warmup)
     g.sync()
     torch.cuda.synchronize()
@@ -239,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3.5M-atom secondary workload")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--schedule", default=None,
+                    help="fixed block edge and threads for the primary workload, e.g. 3,512 (default: autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the run, copy a 1 GiB buffer 3 times with torch: a kernel of known traffic "
                          "(1 GiB read + 1 GiB written per launch) to calibrate FETCH_SIZE / WRITE_SIZE counters")
@@ -261,7 +267,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prim = run_gpu(args.workload, steps, args.warmup)
+    sched = tuple(int(v) for v in args.schedule.split(",")) if args.schedule else None
+    prim = run_gpu(args.workload, steps, args.warmup, sched)
     print(f"# primary {args.workload}: {prim['value']:.4g} atom-steps/s, {prim['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)
     out = {

@@ -240,7 +240,7 @@ bool layout_blocks(tmd_system *s, int E) {
     const int need = int(1.15 * worst) + 32;
     d.cap = std::min(kMaxCap, round_up(int(1.3 * worst) + 64, 64));
     for (int wg = 8; wg >= 1; --wg) {
-        const int c = ((kLdsPerCu / wg - kStaticLds) / 24 - 1) / 64 * 64;
+        const int c = ((kLdsPerCu / wg - kStaticLds) / 24 - 2) / 64 * 64;  // + sentinel and scratch slots
         if (c >= need) {
             d.cap = std::min(kMaxCap, c);
             break;
@@ -330,7 +330,7 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
         d.ntp = round_up(d.nt + 1, 256);  // slot nt holds the NaN sentinel atom
         d.nbox = nbox;
         d.maxnb = params[0].max_neighbors;
-        d.nchunk = (d.maxnb + 3) / 4;
+        d.nchunk = (d.maxnb + 3) / 4 + 1;  // one spare chunk of sentinel padding
         if (int64_t(d.ntp) * d.maxnb > (int64_t(1) << 40)) {
             delete s;
             return TMD_EINVAL;

@@ -115,19 +115,25 @@ __device__ __forceinline__ void hood_setup(const Box &B, int lb, const int32_t *
         int n[3], co[3][kAxis];
         hood_axes(B, lb, n, co);
         const int nh = n[0] * n[1] * n[2];
-        int base = 0;
+        // all cell_start reads first (one memory round trip), then the scans
+        int cs[2] = {0, 0}, cnt[2] = {0, 0};
+#pragma unroll
         for (int half = 0; half < 2; ++half) {
             const int u = threadIdx.x + 64 * half;
-            int cs = 0, cnt = 0;
             if (u < nh) {
                 const int ix = u % n[0], iy = (u / n[0]) % n[1], iz = u / (n[0] * n[1]);
                 const int sl = cell_slot(B, co[0][ix], co[1][iy], co[2][iz]);
-                cs = cell_start[sl];
-                cnt = cell_start[sl + 1] - cs;
+                cs[half] = cell_start[sl];
+                cnt[half] = cell_start[sl + 1];
             }
-            const int incl = base + wave_prefix_incl(cnt);
+        }
+        int base = 0;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int u = threadIdx.x + 64 * half;
+            const int incl = base + wave_prefix_incl(cnt[half] - cs[half]);
             if (u < nh) {
-                h.cs[u] = cs;
+                h.cs[u] = cs[half];
                 h.off[u + 1] = incl;
             }
             base = __shfl(incl, 63, 64);
@@ -189,23 +195,45 @@ struct GlobalPos {
 };
 
 // Copy the neighborhood's positions into LDS (the global loads are
-// coalesced within each cell), and a NaN sentinel atom at slot `total`:
-// list padding points there, and every comparison with a NaN distance is
-// false, so padded entries need no test.  Ends with a workgroup barrier.
-__device__ __forceinline__ void hood_stage(const Hood &h, int total, const double *__restrict__ x,
+// coalesced within each cell), and a NaN sentinel atom at slot `sent` (the
+// LDS capacity, the same slot for every block): list padding points there,
+// and every comparison with a NaN distance is false, so padded entries need
+// no test.  Ends with a workgroup barrier.
+__device__ __forceinline__ void hood_stage(const Hood &h, int total, int sent, const double *__restrict__ x,
                                            const double *__restrict__ y, const double *__restrict__ z,
                                            lds_double *s) {
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int u = hood_find(h, t);
-        const int g = h.cs[u] + (t - h.off[u]);
-        lds_double *a = lds_slot(s, t);
-        a[0] = x[g];
-        a[1] = y[g];
-        a[2] = z[g];
+    // four slots per thread per round: the four searches, then all twelve
+    // global loads in flight together, then the LDS writes.  Every memory
+    // operation is unconditional: a slot past the end copies the last atom
+    // into the scratch slot after the sentinel.
+    constexpr int R = 4;
+    const int T = blockDim.x;
+    for (int base = threadIdx.x; base < total; base += R * T) {
+        int g[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int t = min(base + r * T, total - 1);
+            const int u = hood_find(h, t);
+            g[r] = h.cs[u] + (t - h.off[u]);
+        }
+        double px[R], py[R], pz[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            px[r] = x[g[r]];
+            py[r] = y[g[r]];
+            pz[r] = z[g[r]];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            lds_double *a = lds_slot(s, base + r * T < total ? base + r * T : sent + 1);
+            a[0] = px[r];
+            a[1] = py[r];
+            a[2] = pz[r];
+        }
     }
     if (threadIdx.x == 0) {
         const double nan = __builtin_nan("");
-        lds_double *a = lds_slot(s, total);
+        lds_double *a = lds_slot(s, sent);
         a[0] = nan;
         a[1] = nan;
         a[2] = nan;
@@ -427,11 +455,18 @@ __global__ __launch_bounds__(kAtomThreads) void k_rank_permute(
 
 // ------------------------------------------------------------------ neighbor list
 
+// Descriptor of the box that block b belongs to (a single box needs no
+// lookup, which saves a dependent memory round trip at every workgroup start).
+__device__ __forceinline__ Box block_box(const Dims &d, const Box *__restrict__ boxes,
+                                         const int32_t *__restrict__ blk_box, int b) {
+    return boxes[d.nbox == 1 ? 0 : blk_box[b]];
+}
+
 // One workgroup per block, one lane per atom: every j != i in the distinct
 // cells of i's 27-cell stencil with s < (cutoff + skin)^2 enters i's list.
 // Candidates come from the LDS copy of the neighborhood (lanes of one cell
-// read the same candidate, a broadcast); list entries are LDS slots, or
-// global indices when the neighborhood did not fit.
+// read the same candidate, a broadcast); list entries are 16-bit LDS slots,
+// or 32-bit global indices when the neighborhood did not fit.
 __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__restrict__ boxes,
                                                        const int32_t *__restrict__ blk_box,
                                                        const double *__restrict__ x, const double *__restrict__ y,
@@ -444,16 +479,17 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     const int b = xcd_remap();
     if (b >= d.nblk)
         return;
-    const Box B = boxes[blk_box[b]];
+    const Box B = block_box(d, boxes, blk_box, b);
     const int lb = b - B.block_off;
     hood_setup(B, lb, cell_start, h);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     lds_double *S = (lds_double *)lds;
     if (fits)
-        hood_stage(h, total, x, y, z, S);
-    // list padding up to a whole 4-entry chunk points at the NaN sentinel
-    const int sentinel = fits ? total : d.nt;
+        hood_stage(h, total, d.cap, x, y, z, S);
+    // list padding points at the NaN sentinel: LDS slot cap, or global slot nt
+    const int sentinel = fits ? d.cap : d.nt;
+    uint16_t *nbr16 = reinterpret_cast<uint16_t *>(nbr);
     int n[3], co[3][kAxis];
     hood_axes(B, lb, n, co);
     for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
@@ -493,7 +529,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                                 pair_delta(xi, yi, zi, p[0], p[1], p[2], B.L, B.halfL, B.halfL2, dx, dy, dz);
                             if (s < B.rl2 && t != self) {
                                 if (c < d.maxnb)
-                                    nbr[nbr_index(i, c, d.nchunk)] = t;
+                                    nbr16[nbr_index16(i, c, d.nchunk)] = uint16_t(t);
                                 ++c;
                             }
                         }
@@ -513,9 +549,16 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                 }
         const int stored = c < d.maxnb ? c : d.maxnb;
         cnt[i] = stored;
-        // pad to a whole chunk (a whole sentinel chunk for an empty list)
-        for (int k = stored; k < (stored > 0 ? (stored + 3) & ~3 : 4); ++k)
-            nbr[nbr_index(i, k, d.nchunk)] = sentinel;
+        // pad the last chunk and one whole chunk after it (every list has
+        // room for it: nchunk = ceil(maxnb / 4) + 1); force loops read that
+        // chunk in place of any chunk past the end
+        if (fits) {
+            for (int k = stored; k < ((stored + 7) & ~7) + 8; ++k)
+                nbr16[nbr_index16(i, k, d.nchunk)] = uint16_t(sentinel);
+        } else {
+            for (int k = stored; k < ((stored + 3) & ~3) + 4; ++k)
+                nbr[nbr_index(i, k, d.nchunk)] = sentinel;
+        }
         if (c > d.maxnb) {
             atomicOr(err, kErrOverflow);
             atomicMax(err + 1, c);
@@ -527,30 +570,29 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-// Positions of the four atoms of one list chunk.
-struct Quad {
-    double x[4], y[4], z[4];
+// Positions of two list entries.
+struct Duo {
+    double x[2], y[2], z[2];
 };
 
 template <class POS>
-__device__ __forceinline__ void fetch4(const POS &pos, const v4i &n, Quad &q) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-        pos.get(n[m], q.x[m], q.y[m], q.z[m]);
+__device__ __forceinline__ void fetch2(const POS &pos, int j0, int j1, Duo &q) {
+    pos.get(j0, q.x[0], q.y[0], q.z[0]);
+    pos.get(j1, q.x[1], q.y[1], q.z[1]);
 }
 
-// Four pairs of the sum F_i = sum f(s) d_ij over s < cutoff^2, with
+// Two pairs of the sum F_i = sum f(s) d_ij over s < cutoff^2, with
 // f = 48 eps sr6 (sr6 - 1/2) sr2 written as sr2 q (f12 q - f6), q = sr2^3,
 // f12 = 48 eps sigma^12, f6 = 24 eps sigma^6 (Sec. 3.2, Eq. 2).  |d|^2 may
 // use fused multiply-adds here: it decides only the cutoff test, whose pairs
 // at s within an ulp of cutoff^2 have a vanishing share (the neighbor sets
 // themselves come from the build's unfused sum).  mf6 and mu6 are -f6 and
-// -u6.
+// -u6.  A NaN sentinel entry fails both tests and adds nothing.
 template <bool THERMO>
-__device__ __forceinline__ void eval4(const Quad &q, double xi, double yi, double zi, const Box &B, double mf6,
+__device__ __forceinline__ void eval2(const Duo &q, double xi, double yi, double zi, const Box &B, double mf6,
                                       double mu6, double &ax, double &ay, double &az, double &u, double &w) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < 2; ++m) {
         double dx = xi - q.x[m], dy = yi - q.y[m], dz = zi - q.z[m];
         double s = fma(dz, dz, fma(dy, dy, dx * dx));
         if (s >= B.halfL2) {
@@ -574,59 +616,111 @@ __device__ __forceinline__ void eval4(const Quad &q, double xi, double yi, doubl
     }
 }
 
-// Sum over one atom's list (c entries, chunks of four).  Index chunks are
+// Sum over one atom's list (c entries in chunks of four).  Index chunks are
 // read with 16-byte non-temporal loads (the list is streamed once per step
-// and should not displace positions from the caches) four chunks ahead of
-// use; the positions of a chunk are read one chunk ahead.  The loop body
-// covers four chunks so that every in-flight value lands in the register
-// that consumes it, and it issues its loads unconditionally (straight-line
-// memory operations keep the wait counters exact, with no copy or branch
-// forcing an early wait): a chunk index past the atom's last chunk is
-// clamped to that chunk, which holds valid slots, and the pairs of such
-// chunks are not evaluated.  Entries past the count inside the last chunk
-// point at a NaN sentinel atom, so no pair needs a bounds test; the build
-// writes a sentinel chunk for an empty list.  POS reads positions from the
-// LDS copy of the neighborhood or from global memory.
+// and should not displace positions from the caches) about three chunks
+// ahead of use, the positions of two entries two entries ahead.  The loop
+// body covers four chunks so that every in-flight value lands in the
+// register that consumes it (no copies that would force an early wait), and
+// all its memory operations are unconditional, so the wait counters stay
+// exact.  A chunk index past the atom's last chunk reads the chunk after it,
+// which the build fills with NaN sentinel entries (as it fills the rest of
+// the last chunk): such entries add nothing, so every lane runs the same
+// straight-line body until no lane of the wavefront has chunks left.  POS
+// reads positions from the LDS copy of the neighborhood or from global
+// memory.
 template <bool THERMO, class POS>
 __device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int c, const POS &pos, double xi,
                                          double yi, double zi, const Box &B, double mf6, double mu6, double &ax,
                                          double &ay, double &az, double &u, double &w) {
     const int nch = (c + 3) >> 2;
-    const int lastc = nch > 0 ? nch - 1 : 0;
-    auto ld = [&](int k) { return __builtin_nontemporal_load(chunks + (k < lastc ? k : lastc) * 64); };
-    Quad P, Q;
-    fetch4(pos, ld(0), P);
-    // issue the four look-ahead loads in chunk order (the loop consumes them
-    // oldest first)
-    v4i n1 = ld(1);
+    auto ld = [&](int k) { return __builtin_nontemporal_load(chunks + (k < nch ? k : nch) * 64); };
+    // issue the look-ahead loads in chunk order (consumed oldest first)
+    v4i i0 = ld(0);
     __builtin_amdgcn_sched_barrier(0);
-    v4i n2 = ld(2);
+    v4i i1 = ld(1);
     __builtin_amdgcn_sched_barrier(0);
-    v4i n3 = ld(3);
+    v4i i2 = ld(2);
     __builtin_amdgcn_sched_barrier(0);
-    v4i n4 = ld(4);
-    for (int k = 0; k < nch; k += 4) {
-        fetch4(pos, n1, Q);
-        n1 = ld(k + 5);
-        eval4<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch4(pos, n2, P);
-        n2 = ld(k + 6);
-        if (k + 1 < nch)
-            eval4<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch4(pos, n3, Q);
-        n3 = ld(k + 7);
-        if (k + 2 < nch)
-            eval4<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch4(pos, n4, P);
-        n4 = ld(k + 8);
-        if (k + 3 < nch)
-            eval4<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        // Q's reads are done on every path (not only where Q was evaluated);
-        // the eight reads of P stay in flight into the next iteration
-        __builtin_amdgcn_s_waitcnt(0xC87F);  // lgkmcnt(8)
+    v4i i3 = ld(3);
+    Duo P, Q;
+    fetch2(pos, i0[0], i0[1], P);
+    for (int k = 0;; k += 4) {
+        fetch2(pos, i0[2], i0[3], Q);
+        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, i1[0], i1[1], P);
+        i0 = ld(k + 4);
+        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, i1[2], i1[3], Q);
+        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, i2[0], i2[1], P);
+        i1 = ld(k + 5);
+        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, i2[2], i2[3], Q);
+        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, i3[0], i3[1], P);
+        i2 = ld(k + 6);
+        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, i3[2], i3[3], Q);
+        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, i0[0], i0[1], P);
+        i3 = ld(k + 7);
+        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        if (!__any(k + 4 < nch))
+            break;
     }
     // retire the unused look-ahead reads here, so the next atom's loop
     // starts from an exactly known set of outstanding operations
+    __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) expcnt(7) lgkmcnt(0)
+}
+
+// Two LDS-slot entries packed in one 32-bit word of a 16-bit list.
+__device__ __forceinline__ void fetch2w(const LdsPos &pos, int word, Duo &q) {
+    const unsigned w = unsigned(word);
+    pos.get(int(w & 0xffffu), q.x[0], q.y[0], q.z[0]);
+    pos.get(int(w >> 16), q.x[1], q.y[1], q.z[1]);
+}
+
+// pair_sum over a list of 16-bit LDS slots (eight entries per chunk): half
+// the bytes of the 32-bit list per entry.  The body covers two chunks, with
+// the same look-ahead discipline (index chunks one to two chunks ahead,
+// positions two entries ahead, unconditional memory operations, the chunk
+// after the last standing in for every chunk past the end).  The only exit
+// is at the end of the body: a loop with several exits loses the exact wait
+// counts at its head.
+template <bool THERMO>
+__device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, int c, const LdsPos &pos, double xi,
+                                           double yi, double zi, const Box &B, double mf6, double mu6,
+                                           double &ax, double &ay, double &az, double &u, double &w) {
+    const int nch = (c + 7) >> 3;
+    auto ld = [&](int k) { return __builtin_nontemporal_load(chunks + (k < nch ? k : nch) * 64); };
+    v4i i0 = ld(0);
+    __builtin_amdgcn_sched_barrier(0);
+    v4i i1 = ld(1);
+    Duo P, Q;
+    fetch2w(pos, i0[0], P);
+    for (int k = 0;; k += 2) {
+        fetch2w(pos, i0[1], Q);
+        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2w(pos, i0[2], P);
+        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2w(pos, i0[3], Q);
+        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2w(pos, i1[0], P);
+        i0 = ld(k + 2);
+        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2w(pos, i1[1], Q);
+        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2w(pos, i1[2], P);
+        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2w(pos, i1[3], Q);
+        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2w(pos, i0[0], P);
+        i1 = ld(k + 3);
+        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        if (!__any(k + 2 < nch))
+            break;
+    }
     __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) expcnt(7) lgkmcnt(0)
 }
 
@@ -657,7 +751,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     const int b = xcd_remap();
     if (b >= d.nblk)
         return;
-    const Box B = boxes[blk_box[b]];
+    const Box B = block_box(d, boxes, blk_box, b);
     // -f6 and -u6 live in vector registers: each fma of the pair loop that
     // uses them already reads one scalar operand
     double mf6 = -B.f6, mu6 = -B.u6;
@@ -667,17 +761,41 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     const bool fits = total <= d.cap;
     const LdsPos spos{(lds_double *)lds};
     const GlobalPos gpos{x, y, z};
+    // The operands of a lane's next atom (position, list length, velocity)
+    // are loaded one pass ahead - those of the first pass before the staging
+    // barrier, so their latency overlaps the staging.  Past the block's last
+    // atom the loads read that atom again (a cache hit) and are not used.
+    const int T = blockDim.x;
+    int i = h.a0 + threadIdx.x;
+    double xi = 0.0, yi = 0.0, zi = 0.0, vxi = 0.0, vyi = 0.0, vzi = 0.0;
+    int ci = 0;
+    auto load_atom = [&](int k) {
+        const int ic = min(k, h.a1 - 1);
+        xi = x[ic];
+        yi = y[ic];
+        zi = z[ic];
+        ci = cnt[ic];
+        if (MODE >= 1) {
+            vxi = vx[ic];
+            vyi = vy[ic];
+            vzi = vz[ic];
+        }
+    };
+    if (h.a1 > h.a0)
+        load_atom(i);
     if (fits)
-        hood_stage(h, total, x, y, z, spos.s);
+        hood_stage(h, total, d.cap, x, y, z, spos.s);
+    // have every kernel argument in registers before the atom loop: a scalar
+    // load still in flight at the pair loop's head costs it exact LDS waits
+    asm volatile("" ::"s"(err), "s"(partials), "s"(xo), "s"(fx));
     double u = 0.0, w = 0.0, ke = 0.0;
-    for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
-        const double xi = x[i], yi = y[i], zi = z[i];
+    for (; i < h.a1; i += T) {
         double ax = 0.0, ay = 0.0, az = 0.0;
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
         if (fits)
-            pair_sum<THERMO>(chunks, cnt[i], spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+            pair_sum16<THERMO>(chunks, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         else
-            pair_sum<THERMO>(chunks, cnt[i], gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+            pair_sum<THERMO>(chunks, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         if (MODE == 0 || MODE == 1) {
             fx[i] = ax;
             fy[i] = ay;
@@ -686,7 +804,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
                 atomicOr(err, kErrNonFinite);
         }
         if (MODE >= 1) {
-            double a = vx[i] + B.h * ax, bb = vy[i] + B.h * ay, c = vz[i] + B.h * az;
+            double a = vxi + B.h * ax, bb = vyi + B.h * ay, c = vzi + B.h * az;
             if (THERMO)
                 ke += a * a + bb * bb + c * c;
             if (MODE == 2) {
@@ -705,6 +823,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
             vy[i] = bb;
             vz[i] = c;
         }
+        load_atom(i + T);
     }
     if (THERMO) {
         block_sum3(u, w, ke);
@@ -785,14 +904,15 @@ __global__ __launch_bounds__(kMaxThreads) void k_export_neighbors(Dims d, const 
     const int b = xcd_remap();
     if (b >= d.nblk)
         return;
-    const Box B = boxes[blk_box[b]];
+    const Box B = block_box(d, boxes, blk_box, b);
     hood_setup(B, b - B.block_off, cell_start, h);
     const bool fits = h.off[h.ncell] <= d.cap;
+    const uint16_t *nbr16 = reinterpret_cast<const uint16_t *>(nbr);
     for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
         const int o = orig[i], c = cnt[i];
         int32_t *row = ids + int64_t(o) * d.maxnb;
         for (int k = 0; k < c; ++k) {
-            int g = nbr[nbr_index(i, k, d.nchunk)];
+            int g = fits ? int(nbr16[nbr_index16(i, k, d.nchunk)]) : nbr[nbr_index(i, k, d.nchunk)];
             if (fits) {
                 const int uu = hood_find(h, g);
                 g = h.cs[uu] + (g - h.off[uu]);
@@ -859,23 +979,22 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
     const int b = xcd_remap();
     if (b >= d.nblk)
         return;
-    const Box B = boxes[blk_box[b]];
+    const Box B = block_box(d, boxes, blk_box, b);
     hood_setup(B, b - B.block_off, cell_start, h);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     lds_double *S = (lds_double *)lds;
     if (fits)
         hood_stage6(h, total, x, w, S);
-    const int sentinel = fits ? total : d.nt;
+    const uint16_t *nbr16 = reinterpret_cast<const uint16_t *>(nbr);
     double pe = 0.0, ps = 0.0, unused = 0.0;
     for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
         const double xi = x.x[i], yi = x.y[i], zi = x.z[i];
         const double wxi = w.x[i], wyi = w.y[i], wzi = w.z[i];
         double gx = 0.0, gy = 0.0, gz = 0.0;
         const int c = cnt[i];
-        const int32_t *nb = nbr;
         for (int k = 0; k < c; ++k) {
-            const int j = nb[nbr_index(i, k, d.nchunk)];
+            const int j = fits ? int(nbr16[nbr_index16(i, k, d.nchunk)]) : nbr[nbr_index(i, k, d.nchunk)];
             double xj, yj, zj, wxj, wyj, wzj;
             if (fits) {
                 const lds_double *a = lds_slot6(S, j);
@@ -912,7 +1031,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
                 ps += B.eps_over_sigma * q * (576.0 * sr6 - 144.0) * wd;
             }
         }
-        (void)sentinel;
         const double cc = mult * B.h;
         const double lx = lam.x[i] + cc * gx, ly = lam.y[i] + cc * gy, lz = lam.z[i] + cc * gz;
         lam.x[i] = lx;

@@ -53,7 +53,7 @@ struct Dims {
     int32_t maxnb;    // list capacity per atom
     int32_t cap;      // atoms a block neighborhood may stage in LDS
     int32_t threads;  // threads per block workgroup (64..kMaxThreads, multiple of 64)
-    int32_t nchunk;   // 4-entry list chunks per atom: ceil(maxnb / 4)
+    int32_t nchunk;   // 4-entry list chunks per atom: ceil(maxnb / 4) + 1 (a spare chunk of padding)
     int32_t pad_;
 };
 
@@ -65,6 +65,14 @@ struct Dims {
 // contiguous stretch of nchunk KB that a wavefront streams through in order.
 __host__ __device__ inline int64_t nbr_index(int i, int k, int nchunk) {
     return ((int64_t((i >> 6)) * nchunk + (k >> 2)) * 64 + (i & 63)) * 4 + (k & 3);
+}
+
+// Atoms of blocks whose neighborhood is staged in LDS store 16-bit LDS slots
+// instead, eight to a 16-byte chunk, in the same rows: entry k of atom i is
+// uint16 element
+//   ((tile(i) * nchunk + k / 8) * 64 + lane(i)) * 8 + k % 8.
+__host__ __device__ inline int64_t nbr_index16(int i, int k, int nchunk) {
+    return ((int64_t((i >> 6)) * nchunk + (k >> 3)) * 64 + (i & 63)) * 8 + (k & 7);
 }
 
 // Three SoA coordinate arrays.
@@ -103,8 +111,9 @@ inline int scan_blocks(int ncell) { return (ncell + kScanTile - 1) / kScanTile; 
 // Grid of block workgroups: a multiple of the XCD count so the remap in the
 // kernels gives every XCD one contiguous range of blocks.
 inline int block_grid(int nblk) { return round_up(nblk, kNumXcd); }
-// LDS bytes of a block workgroup staging `cap` atoms plus the NaN sentinel.
-inline size_t hood_lds_bytes(int cap) { return size_t(cap + 1) * 3 * sizeof(double); }
+// LDS bytes of a block workgroup staging `cap` atoms plus the NaN sentinel
+// and one scratch slot.
+inline size_t hood_lds_bytes(int cap) { return size_t(cap + 2) * 3 * sizeof(double); }
 
 // Launchers (engine.hip).  All enqueue on `s` and return the launch status.
 hipError_t prepare_kernels(const Dims &d);
