@@ -93,8 +93,7 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     g.sync()
     tm = g.get_timing()
     g.set_timing(False)
-    counts, _ = g.get_neighbors()
-    mean_list = float(counts.double().mean().item())
+    mean_list = float(g.neighbor_counts().double().mean().item())
     g.sync()
     ms, launches = tm["force"]
     avg_s = ms / max(launches, 1) * 1e-3
@@ -296,7 +295,7 @@ def main():
         out["secondary"] = {"c2": {"workload": WORKLOADS["c2"]["name"], "value": sec["value"],
                                    "ms_per_step": sec["ms_per_step"], "steps": sec["steps"],
                                    "roofline": sec["roofline"], "kernel_avg_ms": sec["kernel_ms"],
-                                   "mean_list_length": sec["mean_list_length"]}}
+                                   "mean_list_length": sec["mean_list_length"], "schedule": sec["schedule"]}}
         bat = run_batched()
         print(f"# secondary batched: {bat['value']:.4g} atom-steps/s, {bat['speedup_vs_sequential']:.1f}x "
               "sequential", file=sys.stderr, flush=True)

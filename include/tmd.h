@@ -174,7 +174,9 @@ tmd_status tmd_get_state(const tmd_system *sys, double *const pos[3], double *co
 /* Export the current list in original ids: counts[N] (device int32) and
  * ids[N * max_neighbors] (device int32, row i holds atom i's neighbors sorted
  * ascending, unused slots -1).  capacity is the length of ids in elements.
- * TMD_EINVAL if capacity < N * max_neighbors; TMD_ESTATE without a list. */
+ * ids may be NULL to export the counts only (capacity is then ignored).
+ * TMD_EINVAL if counts is NULL or capacity < N * max_neighbors; TMD_ESTATE
+ * without a list. */
 tmd_status tmd_get_neighbors(const tmd_system *sys, int32_t *counts, int32_t *ids, int64_t capacity,
                              tmd_stream stream);
 
@@ -202,9 +204,9 @@ tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
 tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms, int32_t block_edge);
 
 /* Pick the schedule (block edge 2 or 3, threads per block workgroup) with the
- * shortest force-kernel time for the current positions: times `repeats`
- * force evaluations per candidate on `stream` with HIP events
- * (synchronises).  Positions and velocities are not changed, but the list is
+ * shortest time per step for the current positions - one force evaluation
+ * plus 1/rebuild_every of a list build: times `repeats` force evaluations
+ * and one build per candidate on `stream` with HIP events (synchronises).  Positions and velocities are not changed, but the list is
  * rebuilt at the current positions, as by tmd_build_neighbors(); call it
  * right after tmd_set_state() or at a rebuild step to keep the fixed
  * rebuild schedule. */

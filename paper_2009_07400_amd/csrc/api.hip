@@ -632,8 +632,8 @@ tmd_status tmd_get_neighbors(const tmd_system *cs, int32_t *counts, int32_t *ids
     tmd_status st = check_ready(s, true);
     if (st != TMD_OK)
         return st;
-    if (!counts || !ids || capacity < int64_t(s->d.nt) * s->d.maxnb)
-        return fail(s, TMD_EINVAL, "get_neighbors: NULL buffer or capacity below n_atoms * max_neighbors");
+    if (!counts || (ids && capacity < int64_t(s->d.nt) * s->d.maxnb))
+        return fail(s, TMD_EINVAL, "get_neighbors: NULL counts or capacity below n_atoms * max_neighbors");
     if (!s->list_valid)
         return fail(s, TMD_ESTATE, "get_neighbors: no list built since the state was set");
     hipStream_t hs = static_cast<hipStream_t>(stream);
@@ -725,6 +725,22 @@ static hipError_t time_force(tmd_system *s, int32_t repeats, hipStream_t hs, hip
     return e;
 }
 
+// Average time of one list build at the current schedule (it rewrites the
+// same list: positions and binning are unchanged).
+static hipError_t time_build(tmd_system *s, int32_t repeats, hipStream_t hs, hipEvent_t a, hipEvent_t b, float &ms) {
+    hipError_t e = hipEventRecord(a, hs);
+    for (int32_t r = 0; r < repeats && e == hipSuccess; ++r)
+        e = launch_build(s->d, s->b, s->cur, hs);
+    if (e == hipSuccess)
+        e = hipEventRecord(b, hs);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(b);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, a, b);
+    ms /= float(repeats);
+    return e;
+}
+
 tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     tmd_status st = check_ready(s, true);
     if (st != TMD_OK)
@@ -748,8 +764,12 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
         const int32_t t0 = s->d.threads;
         for (int32_t t = std::max(64, t0 - 192); t <= std::min(kMaxThreads, t0 + 192) && e == hipSuccess; t += 64) {
             s->d.threads = t;
-            float ms = 0.0f;
+            // cost per step: one force evaluation plus the list build's share
+            float ms = 0.0f, mb = 0.0f;
             e = time_force(s, repeats, hs, a, b, ms);
+            if (e == hipSuccess)
+                e = time_build(s, 1, hs, a, b, mb);
+            ms += mb / float(s->rebuild_every);
             if (e == hipSuccess && ms < best) {
                 best = ms;
                 best_edge = E;

@@ -509,36 +509,70 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
             for (int k = 0; k < ns[2]; ++k)
                 st[2][k] = axis_index(co[2], n[2], v[k]);
         }
-        int self = i;
-        if (fits) {
-            const int us = (axis_index(co[2], n[2], cz) * n[1] + axis_index(co[1], n[1], cy)) * n[0] +
-                           axis_index(co[0], n[0], cx);
-            self = h.off[us] + (i - h.cs[us]);
-        }
         int c = 0;
-        for (int kz = 0; kz < ns[2]; ++kz)
-            for (int ky = 0; ky < ns[1]; ++ky)
-                for (int kx = 0; kx < ns[0]; ++kx) {
-                    const int u = (st[2][kz] * n[1] + st[1][ky]) * n[0] + st[0][kx];
-                    const int beg = h.off[u], end = h.off[u + 1];
-                    if (fits) {
-                        for (int t = beg; t < end; ++t) {
-                            double dx, dy, dz;
-                            const lds_double *p = lds_slot(S, t);
-                            const double s =
-                                pair_delta(xi, yi, zi, p[0], p[1], p[2], B.L, B.halfL, B.halfL2, dx, dy, dz);
-                            if (s < B.rl2 && t != self) {
-                                if (c < d.maxnb)
-                                    nbr16[nbr_index16(i, c, d.nchunk)] = uint16_t(t);
-                                ++c;
+        if (fits) {
+            const int hx = axis_index(co[0], n[0], cx);
+            const int us = (axis_index(co[2], n[2], cz) * n[1] + axis_index(co[1], n[1], cy)) * n[0] + hx;
+            const int self = h.off[us] + (i - h.cs[us]);
+            // The x-stencil cells of a row: one run of consecutive neighborhood
+            // cells (contiguous LDS slots) whenever their positions along the
+            // neighborhood axis are consecutive, else one run per cell.
+            int lo = st[0][0], hi = st[0][0];
+            for (int k = 1; k < ns[0]; ++k) {
+                lo = min(lo, st[0][k]);
+                hi = max(hi, st[0][k]);
+            }
+            const bool run = hi - lo + 1 == ns[0];
+            const int nrun = run ? 1 : ns[0];
+            uint16_t *wp = nbr16 + nbr_index16(i, 0, d.nchunk);
+            for (int kz = 0; kz < ns[2]; ++kz)
+                for (int ky = 0; ky < ns[1]; ++ky) {
+                    const int row = (st[2][kz] * n[1] + st[1][ky]) * n[0];
+                    for (int q = 0; q < nrun; ++q) {
+                        const int u0 = row + (run ? lo : st[0][q]), u1 = row + (run ? hi : st[0][q]);
+                        const int beg = h.off[u0], end = h.off[u1 + 1];
+                        // four candidates per round, their LDS reads issued together;
+                        // past the end of the run a candidate is the NaN sentinel
+                        for (int t0 = beg; t0 < end; t0 += 4) {
+                            int tt[4];
+                            double px[4], py[4], pz[4];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                tt[r] = t0 + r < end ? t0 + r : d.cap;
+                                const lds_double *p = lds_slot(S, tt[r]);
+                                px[r] = p[0];
+                                py[r] = p[1];
+                                pz[r] = p[2];
+                            }
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                double dx, dy, dz;
+                                const double s = pair_delta(xi, yi, zi, px[r], py[r], pz[r], B.L, B.halfL, B.halfL2,
+                                                            dx, dy, dz);
+                                if (s < B.rl2 && tt[r] != self) {
+                                    // entry c of the 16-bit list: the next element, or the
+                                    // first element of the next 16-byte row of the tile
+                                    if (c < d.maxnb)
+                                        *wp = uint16_t(tt[r]);
+                                    wp += ((c & 7) == 7) ? 505 : 1;
+                                    ++c;
+                                }
                             }
                         }
-                    } else {
+                    }
+                }
+        } else {
+            for (int kz = 0; kz < ns[2]; ++kz)
+                for (int ky = 0; ky < ns[1]; ++ky)
+                    for (int kx = 0; kx < ns[0]; ++kx) {
+                        const int u = (st[2][kz] * n[1] + st[1][ky]) * n[0] + st[0][kx];
+                        const int beg = h.off[u], end = h.off[u + 1];
                         const int g0 = h.cs[u] - beg;
                         for (int t = beg; t < end; ++t) {
                             const int g = g0 + t;
                             double dx, dy, dz;
-                            const double s = pair_delta(xi, yi, zi, x[g], y[g], z[g], B.L, B.halfL, B.halfL2, dx, dy, dz);
+                            const double s =
+                                pair_delta(xi, yi, zi, x[g], y[g], z[g], B.L, B.halfL, B.halfL2, dx, dy, dz);
                             if (s < B.rl2 && g != i) {
                                 if (c < d.maxnb)
                                     nbr[nbr_index(i, c, d.nchunk)] = g;
@@ -546,7 +580,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                             }
                         }
                     }
-                }
+        }
         const int stored = c < d.maxnb ? c : d.maxnb;
         cnt[i] = stored;
         // pad the last chunk and one whole chunk after it (every list has
@@ -910,6 +944,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_export_neighbors(Dims d, const 
     const uint16_t *nbr16 = reinterpret_cast<const uint16_t *>(nbr);
     for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
         const int o = orig[i], c = cnt[i];
+        counts[o] = c;
+        if (!ids)
+            continue;
         int32_t *row = ids + int64_t(o) * d.maxnb;
         for (int k = 0; k < c; ++k) {
             int g = fits ? int(nbr16[nbr_index16(i, k, d.nchunk)]) : nbr[nbr_index(i, k, d.nchunk)];
@@ -927,7 +964,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_export_neighbors(Dims d, const 
         }
         for (int k = c; k < d.maxnb; ++k)
             row[k] = -1;
-        counts[o] = c;
     }
 }
 

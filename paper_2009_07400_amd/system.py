@@ -134,6 +134,12 @@ class System:
         abi.tmd_get_neighbors(self._h, int(counts.data_ptr()), int(ids.data_ptr()), self.n * m, _stream())
         return counts, ids
 
+    def neighbor_counts(self):
+        """List lengths [N] int32 in original atom order."""
+        counts = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        abi.tmd_get_neighbors(self._h, int(counts.data_ptr()), None, 0, _stream())
+        return counts
+
     def sync(self) -> None:
         abi.tmd_sync(self._h, _stream())
         self._keep = []

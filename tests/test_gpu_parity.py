@@ -104,6 +104,7 @@ def test_fcc_lattice_sums_on_gpu():
     assert W / n == pytest.approx(-22.158199254035498, rel=1e-12)
     counts, _ = g.get_neighbors()
     assert (counts.cpu().numpy() == 78).all()
+    assert (g.neighbor_counts().cpu().numpy() == 78).all()  # counts-only export
 
 
 def test_parameters_epsilon_sigma():
