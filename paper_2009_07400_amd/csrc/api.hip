@@ -94,7 +94,7 @@ size_t carve(const Dims &d, char *base, Buffers *out) {
     b.scan_sums = (int32_t *)take((size_t(scan_blocks(d.ncs)) + 1) * 4);
     b.nbr_count = (int32_t *)take(np * 4);
     b.nbr = (int32_t *)take(np * size_t(d.nchunk) * 4 * 4);
-    b.partials = (double *)take(size_t(d.nblk) * kPartialStride * 8);
+    b.partials = (double *)take(size_t(d.nblk) * kMaxParts * kPartialStride * 8);
     b.err = (int32_t *)take(64);
     if (out)
         *out = b;
@@ -187,6 +187,13 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
     return TMD_OK;
 }
 
+// Threads per block workgroup: ~15% above the mean number of atoms one
+// workgroup takes (a block's atoms split over d.parts workgroups).
+int default_threads(const Dims &d) {
+    const double per_wg = double(d.nt) / (double(d.nblk) * d.parts);
+    return std::min(kMaxThreads, std::max(64, round_up(int(per_wg * 1.15), 64)));
+}
+
 // LJ 12-6 constants of one box (Sec. 3.2, Eq. 2) in the forms the kernels use.
 void set_lj(Box &B, double eps, double sigma) {
     const double s2 = sigma * sigma;
@@ -200,6 +207,12 @@ void set_lj(Box &B, double eps, double sigma) {
     B.f6 = B.eps24 * B.sigma6;
     B.u12 = B.eps4 * B.sigma6 * B.sigma6;
     B.u6 = B.eps4 * B.sigma6;
+    B.g14 = 14.0 * B.f12;
+    B.g8 = 8.0 * B.f6;
+    B.e12 = 48.0 * B.sigma6 * B.sigma6;
+    B.e6 = 24.0 * B.sigma6;
+    B.h12 = 12.0 * B.f12 / sigma;
+    B.h6 = 6.0 * B.f6 / sigma;
 }
 
 // Expected atoms in a block neighborhood (E + 2 cells per axis, or the whole
@@ -246,8 +259,9 @@ bool layout_blocks(tmd_system *s, int E) {
             break;
         }
     }
-    const double per_block = double(d.nt) / double(blocks);
-    d.threads = std::min(kMaxThreads, std::max(64, round_up(int(per_block * 1.15), 64)));
+    if (d.parts < 1)
+        d.parts = 1;
+    d.threads = default_threads(d);
     s->blk_box.assign(size_t(blocks), 0);
     for (int32_t k = 0; k < d.nbox; ++k) {
         const Box &B = s->boxes[size_t(k)];
@@ -397,7 +411,7 @@ size_t carve_adj(const Dims &d, int32_t R, int32_t nsteps, char *base, AdjBuf *o
         p->z = (double *)take(np * 8);
     }
     a.lo = (double *)take(6 * nt * 8);
-    a.partials = (double *)take(size_t(d.nblk) * kPartialStride * 8);
+    a.partials = (double *)take(size_t(d.nblk) * kMaxParts * kPartialStride * 8);
     a.acc = (double *)take(size_t(d.nbox) * 2 * 8);
     if (out)
         *out = a;
@@ -683,18 +697,24 @@ tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
     info->block_threads = s->d.threads;
     info->lds_atoms = s->d.cap;
     info->block_edge = s->d.edge;
-    info->reserved_ = 0;
+    info->block_parts = s->d.parts;
     return TMD_OK;
 }
 
-tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, int32_t block_edge) {
+tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, int32_t block_edge,
+                            int32_t block_parts) {
     if (!s || threads < 0 || threads > kMaxThreads || threads % 64 != 0 || lds_atoms < 0 || lds_atoms > kMaxCap ||
-        lds_atoms % 64 != 0 || (block_edge != 0 && block_edge != 2 && block_edge != 3))
+        lds_atoms % 64 != 0 || (block_edge != 0 && block_edge != 2 && block_edge != 3) ||
+        (block_parts != 0 && block_parts != 1 && block_parts != 2 && block_parts != 4))
         return TMD_EINVAL;
     if (block_edge != 0 && block_edge != s->d.edge) {
         layout_blocks(s, block_edge);  // resets threads and capacity to that edge's defaults
         s->list_valid = s->force_valid = false;
         s->gen++;
+    }
+    if (block_parts != 0 && block_parts != s->d.parts) {
+        s->d.parts = block_parts;  // the list does not depend on it
+        s->d.threads = default_threads(s->d);
     }
     if (threads > 0)
         s->d.threads = threads;
@@ -755,25 +775,30 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     if (e != hipSuccess)
         return hip_fail(s, e, "autotune");
     float best = 1e30f;
-    int32_t best_edge = s->d.edge, best_t = s->d.threads;
+    int32_t best_edge = s->d.edge, best_t = s->d.threads, best_p = s->d.parts;
     for (int32_t E = 2; E <= kMaxEdge && e == hipSuccess; ++E) {
         layout_blocks(s, E);
         s->list_valid = s->force_valid = false;
         if ((st = rebuild(s, hs)) != TMD_OK)
             break;
-        const int32_t t0 = s->d.threads;
-        for (int32_t t = std::max(64, t0 - 192); t <= std::min(kMaxThreads, t0 + 192) && e == hipSuccess; t += 64) {
-            s->d.threads = t;
-            // cost per step: one force evaluation plus the list build's share
-            float ms = 0.0f, mb = 0.0f;
-            e = time_force(s, repeats, hs, a, b, ms);
-            if (e == hipSuccess)
-                e = time_build(s, 1, hs, a, b, mb);
-            ms += mb / float(s->rebuild_every);
-            if (e == hipSuccess && ms < best) {
-                best = ms;
-                best_edge = E;
-                best_t = t;
+        for (int32_t P = 1; P <= kMaxParts && e == hipSuccess; P *= 2) {
+            s->d.parts = P;
+            const int32_t t0 = default_threads(s->d);
+            for (int32_t t = std::max(64, t0 - 128); t <= std::min(kMaxThreads, t0 + 128) && e == hipSuccess;
+                 t += 64) {
+                s->d.threads = t;
+                // cost per step: one force evaluation plus the list build's share
+                float ms = 0.0f, mb = 0.0f;
+                e = time_force(s, repeats, hs, a, b, ms);
+                if (e == hipSuccess)
+                    e = time_build(s, 1, hs, a, b, mb);
+                ms += mb / float(s->rebuild_every);
+                if (e == hipSuccess && ms < best) {
+                    best = ms;
+                    best_edge = E;
+                    best_t = t;
+                    best_p = P;
+                }
             }
         }
     }
@@ -784,6 +809,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     if (e != hipSuccess)
         return hip_fail(s, e, "autotune");
     layout_blocks(s, best_edge);
+    s->d.parts = best_p;
     s->d.threads = best_t;
     s->list_valid = s->force_valid = false;
     return rebuild(s, hs);

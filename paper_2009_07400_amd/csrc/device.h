@@ -50,6 +50,26 @@ __device__ __forceinline__ double pair_delta(double xi, double yi, double zi, do
     return s;
 }
 
+// The same pair geometry with |d|^2 formed by fused multiply-adds, for the
+// kernels that evaluate forces and their derivatives: there |d|^2 only
+// decides the cutoff test, and the force kernel and the adjoint's
+// Hessian-vector product must take that decision identically.
+__device__ __forceinline__ double pair_delta_fma(double xi, double yi, double zi, double xj, double yj, double zj,
+                                                double L, double halfL, double halfL2, double &dx, double &dy,
+                                                double &dz) {
+    dx = xi - xj;
+    dy = yi - yj;
+    dz = zi - zj;
+    double s = fma(dz, dz, fma(dy, dy, dx * dx));
+    if (s >= halfL2) {
+        dx = mic(dx, L, halfL);
+        dy = mic(dy, L, halfL);
+        dz = mic(dz, L, halfL);
+        s = fma(dz, dz, fma(dy, dy, dx * dx));
+    }
+    return s;
+}
+
 // 1/s for s > 0: hardware reciprocal estimate refined by one Newton-Raphson
 // step r <- r + r (1 - s r), which squares the estimate's relative error
 // (about 2^-23 or better) to about 2^-46, far inside the 1e-12 per-atom

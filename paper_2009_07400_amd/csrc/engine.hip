@@ -39,6 +39,15 @@ __device__ __forceinline__ int xcd_remap() {
     return (b % kNumXcd) * (nb / kNumXcd) + b / kNumXcd;
 }
 
+// Workgroup -> (block, part): d.parts workgroups share one block, each taking
+// a contiguous share of its atoms (and staging the whole neighborhood).
+__device__ __forceinline__ bool block_part(const Dims &d, int &b, int &part) {
+    const int wg = xcd_remap();
+    b = wg / d.parts;
+    part = wg - b * d.parts;
+    return b < d.nblk;
+}
+
 // Block coordinate and offset inside the block of cell coordinate c.
 __device__ __forceinline__ void split_edge(int c, int E, int &blk, int &loc) {
     blk = (E == 2) ? (c >> 1) : (c / 3);
@@ -95,6 +104,13 @@ struct Hood {
     int off[kMaxHood + 1];  // LDS slot of each cell's first atom; off[ncell] = atoms staged
     int ncell;
     int a0, a1;             // the block's own atoms
+
+    // the atoms of share `part` of `parts`
+    __device__ __forceinline__ void share(int part, int parts, int &lo, int &hi) const {
+        const int n = a1 - a0;
+        lo = a0 + (n * part) / parts;
+        hi = a0 + (n * (part + 1)) / parts;
+    }
 };
 
 __device__ __forceinline__ int wave_prefix_incl(int v) {
@@ -163,6 +179,25 @@ __device__ __forceinline__ int hood_find(const Hood &h, int t) {
     return lo;
 }
 
+// hood_find for R slots at once: a fixed seven-step branchless search
+// (kMaxHood < 128) whose R table reads per step are independent, so a thread
+// waits for seven LDS round trips instead of seven per slot.  off[ncell]
+// exceeds every slot, so probes past the last cell read it and never move.
+template <int R>
+__device__ __forceinline__ void hood_find_n(const Hood &h, const int (&t)[R], int (&u)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        u[r] = 0;
+#pragma unroll
+    for (int step = 64; step > 0; step >>= 1) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int m = min(u[r] + step, h.ncell);
+            u[r] = h.off[m] <= t[r] ? m : u[r];
+        }
+    }
+}
+
 // LDS copy of a neighborhood: packed (x, y, z) triples, 24 bytes per slot,
 // addressed with 32-bit LDS pointers (one 24-bit multiply-add per atom, then
 // ds_read2_b64 + ds_read_b64 with immediate offsets).
@@ -209,13 +244,14 @@ __device__ __forceinline__ void hood_stage(const Hood &h, int total, int sent, c
     constexpr int R = 4;
     const int T = blockDim.x;
     for (int base = threadIdx.x; base < total; base += R * T) {
-        int g[R];
+        int ts[R], us[R], g[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int t = min(base + r * T, total - 1);
-            const int u = hood_find(h, t);
-            g[r] = h.cs[u] + (t - h.off[u]);
-        }
+        for (int r = 0; r < R; ++r)
+            ts[r] = min(base + r * T, total - 1);
+        hood_find_n<R>(h, ts, us);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            g[r] = h.cs[us[r]] + (ts[r] - h.off[us[r]]);
         double px[R], py[R], pz[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -476,12 +512,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                                                        int32_t *err) {
     __shared__ Hood h;
     extern __shared__ double lds[];
-    const int b = xcd_remap();
-    if (b >= d.nblk)
+    int b, part;
+    if (!block_part(d, b, part))
         return;
     const Box B = block_box(d, boxes, blk_box, b);
     const int lb = b - B.block_off;
     hood_setup(B, lb, cell_start, h);
+    int lo, hi;
+    h.share(part, d.parts, lo, hi);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     lds_double *S = (lds_double *)lds;
@@ -492,7 +530,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     uint16_t *nbr16 = reinterpret_cast<uint16_t *>(nbr);
     int n[3], co[3][kAxis];
     hood_axes(B, lb, n, co);
-    for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         const double xi = x[i], yi = y[i], zi = z[i];
         const int cx = cell_coord(xi, B.side, B.nc), cy = cell_coord(yi, B.side, B.nc),
                   cz = cell_coord(zi, B.side, B.nc);
@@ -587,7 +625,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
         // room for it: nchunk = ceil(maxnb / 4) + 1); force loops read that
         // chunk in place of any chunk past the end
         if (fits) {
-            for (int k = stored; k < ((stored + 7) & ~7) + 8; ++k)
+            // (at least through row 1: the force kernel loads rows 0 and 1
+            // before it knows the count)
+            for (int k = stored; k < max(((stored + 7) & ~7) + 8, 16); ++k)
                 nbr16[nbr_index16(i, k, d.nchunk)] = uint16_t(sentinel);
         } else {
             for (int k = stored; k < ((stored + 3) & ~3) + 4; ++k)
@@ -627,14 +667,8 @@ __device__ __forceinline__ void eval2(const Duo &q, double xi, double yi, double
                                       double mu6, double &ax, double &ay, double &az, double &u, double &w) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-        double dx = xi - q.x[m], dy = yi - q.y[m], dz = zi - q.z[m];
-        double s = fma(dz, dz, fma(dy, dy, dx * dx));
-        if (s >= B.halfL2) {
-            dx = mic(dx, B.L, B.halfL);
-            dy = mic(dy, B.L, B.halfL);
-            dz = mic(dz, B.L, B.halfL);
-            s = fma(dz, dz, fma(dy, dy, dx * dx));
-        }
+        double dx, dy, dz;
+        const double s = pair_delta_fma(xi, yi, zi, q.x[m], q.y[m], q.z[m], B.L, B.halfL, B.halfL2, dx, dy, dz);
         if (s < B.rc2) {
             const double sr2 = recip(s);
             const double q3 = sr2 * sr2 * sr2;
@@ -719,18 +753,17 @@ __device__ __forceinline__ void fetch2w(const LdsPos &pos, int word, Duo &q) {
 // the bytes of the 32-bit list per entry.  The body covers two chunks, with
 // the same look-ahead discipline (index chunks one to two chunks ahead,
 // positions two entries ahead, unconditional memory operations, the chunk
-// after the last standing in for every chunk past the end).  The only exit
+// after the last standing in for every chunk past the end).  The caller
+// passes rows 0 and 1, which every 16-bit list fills (with sentinels past
+// the count), so it can load them before the count is known.  The only exit
 // is at the end of the body: a loop with several exits loses the exact wait
 // counts at its head.
 template <bool THERMO>
-__device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, int c, const LdsPos &pos, double xi,
-                                           double yi, double zi, const Box &B, double mf6, double mu6,
+__device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int c, const LdsPos &pos,
+                                           double xi, double yi, double zi, const Box &B, double mf6, double mu6,
                                            double &ax, double &ay, double &az, double &u, double &w) {
     const int nch = (c + 7) >> 3;
     auto ld = [&](int k) { return __builtin_nontemporal_load(chunks + (k < nch ? k : nch) * 64); };
-    v4i i0 = ld(0);
-    __builtin_amdgcn_sched_barrier(0);
-    v4i i1 = ld(1);
     Duo P, Q;
     fetch2w(pos, i0[0], P);
     for (int k = 0;; k += 2) {
@@ -782,8 +815,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
                                                        double *__restrict__ partials, int32_t *err) {
     __shared__ Hood h;
     extern __shared__ double lds[];
-    const int b = xcd_remap();
-    if (b >= d.nblk)
+    int b, part;
+    if (!block_part(d, b, part))
         return;
     const Box B = block_box(d, boxes, blk_box, b);
     // -f6 and -u6 live in vector registers: each fma of the pair loop that
@@ -800,11 +833,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     // barrier, so their latency overlaps the staging.  Past the block's last
     // atom the loads read that atom again (a cache hit) and are not used.
     const int T = blockDim.x;
-    int i = h.a0 + threadIdx.x;
+    int lo, hi;
+    h.share(part, d.parts, lo, hi);
+    int i = lo + threadIdx.x;
     double xi = 0.0, yi = 0.0, zi = 0.0, vxi = 0.0, vyi = 0.0, vzi = 0.0;
     int ci = 0;
+    v4i r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0};
     auto load_atom = [&](int k) {
-        const int ic = min(k, h.a1 - 1);
+        const int ic = min(k, hi - 1);
         xi = x[ic];
         yi = y[ic];
         zi = z[ic];
@@ -814,8 +850,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
             vyi = vy[ic];
             vzi = vz[ic];
         }
+        if (fits) {  // rows 0 and 1 of the 16-bit list
+            const v4i *ch = list_chunks(nbr, ic, d.nchunk);
+            r0 = __builtin_nontemporal_load(ch);
+            r1 = __builtin_nontemporal_load(ch + 64);
+        }
     };
-    if (h.a1 > h.a0)
+    if (hi > lo)
         load_atom(i);
     if (fits)
         hood_stage(h, total, d.cap, x, y, z, spos.s);
@@ -823,11 +864,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     // load still in flight at the pair loop's head costs it exact LDS waits
     asm volatile("" ::"s"(err), "s"(partials), "s"(xo), "s"(fx));
     double u = 0.0, w = 0.0, ke = 0.0;
-    for (; i < h.a1; i += T) {
+    for (; i < hi; i += T) {
         double ax = 0.0, ay = 0.0, az = 0.0;
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
         if (fits)
-            pair_sum16<THERMO>(chunks, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+            pair_sum16<THERMO>(chunks, r0, r1, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         else
             pair_sum<THERMO>(chunks, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         if (MODE == 0 || MODE == 1) {
@@ -862,9 +903,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     if (THERMO) {
         block_sum3(u, w, ke);
         if (threadIdx.x == 0) {
-            partials[b * kPartialStride + 0] = u;
-            partials[b * kPartialStride + 1] = w;
-            partials[b * kPartialStride + 2] = ke;
+            const int q = b * d.parts + part;
+            partials[q * kPartialStride + 0] = u;
+            partials[q * kPartialStride + 1] = w;
+            partials[q * kPartialStride + 2] = ke;
         }
     }
 }
@@ -896,13 +938,14 @@ __global__ __launch_bounds__(kAtomThreads) void k_drift(Dims d, const Box *__res
         atomicOr(err, kErrNonFinite);
 }
 
-// One wavefront per box sums that box's block partials in a fixed order.
+// One wavefront per box sums that box's workgroup partials (parts per
+// block) in a fixed order.
 __global__ __launch_bounds__(64) void k_reduce(const Box *__restrict__ boxes, const double *__restrict__ partials,
-                                               double *out, int row_len) {
+                                               int parts, double *out, int row_len) {
     const Box &B = boxes[blockIdx.x];
     double u = 0.0, w = 0.0, k = 0.0;
-    for (int q = threadIdx.x; q < B.nblocks; q += 64) {
-        const int blk = B.block_off + q;
+    for (int q = threadIdx.x; q < B.nblocks * parts; q += 64) {
+        const int blk = B.block_off * parts + q;
         u += partials[blk * kPartialStride + 0];
         w += partials[blk * kPartialStride + 1];
         k += partials[blk * kPartialStride + 2];
@@ -975,35 +1018,152 @@ __device__ __forceinline__ lds_double *lds_slot6(lds_double *base, int slot) {
     return (lds_double *)((lds_char *)base + __umul24(unsigned(slot), 48u));
 }
 
-__device__ __forceinline__ void hood_stage6(const Hood &h, int total, const Pos &x, const Pos &w, lds_double *s) {
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int u = hood_find(h, t);
-        const int g = h.cs[u] + (t - h.off[u]);
-        lds_double *a = lds_slot6(s, t);
-        a[0] = x.x[g];
-        a[1] = x.y[g];
-        a[2] = x.z[g];
-        a[3] = w.x[g];
-        a[4] = w.y[g];
-        a[5] = w.z[g];
+__device__ __forceinline__ void hood_stage6(const Hood &h, int total, int sent, const Pos &x, const Pos &w,
+                                            lds_double *s) {
+    // as hood_stage: four slots per thread per round, unconditional memory
+    // operations, a slot past the end copied into the scratch slot sent + 1
+    constexpr int R = 4;
+    const int T = blockDim.x;
+    for (int base = threadIdx.x; base < total; base += R * T) {
+        int ts[R], us[R], g[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            ts[r] = min(base + r * T, total - 1);
+        hood_find_n<R>(h, ts, us);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            g[r] = h.cs[us[r]] + (ts[r] - h.off[us[r]]);
+        double v[R][6];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            v[r][0] = x.x[g[r]];
+            v[r][1] = x.y[g[r]];
+            v[r][2] = x.z[g[r]];
+            v[r][3] = w.x[g[r]];
+            v[r][4] = w.y[g[r]];
+            v[r][5] = w.z[g[r]];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            lds_double *a = lds_slot6(s, base + r * T < total ? base + r * T : sent + 1);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                a[k] = v[r][k];
+        }
     }
     if (threadIdx.x == 0) {
-        lds_double *a = lds_slot6(s, total);
+        lds_double *a = lds_slot6(s, sent);
         a[0] = a[1] = a[2] = __builtin_nan("");
         a[3] = a[4] = a[5] = 0.0;
     }
     __syncthreads();
 }
 
+// Positions and w of two list entries.
+struct Duo6 {
+    double x[2], y[2], z[2], wx[2], wy[2], wz[2];
+};
+
+__device__ __forceinline__ void fetch2w6(lds_double *S, int word, Duo6 &q) {
+    const unsigned wd = unsigned(word);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const lds_double *a = lds_slot6(S, int(m == 0 ? (wd & 0xffffu) : (wd >> 16)));
+        q.x[m] = a[0];
+        q.y[m] = a[1];
+        q.z[m] = a[2];
+        q.wx[m] = a[3];
+        q.wy[m] = a[4];
+        q.wz[m] = a[5];
+    }
+}
+
+// Constants of the reverse pair terms that live in vector registers (each
+// fma that uses them already reads one scalar operand).
+struct HvpConst {
+    double mf6, me6, mh6, g8;
+};
+
+// Reverse-mode terms of one pair (the cutoff decision is the force kernel's:
+// same geometry, same fused |d|^2):
+//   (J w)_i += f(s) u + 2 f'(s) (d . u) d,  u = w_i - w_j,
+//   pe += (df/deps) (w_i . d),  ps += (df/dsigma) (w_i . d),
+// with q = sr2^3, f = sr2 q (f12 q - f6), 2 f' = sr2^2 q (g8 - g14 q),
+// df/deps = sr2 q (e12 q - e6), df/dsigma = sr2 q (h12 q - h6).
+__device__ __forceinline__ void hvp_pair(double xj, double yj, double zj, double wxj, double wyj, double wzj,
+                                         double xi, double yi, double zi, double wxi, double wyi, double wzi,
+                                         const Box &B, const HvpConst &k, double &gx, double &gy, double &gz,
+                                         double &pe, double &ps) {
+    double dx, dy, dz;
+    const double s = pair_delta_fma(xi, yi, zi, xj, yj, zj, B.L, B.halfL, B.halfL2, dx, dy, dz);
+    if (s < B.rc2) {
+        const double sr2 = recip_exact(s);
+        const double q3 = sr2 * sr2 * sr2;
+        const double a = sr2 * q3;
+        const double f = a * fma(B.f12, q3, k.mf6);
+        const double fe = a * fma(B.e12, q3, k.me6);
+        const double fs = a * fma(B.h12, q3, k.mh6);
+        const double c2 = (sr2 * a) * fma(-B.g14, q3, k.g8);
+        const double ux = wxi - wxj, uy = wyi - wyj, uz = wzi - wzj;
+        const double t2 = c2 * fma(dz, uz, fma(dy, uy, dx * ux));
+        gx = fma(f, ux, fma(t2, dx, gx));
+        gy = fma(f, uy, fma(t2, dy, gy));
+        gz = fma(f, uz, fma(t2, dz, gz));
+        const double wd = fma(wzi, dz, fma(wyi, dy, wxi * dx));
+        pe = fma(fe, wd, pe);
+        ps = fma(fs, wd, ps);
+    }
+}
+
+// hvp terms over a 16-bit list, with pair_sum16's loop discipline.
+__device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int c, lds_double *S,
+                                          double xi, double yi, double zi, double wxi, double wyi, double wzi,
+                                          const Box &B, const HvpConst &k, double &gx, double &gy, double &gz,
+                                          double &pe, double &ps) {
+    const int nch = (c + 7) >> 3;
+    auto ld = [&](int kk) { return __builtin_nontemporal_load(chunks + (kk < nch ? kk : nch) * 64); };
+    auto ev = [&](const Duo6 &q) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+            hvp_pair(q.x[m], q.y[m], q.z[m], q.wx[m], q.wy[m], q.wz[m], xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz,
+                     pe, ps);
+    };
+    Duo6 P, Q;
+    fetch2w6(S, i0[0], P);
+    for (int kk = 0;; kk += 2) {
+        fetch2w6(S, i0[1], Q);
+        ev(P);
+        fetch2w6(S, i0[2], P);
+        ev(Q);
+        fetch2w6(S, i0[3], Q);
+        ev(P);
+        fetch2w6(S, i1[0], P);
+        i0 = ld(kk + 2);
+        ev(Q);
+        fetch2w6(S, i1[1], Q);
+        ev(P);
+        fetch2w6(S, i1[2], P);
+        ev(Q);
+        fetch2w6(S, i1[3], Q);
+        ev(P);
+        fetch2w6(S, i0[0], P);
+        i1 = ld(kk + 3);
+        ev(Q);
+        if (!__any(kk + 2 < nch))
+            break;
+    }
+    __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) expcnt(7) lgkmcnt(0)
+}
+
 // Reverse-mode step at one force evaluation of the velocity-Verlet map,
 // with the list and the cutoff indicators of the forward run held fixed.
 // For w = lam_v (one lane per atom, one workgroup per block):
 //   (J w)_i = sum_{j in list(i), s < rc^2} [ f(s) (w_i - w_j) + 2 f'(s) ((w_i - w_j) . d_ij) d_ij ]
-// with f' = df/ds = sr2^2 sr6 (96 eps - 336 eps sr6);  lam_x_i += c (J w)_i,
-// c = mult * dt / (2 m).  The block's partial sums of w_i . dF_i/deps
-// (df/deps = f / eps) and w_i . dF_i/dsigma (df/dsigma = (eps / sigma) sr2
-// sr6 (576 sr6 - 144)) go to `partials`.  With drift_adj the adjoint of the
-// drift before this force evaluation follows: wout_i = w_i + dt lam_x_i.
+// (the terms of hvp_pair); lam_x_i += c (J w)_i, c = mult * dt / (2 m).  The
+// workgroup's partial sums of w_i . dF_i/deps and w_i . dF_i/dsigma go to
+// `partials`.  With drift_adj the adjoint of the drift before this force
+// evaluation follows: wout_i = w_i + dt lam_x_i.  The neighborhood is staged
+// with w (48 bytes per slot).
 __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restrict__ boxes,
                                                      const int32_t *__restrict__ blk_box, Pos x,
                                                      const int32_t *__restrict__ cell_start,
@@ -1012,59 +1172,36 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
                                                      double mult, int drift_adj, double *__restrict__ partials) {
     __shared__ Hood h;
     extern __shared__ double lds[];
-    const int b = xcd_remap();
-    if (b >= d.nblk)
+    int b, part;
+    if (!block_part(d, b, part))
         return;
     const Box B = block_box(d, boxes, blk_box, b);
+    HvpConst k{-B.f6, -B.e6, -B.h6, B.g8};
+    asm volatile("" : "+v"(k.mf6), "+v"(k.me6), "+v"(k.mh6), "+v"(k.g8));
     hood_setup(B, b - B.block_off, cell_start, h);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     lds_double *S = (lds_double *)lds;
     if (fits)
-        hood_stage6(h, total, x, w, S);
-    const uint16_t *nbr16 = reinterpret_cast<const uint16_t *>(nbr);
+        hood_stage6(h, total, d.cap, x, w, S);
+    asm volatile("" ::"s"(partials), "s"(wout.x), "s"(lam.x));
     double pe = 0.0, ps = 0.0, unused = 0.0;
-    for (int i = h.a0 + threadIdx.x; i < h.a1; i += blockDim.x) {
+    int lo, hi;
+    h.share(part, d.parts, lo, hi);
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         const double xi = x.x[i], yi = x.y[i], zi = x.z[i];
         const double wxi = w.x[i], wyi = w.y[i], wzi = w.z[i];
         double gx = 0.0, gy = 0.0, gz = 0.0;
         const int c = cnt[i];
-        for (int k = 0; k < c; ++k) {
-            const int j = fits ? int(nbr16[nbr_index16(i, k, d.nchunk)]) : nbr[nbr_index(i, k, d.nchunk)];
-            double xj, yj, zj, wxj, wyj, wzj;
-            if (fits) {
-                const lds_double *a = lds_slot6(S, j);
-                xj = a[0];
-                yj = a[1];
-                zj = a[2];
-                wxj = a[3];
-                wyj = a[4];
-                wzj = a[5];
-            } else {
-                xj = x.x[j];
-                yj = x.y[j];
-                zj = x.z[j];
-                wxj = w.x[j];
-                wyj = w.y[j];
-                wzj = w.z[j];
-            }
-            double dx, dy, dz;
-            const double s = pair_delta(xi, yi, zi, xj, yj, zj, B.L, B.halfL, B.halfL2, dx, dy, dz);
-            if (s < B.rc2) {
-                const double sr2 = recip_exact(s);
-                const double sr6 = sr2 * sr2 * sr2 * B.sigma6;
-                const double q = sr2 * sr6;
-                const double fe = q * (48.0 * sr6 - 24.0);  // f / eps
-                const double f = B.eps * fe;
-                const double fp = sr2 * q * B.eps * (96.0 - 336.0 * sr6);
-                const double ux = wxi - wxj, uy = wyi - wyj, uz = wzi - wzj;
-                const double t2 = 2.0 * fp * (dx * ux + dy * uy + dz * uz);
-                gx += f * ux + t2 * dx;
-                gy += f * uy + t2 * dy;
-                gz += f * uz + t2 * dz;
-                const double wd = wxi * dx + wyi * dy + wzi * dz;
-                pe += fe * wd;
-                ps += B.eps_over_sigma * q * (576.0 * sr6 - 144.0) * wd;
+        const v4i *chunks = list_chunks(nbr, i, d.nchunk);
+        if (fits) {
+            hvp_sum16(chunks, __builtin_nontemporal_load(chunks), __builtin_nontemporal_load(chunks + 64), c, S, xi,
+                      yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
+        } else {
+            for (int kk = 0; kk < c; ++kk) {
+                const int j = nbr[nbr_index(i, kk, d.nchunk)];
+                hvp_pair(x.x[j], x.y[j], x.z[j], w.x[j], w.y[j], w.z[j], xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy,
+                         gz, pe, ps);
             }
         }
         const double cc = mult * B.h;
@@ -1080,20 +1217,20 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
     }
     block_sum3(pe, ps, unused);
     if (threadIdx.x == 0) {
-        partials[b * kPartialStride + 0] = pe;
-        partials[b * kPartialStride + 1] = ps;
+        partials[(b * d.parts + part) * kPartialStride + 0] = pe;
+        partials[(b * d.parts + part) * kPartialStride + 1] = ps;
     }
 }
 
 // acc[2 box + q] += mult * h * (sum over the box's blocks of partial q), one
 // wavefront per box, fixed order.
 __global__ __launch_bounds__(64) void k_grad_reduce(const Box *__restrict__ boxes,
-                                                    const double *__restrict__ partials, double mult,
+                                                    const double *__restrict__ partials, int parts, double mult,
                                                     double *acc) {
     const Box &B = boxes[blockIdx.x];
     double e = 0.0, s = 0.0;
-    for (int q = threadIdx.x; q < B.nblocks; q += 64) {
-        const int blk = B.block_off + q;
+    for (int q = threadIdx.x; q < B.nblocks * parts; q += 64) {
+        const int blk = B.block_off * parts + q;
         e += partials[blk * kPartialStride + 0];
         s += partials[blk * kPartialStride + 1];
     }
@@ -1167,7 +1304,7 @@ hipError_t launch_gather(const Dims &d, const double *const src[3], const int32_
 
 hipError_t launch_hvp(const Dims &d, Buffers &b, const Pos &x, const Pos &w, const Pos &lam_x, const Pos &wout,
                       double mult, bool drift_adj, double *partials, hipStream_t s) {
-    k_hvp<<<block_grid(d.nblk), d.threads, 2 * hood_lds_bytes(d.cap), s>>>(
+    k_hvp<<<block_grid(d.nblk * d.parts), d.threads, 2 * hood_lds_bytes(d.cap), s>>>(
         d, b.boxes, b.blk_box, x, b.cell_start, b.nbr_count, b.nbr, w, lam_x, wout, mult, drift_adj ? 1 : 0,
         partials);
     return hipGetLastError();
@@ -1175,7 +1312,7 @@ hipError_t launch_hvp(const Dims &d, Buffers &b, const Pos &x, const Pos &w, con
 
 hipError_t launch_grad_reduce(const Dims &d, const Buffers &b, const double *partials, double mult, double *acc,
                               hipStream_t s) {
-    k_grad_reduce<<<d.nbox, 64, 0, s>>>(b.boxes, partials, mult, acc);
+    k_grad_reduce<<<d.nbox, 64, 0, s>>>(b.boxes, partials, d.parts, mult, acc);
     return hipGetLastError();
 }
 
@@ -1233,14 +1370,14 @@ hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
 }
 
 hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
-    k_build<<<block_grid(d.nblk), d.threads, hood_lds_bytes(d.cap), s>>>(
+    k_build<<<block_grid(d.nblk * d.parts), d.threads, hood_lds_bytes(d.cap), s>>>(
         d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.nbr_count, b.nbr, b.err);
     return hipGetLastError();
 }
 
 template <int MODE, bool THERMO>
 static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
-    k_force<MODE, THERMO><<<block_grid(d.nblk), d.threads, hood_lds_bytes(d.cap), s>>>(
+    k_force<MODE, THERMO><<<block_grid(d.nblk * d.parts), d.threads, hood_lds_bytes(d.cap), s>>>(
         d, b.boxes, b.blk_box, in.x, in.y, in.z, b.cell_start, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
         b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
 }
@@ -1274,7 +1411,7 @@ hipError_t launch_drift(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const Dims &d, const Buffers &b, double *out, int row_len, hipStream_t s) {
-    k_reduce<<<d.nbox, 64, 0, s>>>(b.boxes, b.partials, out, row_len);
+    k_reduce<<<d.nbox, 64, 0, s>>>(b.boxes, b.partials, d.parts, out, row_len);
     return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@ constexpr int kMaxEdge = 3;        // cells per block edge: 2 or 3
 constexpr int kMaxHood = 125;      // cells in a block neighborhood (at most edge + 2 per axis)
 constexpr int kMaxThreads = 1024;  // threads per block workgroup (upper bound)
 constexpr int kAtomThreads = 256;  // threads per workgroup of per-atom kernels
+constexpr int kMaxParts = 4;       // workgroups per block, at most
 
 // Bits of the device error word err[0].
 constexpr int kErrOverflow = 1;
@@ -38,6 +39,12 @@ struct Box {
     double eps_over_sigma;   // d f / d sigma = (eps / sigma) sr2 sr6 (576 sr6 - 144)
     double f12, f6;          // 48 eps sigma^12, 24 eps sigma^6: f = sr2 q (f12 q - f6) with q = sr2^3
     double u12, u6;          // 4 eps sigma^12, 4 eps sigma^6: pair energy q (u12 q - u6)
+    // derivative constants (q = sr2^3): df/ds = sr2^2 q (4 f6 - 7 f12 q), so
+    // 2 df/ds = sr2^2 q (g8 - g14 q); df/deps = sr2 q (e12 q - e6);
+    // df/dsigma = sr2 q (h12 q - h6)
+    double g14, g8;          // 14 f12, 8 f6
+    double e12, e6;          // f12 / eps, f6 / eps
+    double h12, h6;          // 12 f12 / sigma, 6 f6 / sigma
     double h, dt, mass;      // half kick dt / (2 m), time step, mass
 };
 
@@ -54,7 +61,7 @@ struct Dims {
     int32_t cap;      // atoms a block neighborhood may stage in LDS
     int32_t threads;  // threads per block workgroup (64..kMaxThreads, multiple of 64)
     int32_t nchunk;   // 4-entry list chunks per atom: ceil(maxnb / 4) + 1 (a spare chunk of padding)
-    int32_t pad_;
+    int32_t parts;    // workgroups per block (1, 2 or 4), each taking a share of the block's atoms
 };
 
 // Neighbor list layout: neighbor-major within tiles of 64 atoms (one
@@ -93,7 +100,7 @@ struct Buffers {
     int32_t *cell_of, *slot, *tmp_idx;
     int32_t *cell_count, *cell_start, *scan_sums;
     int32_t *nbr_count, *nbr;
-    double *partials;      // [nblk][kPartialStride]
+    double *partials;      // [nblk * parts][kPartialStride]
     int32_t *err;          // [0] flags, [1] largest list length requested on overflow
 };
 

@@ -57,7 +57,8 @@ def test_cells_per_axis_of_the_cases():
     assert [oracle.cells_per_axis(L, 2.8) for _, _, L, _, _ in _states()] == [2, 3, 4, 5, 7]
 
 
-@pytest.mark.parametrize("sched", [{}, {"lds_atoms": 64}, {"threads": 64}, {"threads": 256, "lds_atoms": 2560}])
+@pytest.mark.parametrize("sched", [{}, {"lds_atoms": 64}, {"threads": 64}, {"threads": 256, "lds_atoms": 2560},
+                                   {"block_parts": 2}, {"block_parts": 4, "threads": 64}])
 def test_batch_lists_and_forces_match_oracle(sched):
     states = _states()
     g = _batch(states, **sched)
@@ -117,16 +118,18 @@ def test_batch_equals_single_box_runs_bitwise():
         off += n
 
 
-@pytest.mark.parametrize("threads,lds,edge", [(64, 0, 2), (128, 0, 2), (192, 0, 2), (256, 0, 2), (0, 64, 2),
-                                              (0, 0, 3), (384, 0, 3), (1024, 0, 3), (0, 64, 3)])
-def test_schedule_does_not_change_trajectory(threads, lds, edge):
+@pytest.mark.parametrize("threads,lds,edge,parts", [(64, 0, 2, 1), (128, 0, 2, 1), (192, 0, 2, 1), (256, 0, 2, 1),
+                                                    (0, 64, 2, 1), (0, 0, 3, 1), (384, 0, 3, 1), (1024, 0, 3, 1),
+                                                    (0, 64, 3, 1), (0, 0, 2, 2), (64, 0, 2, 4), (0, 0, 3, 2),
+                                                    (128, 0, 3, 4), (0, 64, 3, 4)])
+def test_schedule_does_not_change_trajectory(threads, lds, edge, parts):
     s = md_system(9, seed=21)  # 5 cells per axis: edge blocks 1 (E = 2) or 2 (E = 3) cells thick
     ref = System(s.n, s.L)
     ref.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
     ref.integrate(30)
     p0, v0, _ = ref.get_state()
     g = System(s.n, s.L)
-    g.set_schedule(threads=threads, lds_atoms=lds, block_edge=edge)
+    g.set_schedule(threads=threads, lds_atoms=lds, block_edge=edge, block_parts=parts)
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
     g.integrate(30)
     p1, v1, _ = g.get_state()
@@ -141,10 +144,10 @@ def test_autotune_keeps_state():
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
     g.integrate(5)
     p0, v0, _ = g.get_state()
-    edge, t = g.autotune(repeats=2)
+    edge, parts, t = g.autotune(repeats=2)
     p1, v1, _ = g.get_state()
     g.sync()
-    assert edge in (2, 3) and t % 64 == 0 and 64 <= t <= 1024
+    assert edge in (2, 3) and parts in (1, 2, 4) and t % 64 == 0 and 64 <= t <= 1024
     assert torch.equal(p0, p1) and torch.equal(v0, v1)
 
 
