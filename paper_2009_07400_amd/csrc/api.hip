@@ -94,6 +94,7 @@ size_t carve(const Dims &d, char *base, Buffers *out) {
     b.scan_sums = (int32_t *)take((size_t(scan_blocks(d.ncs)) + 1) * 4);
     b.nbr_count = (int32_t *)take(np * 4);
     b.nbr = (int32_t *)take(np * size_t(d.nchunk) * 4 * 4);
+    b.hood_tab = (int32_t *)take(size_t(d.nblk) * kHoodWords * 4);
     b.partials = (double *)take(size_t(d.nblk) * kMaxParts * kPartialStride * 8);
     b.err = (int32_t *)take(64);
     if (out)

@@ -131,7 +131,15 @@ __device__ __forceinline__ void hood_setup(const Box &B, int lb, const int32_t *
         int n[3], co[3][kAxis];
         hood_axes(B, lb, n, co);
         const int nh = n[0] * n[1] * n[2];
-        // all cell_start reads first (one memory round trip), then the scans
+        // all cell_start reads first (one memory round trip, the block's own
+        // atom range included), then the scans
+        const int cpb = B.edge * B.edge * B.edge;
+        const int first = B.cell_off + lb * cpb;
+        int a01[2] = {0, 0};
+        if (threadIdx.x == 0) {
+            a01[0] = cell_start[first];
+            a01[1] = cell_start[first + cpb];
+        }
         int cs[2] = {0, 0}, cnt[2] = {0, 0};
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
@@ -157,12 +165,28 @@ __device__ __forceinline__ void hood_setup(const Box &B, int lb, const int32_t *
         if (threadIdx.x == 0) {
             h.off[0] = 0;
             h.ncell = nh;
-            const int cpb = B.edge * B.edge * B.edge;
-            const int first = B.cell_off + lb * cpb;
-            h.a0 = cell_start[first];
-            h.a1 = cell_start[first + cpb];
+            h.a0 = a01[0];
+            h.a1 = a01[1];
         }
     }
+    __syncthreads();
+}
+
+static_assert(sizeof(Hood) <= kHoodWords * 4, "neighborhood table");
+
+// The list build stores each block's table (hood_setup's result) in HBM; the
+// kernels that run on that list read it back in one coalesced round trip
+// instead of recomputing it from cell_start.  Ends with a workgroup barrier.
+__device__ __forceinline__ void hood_store(const Hood &h, int b, int32_t *__restrict__ tab) {
+    const int *src = reinterpret_cast<const int *>(&h);
+    for (int t = threadIdx.x; t < int(sizeof(Hood) / 4); t += blockDim.x)
+        tab[int64_t(b) * kHoodWords + t] = src[t];
+}
+
+__device__ __forceinline__ void hood_load(const int32_t *__restrict__ tab, int b, Hood &h) {
+    int *dst = reinterpret_cast<int *>(&h);
+    for (int t = threadIdx.x; t < int(sizeof(Hood) / 4); t += blockDim.x)
+        dst[t] = tab[int64_t(b) * kHoodWords + t];
     __syncthreads();
 }
 
@@ -381,7 +405,27 @@ __global__ __launch_bounds__(kAtomThreads) void k_bin_count(Dims d, const Box *_
     const int c = cell_slot(B, cell_coord(px, B.side, B.nc), cell_coord(py, B.side, B.nc),
                             cell_coord(pz, B.side, B.nc));
     cell_of[i] = c;
-    slot[i] = atomicAdd(&cell_count[c], 1);
+    // One atomic per distinct cell of the wavefront (atoms arrive nearly
+    // cell-sorted, so a wavefront spans a few cells): the first remaining
+    // lane's cell is counted for every lane that shares it, and those lanes
+    // take consecutive slots in lane order.  (The slot order within a cell is
+    // arbitrary; the later rank by original id makes it deterministic.)
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(1);
+    int s = 0;
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int c0 = __shfl(c, leader, 64);
+        const uint64_t m = __ballot(c == c0);
+        int base = 0;
+        if (lane == leader)
+            base = atomicAdd(&cell_count[c0], __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (c == c0)
+            s = base + __popcll(m & ((uint64_t(1) << lane) - 1));
+        todo &= ~m;
+    }
+    slot[i] = s;
 }
 
 // Exclusive scan, level 1: each workgroup scans a tile of kScanTile counts
@@ -508,8 +552,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                                                        const double *__restrict__ x, const double *__restrict__ y,
                                                        const double *__restrict__ z,
                                                        const int32_t *__restrict__ cell_start,
-                                                       int32_t *__restrict__ cnt, int32_t *__restrict__ nbr,
-                                                       int32_t *err) {
+                                                       int32_t *__restrict__ hood_tab, int32_t *__restrict__ cnt,
+                                                       int32_t *__restrict__ nbr, int32_t *err) {
     __shared__ Hood h;
     extern __shared__ double lds[];
     int b, part;
@@ -518,6 +562,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     const Box B = block_box(d, boxes, blk_box, b);
     const int lb = b - B.block_off;
     hood_setup(B, lb, cell_start, h);
+    if (part == 0)
+        hood_store(h, b, hood_tab);
     int lo, hi;
     h.share(part, d.parts, lo, hi);
     const int total = h.off[h.ncell];
@@ -805,7 +851,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
                                                        const int32_t *__restrict__ blk_box,
                                                        const double *__restrict__ x, const double *__restrict__ y,
                                                        const double *__restrict__ z,
-                                                       const int32_t *__restrict__ cell_start,
+                                                       const int32_t *__restrict__ hood_tab,
                                                        const int32_t *__restrict__ cnt,
                                                        const int32_t *__restrict__ nbr, double *__restrict__ vx,
                                                        double *__restrict__ vy, double *__restrict__ vz,
@@ -823,7 +869,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     // uses them already reads one scalar operand
     double mf6 = -B.f6, mu6 = -B.u6;
     asm volatile("" : "+v"(mf6), "+v"(mu6));
-    hood_setup(B, b - B.block_off, cell_start, h);
+    hood_load(hood_tab, b, h);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     const LdsPos spos{(lds_double *)lds};
@@ -1166,7 +1212,7 @@ __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0
 // with w (48 bytes per slot).
 __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restrict__ boxes,
                                                      const int32_t *__restrict__ blk_box, Pos x,
-                                                     const int32_t *__restrict__ cell_start,
+                                                     const int32_t *__restrict__ hood_tab,
                                                      const int32_t *__restrict__ cnt,
                                                      const int32_t *__restrict__ nbr, Pos w, Pos lam, Pos wout,
                                                      double mult, int drift_adj, double *__restrict__ partials) {
@@ -1178,7 +1224,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
     const Box B = block_box(d, boxes, blk_box, b);
     HvpConst k{-B.f6, -B.e6, -B.h6, B.g8};
     asm volatile("" : "+v"(k.mf6), "+v"(k.me6), "+v"(k.mh6), "+v"(k.g8));
-    hood_setup(B, b - B.block_off, cell_start, h);
+    hood_load(hood_tab, b, h);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     lds_double *S = (lds_double *)lds;
@@ -1305,7 +1351,7 @@ hipError_t launch_gather(const Dims &d, const double *const src[3], const int32_
 hipError_t launch_hvp(const Dims &d, Buffers &b, const Pos &x, const Pos &w, const Pos &lam_x, const Pos &wout,
                       double mult, bool drift_adj, double *partials, hipStream_t s) {
     k_hvp<<<block_grid(d.nblk * d.parts), d.threads, 2 * hood_lds_bytes(d.cap), s>>>(
-        d, b.boxes, b.blk_box, x, b.cell_start, b.nbr_count, b.nbr, w, lam_x, wout, mult, drift_adj ? 1 : 0,
+        d, b.boxes, b.blk_box, x, b.hood_tab, b.nbr_count, b.nbr, w, lam_x, wout, mult, drift_adj ? 1 : 0,
         partials);
     return hipGetLastError();
 }
@@ -1371,14 +1417,14 @@ hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
 
 hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
     k_build<<<block_grid(d.nblk * d.parts), d.threads, hood_lds_bytes(d.cap), s>>>(
-        d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.nbr_count, b.nbr, b.err);
+        d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.hood_tab, b.nbr_count, b.nbr, b.err);
     return hipGetLastError();
 }
 
 template <int MODE, bool THERMO>
 static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
     k_force<MODE, THERMO><<<block_grid(d.nblk * d.parts), d.threads, hood_lds_bytes(d.cap), s>>>(
-        d, b.boxes, b.blk_box, in.x, in.y, in.z, b.cell_start, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
+        d, b.boxes, b.blk_box, in.x, in.y, in.z, b.hood_tab, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
         b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
 }
 

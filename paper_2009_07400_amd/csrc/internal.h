@@ -15,6 +15,7 @@ constexpr int kMaxHood = 125;      // cells in a block neighborhood (at most edg
 constexpr int kMaxThreads = 1024;  // threads per block workgroup (upper bound)
 constexpr int kAtomThreads = 256;  // threads per workgroup of per-atom kernels
 constexpr int kMaxParts = 4;       // workgroups per block, at most
+constexpr int kHoodWords = 256;    // int32 words of one block's stored neighborhood table
 
 // Bits of the device error word err[0].
 constexpr int kErrOverflow = 1;
@@ -100,6 +101,7 @@ struct Buffers {
     int32_t *cell_of, *slot, *tmp_idx;
     int32_t *cell_count, *cell_start, *scan_sums;
     int32_t *nbr_count, *nbr;
+    int32_t *hood_tab;     // [nblk][kHoodWords] neighborhood tables, written by every list build
     double *partials;      // [nblk * parts][kPartialStride]
     int32_t *err;          // [0] flags, [1] largest list length requested on overflow
 };
