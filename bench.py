@@ -290,6 +290,7 @@ def main():
         "roofline": prim["roofline"],
         "kernel_avg_ms": prim["kernel_ms"],
         "mean_list_length": prim["mean_list_length"],
+        "schedule": prim["schedule"],
     }
     if not args.no_secondary and args.workload != "c2":
         sec = run_gpu("c2", WORKLOADS["c2"]["steps"], args.warmup)

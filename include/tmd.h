@@ -258,10 +258,13 @@ tmd_status tmd_adjoint_backward(tmd_system *sys, void *ws, size_t bytes, const d
                                 const double *const lam_v[3], double *const grad_x0[3], double *const grad_v0[3],
                                 double *grad_eps, double *grad_sigma, tmd_stream stream);
 
-/* Per-kernel-class timing with HIP events recorded on the launch stream around
- * every kernel (only while enabled).  tmd_get_timing() synchronises, then
- * returns accumulated milliseconds and launch counts for the TMD_T_* classes
- * (arrays of at least TMD_T_COUNT entries) and resets the accumulators. */
+/* Per-kernel-class timing with HIP events recorded on the launch stream
+ * (only while enabled): around every kernel, except that the back-to-back
+ * force launches of tmd_integrate between two list rebuilds share one pair of
+ * events (their average then holds no event overhead).  tmd_get_timing()
+ * synchronises, then returns accumulated milliseconds and launch counts for
+ * the TMD_T_* classes (arrays of at least TMD_T_COUNT entries) and resets the
+ * accumulators. */
 tmd_status tmd_set_timing(tmd_system *sys, int32_t enable);
 tmd_status tmd_get_timing(tmd_system *sys, double *ms, int64_t *launches);
 

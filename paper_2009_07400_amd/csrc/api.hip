@@ -44,6 +44,7 @@ struct tmd_system {
     struct Ev {
         int cls;
         hipEvent_t a, b;
+        int n;  // launches between the two events
     };
     bool timing = false;
     std::vector<Ev> pending;
@@ -145,8 +146,44 @@ struct Timed {
             return;
         }
         (void)hipEventRecord(b, st);
-        s->pending.push_back({cls, a, b});
+        s->pending.push_back({cls, a, b, 1});
     }
+};
+
+// Brackets a run of back-to-back launches of one class with one pair of
+// events (so the average includes no event overhead between them): add()
+// before each launch, close() before a launch of another class.
+struct TimedRun {
+    tmd_system *s;
+    int cls;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    int n = 0;
+    TimedRun(tmd_system *s_, int cls_, hipStream_t st_) : s(s_), cls(cls_), st(st_) {}
+    void add() {
+        if (!s->timing)
+            return;
+        if (n == 0) {
+            if ((a = get_event(s)) == nullptr)
+                return;
+            (void)hipEventRecord(a, st);
+        }
+        ++n;
+    }
+    void close() {
+        if (n == 0 || !a)
+            return;
+        hipEvent_t b = get_event(s);
+        if (b) {
+            (void)hipEventRecord(b, st);
+            s->pending.push_back({cls, a, b, n});
+        } else {
+            s->pool.push_back(a);
+        }
+        a = nullptr;
+        n = 0;
+    }
+    ~TimedRun() { close(); }
 };
 
 tmd_status check_ready(tmd_system *s, bool need_state) {
@@ -590,21 +627,24 @@ tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, d
     s->force_valid = false;
     const int64_t rb = s->rebuild_every;
     const int64_t row_stride = int64_t(s->d.nbox) * 5;
+    TimedRun run(s, TMD_T_FORCE, hs);
     for (int32_t k = 1; k <= n_steps; ++k) {
         const int64_t stepk = s->step + k;
-        if (stepk % rb == 0 && (st = rebuild(s, hs)) != TMD_OK)
-            return st;
+        if (stepk % rb == 0) {
+            run.close();
+            if ((st = rebuild(s, hs)) != TMD_OK)
+                return st;
+        }
         const bool th = thermo_every > 0 && (k % thermo_every) == 0;
         const int mode = (k < n_steps) ? 2 : 1;
-        {
-            Timed t(s, TMD_T_FORCE, hs);
-            e = launch_force(s->d, s->b, s->cur, mode, th, hs);
-        }
+        run.add();
+        e = launch_force(s->d, s->b, s->cur, mode, th, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "force");
         if (mode == 2)
             s->cur.x = 1 - s->cur.x;
         if (th) {
+            run.close();
             Timed t(s, TMD_T_THERMO, hs);
             e = launch_reduce(s->d, s->b, thermo + int64_t(k / thermo_every - 1) * row_stride, 5, hs);
             if (e != hipSuccess)
@@ -1002,7 +1042,7 @@ tmd_status tmd_get_timing(tmd_system *s, double *ms, int64_t *launches) {
         if (e != hipSuccess)
             return hip_fail(s, e, "get_timing");
         s->t_ms[ev.cls] += t;
-        s->t_n[ev.cls] += 1;
+        s->t_n[ev.cls] += ev.n;
         s->pool.push_back(ev.a);
         s->pool.push_back(ev.b);
     }
