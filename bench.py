@@ -61,6 +61,11 @@ def _traffic(workload: str):
     return ent.get("bytes_per_launch")
 
 
+def _schedule(g) -> dict:
+    info = g.info()
+    return {k: info[k] for k in ("block_edge", "block_parts", "lanes_per_atom", "block_threads", "lds_atoms")}
+
+
 def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     import torch
 
@@ -71,11 +76,10 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     s = md_system(w["ncell"], w["rho"], w["T"], seed=w["seed"], jitter=w["jitter"])
     g = System(s.n, s.L, max_neighbors=128)
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
-    if schedule:  # fixed (block edge, workgroups per block, threads), e.g. for profiling runs
-        g.set_schedule(block_edge=schedule[0], block_parts=schedule[1], threads=schedule[2])
-        edge, parts, threads = schedule
+    if schedule:  # fixed schedule, e.g. for profiling runs
+        g.set_schedule(**schedule)
     else:  # schedule chosen before the warmup, outside the timed region
-        edge, parts, threads = g.autotune(repeats=3)
+        g.autotune(repeats=5)
     g.integrate(warmup)
     g.sync()
     torch.cuda.synchronize()
@@ -111,8 +115,7 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
         "value": s.n * steps / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
         "mean_list_length": mean_list,
-        "schedule": {"block_edge": edge, "block_parts": parts, "block_threads": threads,
-                     "lds_atoms": g.info()["lds_atoms"]},
+        "schedule": _schedule(g),
         "kernel_ms": {k: (v[0] / max(v[1], 1), v[1]) for k, v in tm.items() if v[1]},
         "roofline": {
             "bound": "hbm",
@@ -144,7 +147,8 @@ def run_batched(steps: int = 200, warmup: int = 20, n_boxes: int = 512):
     g = System.batch([b.n for b in boxes], [b.L for b in boxes], dict(max_neighbors=128))
     g.set_state(torch.from_numpy(np.concatenate([b.pos() for b in boxes])),
                 torch.from_numpy(np.concatenate([b.vel() for b in boxes])))
-    edge, parts, threads = g.autotune(repeats=3)
+    g.autotune(repeats=5)
+    sched = _schedule(g)
     g.integrate(warmup)
     g.sync()
     torch.cuda.synchronize()
@@ -175,7 +179,7 @@ def run_batched(steps: int = 200, warmup: int = 20, n_boxes: int = 512):
             "value": total * steps / t_batch, "unit": "atom-steps/s", "steps": steps,
             "ms_per_step": t_batch / steps * 1e3, "sequential_value": total * steps / t_seq,
             "sequential_ms_per_step": t_seq / steps * 1e3, "speedup_vs_sequential": t_seq / t_batch,
-            "block_edge": edge, "block_parts": parts, "block_threads": threads, "n_blocks": info["n_blocks"], "lds_atoms": info["lds_atoms"]}
+            "schedule": sched, "n_blocks": info["n_blocks"], "lds_atoms": info["lds_atoms"]}
 
 
 def run_adjoint(steps: int = 200, replicas: int = 64):
@@ -244,8 +248,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3.5M-atom secondary workload")
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--schedule", default=None,
-                    help="fixed block edge, workgroups per block and threads for the primary workload, "
-                         "e.g. 3,1,640 (default: autotune)")
+                    help="fixed schedule for the primary workload: block edge, workgroups per block, lanes per "
+                         "atom, threads, e.g. 3,1,1,640 (default: autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the run, copy a 1 GiB buffer 3 times with torch: a kernel of known traffic "
                          "(1 GiB read + 1 GiB written per launch) to calibrate FETCH_SIZE / WRITE_SIZE counters")
@@ -268,7 +272,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    sched = tuple(int(v) for v in args.schedule.split(",")) if args.schedule else None
+    sched = None
+    if args.schedule:
+        e_, p_, l_, t_ = (int(v) for v in args.schedule.split(","))
+        sched = dict(block_edge=e_, block_parts=p_, lanes_per_atom=l_, threads=t_)
     prim = run_gpu(args.workload, steps, args.warmup, sched)
     print(f"# primary {args.workload}: {prim['value']:.4g} atom-steps/s, {prim['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)

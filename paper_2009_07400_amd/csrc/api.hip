@@ -228,7 +228,7 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
 // Threads per block workgroup: ~15% above the mean number of atoms one
 // workgroup takes (a block's atoms split over d.parts workgroups).
 int default_threads(const Dims &d) {
-    const double per_wg = double(d.nt) / (double(d.nblk) * d.parts);
+    const double per_wg = double(d.nt) / (double(d.nblk) * d.parts) * d.lpa;
     return std::min(kMaxThreads, std::max(64, round_up(int(per_wg * 1.15), 64)));
 }
 
@@ -299,6 +299,8 @@ bool layout_blocks(tmd_system *s, int E) {
     }
     if (d.parts < 1)
         d.parts = 1;
+    if (d.lpa < 1)
+        d.lpa = 1;
     d.threads = default_threads(d);
     s->blk_box.assign(size_t(blocks), 0);
     for (int32_t k = 0; k < d.nbox; ++k) {
@@ -739,14 +741,16 @@ tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
     info->lds_atoms = s->d.cap;
     info->block_edge = s->d.edge;
     info->block_parts = s->d.parts;
+    info->lanes_per_atom = s->d.lpa;
     return TMD_OK;
 }
 
 tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, int32_t block_edge,
-                            int32_t block_parts) {
+                            int32_t block_parts, int32_t lanes_per_atom) {
     if (!s || threads < 0 || threads > kMaxThreads || threads % 64 != 0 || lds_atoms < 0 || lds_atoms > kMaxCap ||
         lds_atoms % 64 != 0 || (block_edge != 0 && block_edge != 2 && block_edge != 3) ||
-        (block_parts != 0 && block_parts != 1 && block_parts != 2 && block_parts != 4))
+        (block_parts != 0 && block_parts != 1 && block_parts != 2 && block_parts != 4) ||
+        (lanes_per_atom != 0 && lanes_per_atom != 1 && lanes_per_atom != 2))
         return TMD_EINVAL;
     if (block_edge != 0 && block_edge != s->d.edge) {
         layout_blocks(s, block_edge);  // resets threads and capacity to that edge's defaults
@@ -756,6 +760,11 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
     if (block_parts != 0 && block_parts != s->d.parts) {
         s->d.parts = block_parts;  // the list does not depend on it
         s->d.threads = default_threads(s->d);
+    }
+    if (lanes_per_atom != 0 && lanes_per_atom != s->d.lpa) {
+        s->d.lpa = lanes_per_atom;  // nor on this
+        s->d.threads = default_threads(s->d);
+        s->force_valid = false;      // forces are summed in another order
     }
     if (threads > 0)
         s->d.threads = threads;
@@ -816,14 +825,16 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     if (e != hipSuccess)
         return hip_fail(s, e, "autotune");
     float best = 1e30f;
-    int32_t best_edge = s->d.edge, best_t = s->d.threads, best_p = s->d.parts;
+    int32_t best_edge = s->d.edge, best_t = s->d.threads, best_p = s->d.parts, best_l = s->d.lpa;
     for (int32_t E = 2; E <= kMaxEdge && e == hipSuccess; ++E) {
         layout_blocks(s, E);
         s->list_valid = s->force_valid = false;
         if ((st = rebuild(s, hs)) != TMD_OK)
             break;
-        for (int32_t P = 1; P <= kMaxParts && e == hipSuccess; P *= 2) {
+        for (int32_t c = 0; c < 2 * 3 && e == hipSuccess; ++c) {
+            const int32_t P = 1 << (c % 3), Lp = 1 + c / 3;
             s->d.parts = P;
+            s->d.lpa = Lp;
             const int32_t t0 = default_threads(s->d);
             for (int32_t t = std::max(64, t0 - 128); t <= std::min(kMaxThreads, t0 + 128) && e == hipSuccess;
                  t += 64) {
@@ -832,13 +843,14 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
                 float ms = 0.0f, mb = 0.0f;
                 e = time_force(s, repeats, hs, a, b, ms);
                 if (e == hipSuccess)
-                    e = time_build(s, 1, hs, a, b, mb);
+                    e = time_build(s, (repeats + 1) / 2, hs, a, b, mb);
                 ms += mb / float(s->rebuild_every);
                 if (e == hipSuccess && ms < best) {
                     best = ms;
                     best_edge = E;
                     best_t = t;
                     best_p = P;
+                    best_l = Lp;
                 }
             }
         }
@@ -851,6 +863,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
         return hip_fail(s, e, "autotune");
     layout_blocks(s, best_edge);
     s->d.parts = best_p;
+    s->d.lpa = best_l;
     s->d.threads = best_t;
     s->list_valid = s->force_valid = false;
     return rebuild(s, hs);

@@ -671,9 +671,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
         // room for it: nchunk = ceil(maxnb / 4) + 1); force loops read that
         // chunk in place of any chunk past the end
         if (fits) {
-            // (at least through row 1: the force kernel loads rows 0 and 1
-            // before it knows the count)
-            for (int k = stored; k < max(((stored + 7) & ~7) + 8, 16); ++k)
+            // (at least through row 3: with two lanes per atom the force
+            // kernel loads rows 0 to 3 before it knows the count)
+            for (int k = stored; k < max(((stored + 7) & ~7) + 8, 32); ++k)
                 nbr16[nbr_index16(i, k, d.nchunk)] = uint16_t(sentinel);
         } else {
             for (int k = stored; k < ((stored + 3) & ~3) + 4; ++k)
@@ -744,11 +744,18 @@ __device__ __forceinline__ void eval2(const Duo &q, double xi, double yi, double
 // reads positions from the LDS copy of the neighborhood or from global
 // memory.
 template <bool THERMO, class POS>
-__device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int c, const POS &pos, double xi,
-                                         double yi, double zi, const Box &B, double mf6, double mu6, double &ax,
-                                         double &ay, double &az, double &u, double &w) {
+__device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int p, int L, int c, const POS &pos,
+                                         double xi, double yi, double zi, const Box &B, double mf6, double mu6,
+                                         double &ax, double &ay, double &az, double &u, double &w) {
     const int nch = (c + 3) >> 2;
-    auto ld = [&](int k) { return __builtin_nontemporal_load(chunks + (k < nch ? k : nch) * 64); };
+    // with L lanes per atom the list is dealt in groups of eight entries (two
+    // chunks), lane p taking groups p, p + L, ... - the same split as the
+    // 16-bit list's eight-entry chunks, so both give the same sums
+    auto idx = [&](int k) { return 2 * (p + L * (k >> 1)) + (k & 1); };
+    auto ld = [&](int k) {
+        const int q = idx(k);
+        return __builtin_nontemporal_load(chunks + (q < nch ? q : nch) * 64);
+    };
     // issue the look-ahead loads in chunk order (consumed oldest first)
     v4i i0 = ld(0);
     __builtin_amdgcn_sched_barrier(0);
@@ -780,7 +787,7 @@ __device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int c, 
         fetch2(pos, i0[0], i0[1], P);
         i3 = ld(k + 7);
         eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        if (!__any(k + 4 < nch))
+        if (!__any(idx(k + 4) < nch))
             break;
     }
     // retire the unused look-ahead reads here, so the next atom's loop
@@ -799,17 +806,24 @@ __device__ __forceinline__ void fetch2w(const LdsPos &pos, int word, Duo &q) {
 // the bytes of the 32-bit list per entry.  The body covers two chunks, with
 // the same look-ahead discipline (index chunks one to two chunks ahead,
 // positions two entries ahead, unconditional memory operations, the chunk
-// after the last standing in for every chunk past the end).  The caller
-// passes rows 0 and 1, which every 16-bit list fills (with sentinels past
-// the count), so it can load them before the count is known.  The only exit
+// after the last standing in for every chunk past the end).  With L lanes
+// per atom, lane p of the group walks chunks p, p + L, p + 2L, ...  The
+// caller passes the lane's first two chunks (p and p + L, at most row 3),
+// which every 16-bit list fills (with sentinels past the count), so it can
+// load them before the count is known.  The only exit
 // is at the end of the body: a loop with several exits loses the exact wait
 // counts at its head.
 template <bool THERMO>
-__device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int c, const LdsPos &pos,
-                                           double xi, double yi, double zi, const Box &B, double mf6, double mu6,
-                                           double &ax, double &ay, double &az, double &u, double &w) {
+__device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int p, int L, int c,
+                                           const LdsPos &pos, double xi, double yi, double zi, const Box &B,
+                                           double mf6, double mu6, double &ax, double &ay, double &az, double &u,
+                                           double &w) {
     const int nch = (c + 7) >> 3;
-    auto ld = [&](int k) { return __builtin_nontemporal_load(chunks + (k < nch ? k : nch) * 64); };
+    // this lane's k-th chunk is chunk p + L k of the atom's list
+    auto ld = [&](int k) {
+        const int q = p + L * k;
+        return __builtin_nontemporal_load(chunks + (q < nch ? q : nch) * 64);
+    };
     Duo P, Q;
     fetch2w(pos, i0[0], P);
     for (int k = 0;; k += 2) {
@@ -831,7 +845,7 @@ __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i
         fetch2w(pos, i0[0], P);
         i1 = ld(k + 3);
         eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        if (!__any(k + 2 < nch))
+        if (!__any(p + L * (k + 2) < nch))
             break;
     }
     __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) expcnt(7) lgkmcnt(0)
@@ -846,7 +860,7 @@ __device__ __forceinline__ const v4i *list_chunks(const int32_t *nbr, int i, int
 // opening the next) and drift into the other position buffer.  With THERMO
 // each block writes its partial sums of the pair energy, of s f(s) and of
 // |v|^2 at the full step - no atomics anywhere.
-template <int MODE, bool THERMO>
+template <int MODE, bool THERMO, int L>
 __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__restrict__ boxes,
                                                        const int32_t *__restrict__ blk_box,
                                                        const double *__restrict__ x, const double *__restrict__ y,
@@ -878,10 +892,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     // are loaded one pass ahead - those of the first pass before the staging
     // barrier, so their latency overlaps the staging.  Past the block's last
     // atom the loads read that atom again (a cache hit) and are not used.
-    const int T = blockDim.x;
+    // L lanes per atom (adjacent lanes), lane p of the group taking every
+    // L-th chunk of the list; their sums are combined before the epilogue
+    const int p = threadIdx.x & (L - 1);
+    const int T = blockDim.x / L;
     int lo, hi;
     h.share(part, d.parts, lo, hi);
-    int i = lo + threadIdx.x;
+    int i = lo + threadIdx.x / L;
     double xi = 0.0, yi = 0.0, zi = 0.0, vxi = 0.0, vyi = 0.0, vzi = 0.0;
     int ci = 0;
     v4i r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0};
@@ -896,10 +913,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
             vyi = vy[ic];
             vzi = vz[ic];
         }
-        if (fits) {  // rows 0 and 1 of the 16-bit list
+        if (fits) {  // this lane's first two rows (p and p + L) of the 16-bit list
             const v4i *ch = list_chunks(nbr, ic, d.nchunk);
-            r0 = __builtin_nontemporal_load(ch);
-            r1 = __builtin_nontemporal_load(ch + 64);
+            r0 = __builtin_nontemporal_load(ch + p * 64);
+            r1 = __builtin_nontemporal_load(ch + (p + L) * 64);
         }
     };
     if (hi > lo)
@@ -914,17 +931,23 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
         double ax = 0.0, ay = 0.0, az = 0.0;
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
         if (fits)
-            pair_sum16<THERMO>(chunks, r0, r1, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+            pair_sum16<THERMO>(chunks, r0, r1, p, L, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         else
-            pair_sum<THERMO>(chunks, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        if (MODE == 0 || MODE == 1) {
+            pair_sum<THERMO>(chunks, p, L, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        if (L == 2) {  // the two halves of the sum (addition commutes, so both lanes agree)
+            ax += __shfl_xor(ax, 1, 64);
+            ay += __shfl_xor(ay, 1, 64);
+            az += __shfl_xor(az, 1, 64);
+        }
+        const bool own = p == 0;  // the group's first lane writes the atom
+        if ((MODE == 0 || MODE == 1) && own) {
             fx[i] = ax;
             fy[i] = ay;
             fz[i] = az;
             if (!(isfinite(ax) && isfinite(ay) && isfinite(az)))
                 atomicOr(err, kErrNonFinite);
         }
-        if (MODE >= 1) {
+        if (MODE >= 1 && own) {
             double a = vxi + B.h * ax, bb = vyi + B.h * ay, c = vzi + B.h * az;
             if (THERMO)
                 ke += a * a + bb * bb + c * c;
@@ -1325,12 +1348,18 @@ hipError_t prepare_kernels(const Dims &d) {
     const int bytes = int(hood_lds_bytes(d.cap));
     const void *fns[] = {
         reinterpret_cast<const void *>(&k_build),
-        reinterpret_cast<const void *>(&k_force<0, false>),
-        reinterpret_cast<const void *>(&k_force<0, true>),
-        reinterpret_cast<const void *>(&k_force<1, false>),
-        reinterpret_cast<const void *>(&k_force<1, true>),
-        reinterpret_cast<const void *>(&k_force<2, false>),
-        reinterpret_cast<const void *>(&k_force<2, true>),
+        reinterpret_cast<const void *>(&k_force<0, false, 1>),
+        reinterpret_cast<const void *>(&k_force<0, true, 1>),
+        reinterpret_cast<const void *>(&k_force<1, false, 1>),
+        reinterpret_cast<const void *>(&k_force<1, true, 1>),
+        reinterpret_cast<const void *>(&k_force<2, false, 1>),
+        reinterpret_cast<const void *>(&k_force<2, true, 1>),
+        reinterpret_cast<const void *>(&k_force<0, false, 2>),
+        reinterpret_cast<const void *>(&k_force<0, true, 2>),
+        reinterpret_cast<const void *>(&k_force<1, false, 2>),
+        reinterpret_cast<const void *>(&k_force<1, true, 2>),
+        reinterpret_cast<const void *>(&k_force<2, false, 2>),
+        reinterpret_cast<const void *>(&k_force<2, true, 2>),
     };
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1421,22 +1450,28 @@ hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int MODE, bool THERMO>
+template <int MODE, bool THERMO, int L>
 static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
-    k_force<MODE, THERMO><<<block_grid(d.nblk * d.parts), d.threads, hood_lds_bytes(d.cap), s>>>(
+    k_force<MODE, THERMO, L><<<block_grid(d.nblk * d.parts), d.threads, hood_lds_bytes(d.cap), s>>>(
         d, b.boxes, b.blk_box, in.x, in.y, in.z, b.hood_tab, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
         b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
 }
 
 hipError_t launch_force_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, int mode, bool thermo,
                            hipStream_t s) {
-    switch (mode * 2 + (thermo ? 1 : 0)) {
-    case 0: force_variant<0, false>(d, b, in, out, o, s); break;
-    case 1: force_variant<0, true>(d, b, in, out, o, s); break;
-    case 2: force_variant<1, false>(d, b, in, out, o, s); break;
-    case 3: force_variant<1, true>(d, b, in, out, o, s); break;
-    case 4: force_variant<2, false>(d, b, in, out, o, s); break;
-    case 5: force_variant<2, true>(d, b, in, out, o, s); break;
+    switch ((mode * 2 + (thermo ? 1 : 0)) * 2 + (d.lpa == 2 ? 1 : 0)) {
+    case 0: force_variant<0, false, 1>(d, b, in, out, o, s); break;
+    case 1: force_variant<0, false, 2>(d, b, in, out, o, s); break;
+    case 2: force_variant<0, true, 1>(d, b, in, out, o, s); break;
+    case 3: force_variant<0, true, 2>(d, b, in, out, o, s); break;
+    case 4: force_variant<1, false, 1>(d, b, in, out, o, s); break;
+    case 5: force_variant<1, false, 2>(d, b, in, out, o, s); break;
+    case 6: force_variant<1, true, 1>(d, b, in, out, o, s); break;
+    case 7: force_variant<1, true, 2>(d, b, in, out, o, s); break;
+    case 8: force_variant<2, false, 1>(d, b, in, out, o, s); break;
+    case 9: force_variant<2, false, 2>(d, b, in, out, o, s); break;
+    case 10: force_variant<2, true, 1>(d, b, in, out, o, s); break;
+    case 11: force_variant<2, true, 2>(d, b, in, out, o, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -147,19 +147,21 @@ class System:
     def info(self) -> dict:
         return abi.tmd_get_info(self._h)
 
-    def set_schedule(self, threads: int = 0, lds_atoms: int = 0, block_edge: int = 0, block_parts: int = 0) -> None:
+    def set_schedule(self, threads: int = 0, lds_atoms: int = 0, block_edge: int = 0, block_parts: int = 0,
+                     lanes_per_atom: int = 0) -> None:
         """Threads per block workgroup, LDS staging capacity, cells per block
-        edge and workgroups per block (0 = keep)."""
-        abi.tmd_set_schedule(self._h, threads, lds_atoms, block_edge, block_parts)
+        edge, workgroups per block and lanes per atom (0 = keep)."""
+        abi.tmd_set_schedule(self._h, threads, lds_atoms, block_edge, block_parts, lanes_per_atom)
 
     def autotune(self, repeats: int = 5):
-        """Times each schedule (block edge, workgroups per block, threads) by
-        one force evaluation plus a list build's share per step and keeps the
-        fastest; returns (block_edge, block_parts, block_threads).  Rebuilds
-        the list at the current positions."""
+        """Times each schedule (block edge, workgroups per block, lanes per
+        atom, threads) by one force evaluation plus a list build's share per
+        step and keeps the fastest; returns a dict of block_edge, block_parts,
+        lanes_per_atom and block_threads.  Rebuilds the list at the current
+        positions."""
         abi.tmd_autotune(self._h, repeats, _stream())
         info = self.info()
-        return info["block_edge"], info["block_parts"], info["block_threads"]
+        return {k: info[k] for k in ("block_edge", "block_parts", "lanes_per_atom", "block_threads")}
 
     def set_lj_params(self, epsilon, sigma) -> None:
         """Per-box epsilon and sigma (sequences of n_boxes floats, or scalars)."""
