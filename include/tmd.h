@@ -83,7 +83,7 @@ typedef struct {
     int32_t lds_atoms;       /* atoms of a block neighborhood staged in LDS */
     int32_t block_edge;      /* cells per block edge (2 or 3) */
     int32_t block_parts;     /* workgroups per block (1, 2 or 4) */
-    int32_t lanes_per_atom;  /* lanes sharing one atom's force sum (1 or 2) */
+    int32_t lanes_per_atom;  /* lanes sharing one atom's force sum (1, 2 or 4) */
     int32_t reserved_;
 } tmd_info;
 
@@ -192,7 +192,7 @@ tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
 
 /* Work schedule of the block kernels.  No value changes the lists; only
  * lanes_per_atom changes positions, velocities or forces (in their last
- * bits: the force on an atom is then summed as two interleaved halves), and
+ * bits: the force on an atom is then summed as interleaved parts), and
  * energy, virial and kinetic sums may differ in their last bits (their
  * summation order follows the workgroups).
  * block_edge: cells per edge of the blocks of cells that one workgroup owns
@@ -201,10 +201,11 @@ tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
  * block_parts: workgroups sharing one block, 1, 2 or 4, each taking a
  * contiguous share of the block's atoms and staging the whole neighborhood
  * (more workgroups for small systems; 0 keeps the current value; a new value
- * resets threads to its default).  lanes_per_atom: 1 or 2 lanes of a
- * wavefront per atom in the force kernel, lane p taking list chunks p,
- * p + 2, ... (more parallelism for small systems; 0 keeps the current
- * value; a new value resets threads to its default).  threads: threads per
+ * resets threads to its default).  lanes_per_atom: 1, 2 or 4 lanes of a
+ * wavefront per atom in the force kernel, lane p taking the list's groups of
+ * eight entries p, p + lanes_per_atom, ... (more parallelism for small
+ * systems; 0 keeps the current value; a new value resets threads to its
+ * default).  threads: threads per
  * block workgroup, a multiple of 64 in [64, 1024] (0 keeps the current
  * value).  lds_atoms: how many atoms of a block's neighborhood may be staged
  * in LDS, a multiple of 64 in [64, 4096] (0 keeps the current value; lowered
@@ -217,7 +218,7 @@ tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms,
                             int32_t block_parts, int32_t lanes_per_atom);
 
 /* Pick the schedule (block edge 2 or 3, workgroups per block 1, 2 or 4,
- * lanes per atom 1 or 2, threads per block workgroup) with the
+ * lanes per atom 1, 2 or 4, threads per block workgroup) with the
  * shortest time per step for the current positions - one force evaluation
  * plus 1/rebuild_every of a list build: times `repeats` force evaluations
  * and one build per candidate on `stream` with HIP events (synchronises).  Positions and velocities are not changed, but the list is

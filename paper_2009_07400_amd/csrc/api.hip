@@ -750,7 +750,7 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
     if (!s || threads < 0 || threads > kMaxThreads || threads % 64 != 0 || lds_atoms < 0 || lds_atoms > kMaxCap ||
         lds_atoms % 64 != 0 || (block_edge != 0 && block_edge != 2 && block_edge != 3) ||
         (block_parts != 0 && block_parts != 1 && block_parts != 2 && block_parts != 4) ||
-        (lanes_per_atom != 0 && lanes_per_atom != 1 && lanes_per_atom != 2))
+        (lanes_per_atom != 0 && lanes_per_atom != 1 && lanes_per_atom != 2 && lanes_per_atom != 4))
         return TMD_EINVAL;
     if (block_edge != 0 && block_edge != s->d.edge) {
         layout_blocks(s, block_edge);  // resets threads and capacity to that edge's defaults
@@ -831,8 +831,8 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
         s->list_valid = s->force_valid = false;
         if ((st = rebuild(s, hs)) != TMD_OK)
             break;
-        for (int32_t c = 0; c < 2 * 3 && e == hipSuccess; ++c) {
-            const int32_t P = 1 << (c % 3), Lp = 1 + c / 3;
+        for (int32_t c = 0; c < 3 * 3 && e == hipSuccess; ++c) {
+            const int32_t P = 1 << (c % 3), Lp = 1 << (c / 3);
             s->d.parts = P;
             s->d.lpa = Lp;
             const int32_t t0 = default_threads(s->d);

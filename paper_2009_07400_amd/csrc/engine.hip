@@ -671,9 +671,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
         // room for it: nchunk = ceil(maxnb / 4) + 1); force loops read that
         // chunk in place of any chunk past the end
         if (fits) {
-            // (at least through row 3: with two lanes per atom the force
-            // kernel loads rows 0 to 3 before it knows the count)
-            for (int k = stored; k < max(((stored + 7) & ~7) + 8, 32); ++k)
+            // (at least through row 7, or the whole area when it has fewer
+            // rows: with up to four lanes per atom the force kernel loads
+            // rows 0 to 7 before it knows the count)
+            const int pad_end = min(max(((stored + 7) & ~7) + 8, 64), 8 * d.nchunk);
+            for (int k = stored; k < pad_end; ++k)
                 nbr16[nbr_index16(i, k, d.nchunk)] = uint16_t(sentinel);
         } else {
             for (int k = stored; k < ((stored + 3) & ~3) + 4; ++k)
@@ -808,7 +810,7 @@ __device__ __forceinline__ void fetch2w(const LdsPos &pos, int word, Duo &q) {
 // positions two entries ahead, unconditional memory operations, the chunk
 // after the last standing in for every chunk past the end).  With L lanes
 // per atom, lane p of the group walks chunks p, p + L, p + 2L, ...  The
-// caller passes the lane's first two chunks (p and p + L, at most row 3),
+// caller passes the lane's first two chunks (p and p + L, at most row 7),
 // which every 16-bit list fills (with sentinels past the count), so it can
 // load them before the count is known.  The only exit
 // is at the end of the body: a loop with several exits loses the exact wait
@@ -914,9 +916,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
             vzi = vz[ic];
         }
         if (fits) {  // this lane's first two rows (p and p + L) of the 16-bit list
+            // (a row past the atom's area stands for a chunk past the end of
+            // the list: the area's last row is then sentinel padding)
             const v4i *ch = list_chunks(nbr, ic, d.nchunk);
-            r0 = __builtin_nontemporal_load(ch + p * 64);
-            r1 = __builtin_nontemporal_load(ch + (p + L) * 64);
+            r0 = __builtin_nontemporal_load(ch + min(p, d.nchunk - 1) * 64);
+            r1 = __builtin_nontemporal_load(ch + min(p + L, d.nchunk - 1) * 64);
         }
     };
     if (hi > lo)
@@ -934,10 +938,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
             pair_sum16<THERMO>(chunks, r0, r1, p, L, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         else
             pair_sum<THERMO>(chunks, p, L, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        if (L == 2) {  // the two halves of the sum (addition commutes, so both lanes agree)
-            ax += __shfl_xor(ax, 1, 64);
-            ay += __shfl_xor(ay, 1, 64);
-            az += __shfl_xor(az, 1, 64);
+        // combine the L partial sums of the group (a butterfly: addition
+        // commutes, so every lane of the group ends with the same bits)
+#pragma unroll
+        for (int o = 1; o < L; o <<= 1) {
+            ax += __shfl_xor(ax, o, 64);
+            ay += __shfl_xor(ay, o, 64);
+            az += __shfl_xor(az, o, 64);
         }
         const bool own = p == 0;  // the group's first lane writes the atom
         if ((MODE == 0 || MODE == 1) && own) {
@@ -1360,6 +1367,12 @@ hipError_t prepare_kernels(const Dims &d) {
         reinterpret_cast<const void *>(&k_force<1, true, 2>),
         reinterpret_cast<const void *>(&k_force<2, false, 2>),
         reinterpret_cast<const void *>(&k_force<2, true, 2>),
+        reinterpret_cast<const void *>(&k_force<0, false, 4>),
+        reinterpret_cast<const void *>(&k_force<0, true, 4>),
+        reinterpret_cast<const void *>(&k_force<1, false, 4>),
+        reinterpret_cast<const void *>(&k_force<1, true, 4>),
+        reinterpret_cast<const void *>(&k_force<2, false, 4>),
+        reinterpret_cast<const void *>(&k_force<2, true, 4>),
     };
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1459,19 +1472,26 @@ static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &o
 
 hipError_t launch_force_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, int mode, bool thermo,
                            hipStream_t s) {
-    switch ((mode * 2 + (thermo ? 1 : 0)) * 2 + (d.lpa == 2 ? 1 : 0)) {
+    const int l = d.lpa == 4 ? 2 : (d.lpa == 2 ? 1 : 0);
+    switch ((mode * 2 + (thermo ? 1 : 0)) * 3 + l) {
     case 0: force_variant<0, false, 1>(d, b, in, out, o, s); break;
     case 1: force_variant<0, false, 2>(d, b, in, out, o, s); break;
-    case 2: force_variant<0, true, 1>(d, b, in, out, o, s); break;
-    case 3: force_variant<0, true, 2>(d, b, in, out, o, s); break;
-    case 4: force_variant<1, false, 1>(d, b, in, out, o, s); break;
-    case 5: force_variant<1, false, 2>(d, b, in, out, o, s); break;
-    case 6: force_variant<1, true, 1>(d, b, in, out, o, s); break;
-    case 7: force_variant<1, true, 2>(d, b, in, out, o, s); break;
-    case 8: force_variant<2, false, 1>(d, b, in, out, o, s); break;
-    case 9: force_variant<2, false, 2>(d, b, in, out, o, s); break;
-    case 10: force_variant<2, true, 1>(d, b, in, out, o, s); break;
-    case 11: force_variant<2, true, 2>(d, b, in, out, o, s); break;
+    case 2: force_variant<0, false, 4>(d, b, in, out, o, s); break;
+    case 3: force_variant<0, true, 1>(d, b, in, out, o, s); break;
+    case 4: force_variant<0, true, 2>(d, b, in, out, o, s); break;
+    case 5: force_variant<0, true, 4>(d, b, in, out, o, s); break;
+    case 6: force_variant<1, false, 1>(d, b, in, out, o, s); break;
+    case 7: force_variant<1, false, 2>(d, b, in, out, o, s); break;
+    case 8: force_variant<1, false, 4>(d, b, in, out, o, s); break;
+    case 9: force_variant<1, true, 1>(d, b, in, out, o, s); break;
+    case 10: force_variant<1, true, 2>(d, b, in, out, o, s); break;
+    case 11: force_variant<1, true, 4>(d, b, in, out, o, s); break;
+    case 12: force_variant<2, false, 1>(d, b, in, out, o, s); break;
+    case 13: force_variant<2, false, 2>(d, b, in, out, o, s); break;
+    case 14: force_variant<2, false, 4>(d, b, in, out, o, s); break;
+    case 15: force_variant<2, true, 1>(d, b, in, out, o, s); break;
+    case 16: force_variant<2, true, 2>(d, b, in, out, o, s); break;
+    case 17: force_variant<2, true, 4>(d, b, in, out, o, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -63,7 +63,7 @@ struct Dims {
     int32_t threads;  // threads per block workgroup (64..kMaxThreads, multiple of 64)
     int32_t nchunk;   // 4-entry list chunks per atom: ceil(maxnb / 4) + 1 (a spare chunk of padding)
     int32_t parts;    // workgroups per block (1, 2 or 4), each taking a share of the block's atoms
-    int32_t lpa;      // lanes per atom in the force kernel (1 or 2), each taking every lpa-th list chunk
+    int32_t lpa;      // lanes per atom in the force kernel (1, 2 or 4), each taking every lpa-th list chunk
 };
 
 // Neighbor list layout: neighbor-major within tiles of 64 atoms (one

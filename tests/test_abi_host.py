@@ -134,7 +134,7 @@ def test_batch_create_and_validation():
         assert abi.tmd_get_info(h)["lanes_per_atom"] == 2
         for bad in ((100, 0, 0, 0, 0), (1088, 0, 0, 0, 0), (0, 100, 0, 0, 0), (0, 4160, 0, 0, 0), (-64, 0, 0, 0, 0),
                     (0, 0, 4, 0, 0), (0, 0, 1, 0, 0), (0, 0, 0, 3, 0), (0, 0, 0, 8, 0), (0, 0, 0, -1, 0),
-                    (0, 0, 0, 0, 3), (0, 0, 0, 0, 4), (0, 0, 0, 0, -1)):
+                    (0, 0, 0, 0, 3), (0, 0, 0, 0, 8), (0, 0, 0, 0, -1)):
             with pytest.raises(abi.TmdError):
                 abi.tmd_set_schedule(h, *bad)
     finally:

@@ -59,7 +59,8 @@ def test_cells_per_axis_of_the_cases():
 
 @pytest.mark.parametrize("sched", [{}, {"lds_atoms": 64}, {"threads": 64}, {"threads": 256, "lds_atoms": 2560},
                                    {"block_parts": 2}, {"block_parts": 4, "threads": 64}, {"lanes_per_atom": 2},
-                                   {"lanes_per_atom": 2, "lds_atoms": 64}, {"lanes_per_atom": 2, "block_edge": 3}])
+                                   {"lanes_per_atom": 2, "lds_atoms": 64}, {"lanes_per_atom": 2, "block_edge": 3},
+                                   {"lanes_per_atom": 4}, {"lanes_per_atom": 4, "lds_atoms": 64}])
 def test_batch_lists_and_forces_match_oracle(sched):
     states = _states()
     g = _batch(states, **sched)
@@ -123,7 +124,7 @@ def test_batch_equals_single_box_runs_bitwise():
     (64, 0, 2, 1, 1), (128, 0, 2, 1, 1), (192, 0, 2, 1, 1), (256, 0, 2, 1, 1), (0, 64, 2, 1, 1), (0, 0, 3, 1, 1),
     (384, 0, 3, 1, 1), (1024, 0, 3, 1, 1), (0, 64, 3, 1, 1), (0, 0, 2, 2, 1), (64, 0, 2, 4, 1), (0, 0, 3, 2, 1),
     (128, 0, 3, 4, 1), (0, 64, 3, 4, 1), (0, 0, 2, 1, 2), (128, 0, 2, 2, 2), (0, 64, 2, 1, 2), (0, 0, 3, 1, 2),
-    (256, 0, 3, 4, 2), (0, 64, 3, 2, 2)])
+    (256, 0, 3, 4, 2), (0, 64, 3, 2, 2), (0, 0, 2, 1, 4), (0, 64, 2, 2, 4), (512, 0, 3, 1, 4)])
 def test_schedule_does_not_change_trajectory(threads, lds, edge, parts, lpa):
     """Any schedule gives the trajectory of the default one bit for bit -
     against the default with the same lanes per atom (two lanes sum each
@@ -153,7 +154,7 @@ def test_autotune_keeps_state():
     sc = g.autotune(repeats=2)
     p1, v1, _ = g.get_state()
     g.sync()
-    assert sc["block_edge"] in (2, 3) and sc["block_parts"] in (1, 2, 4) and sc["lanes_per_atom"] in (1, 2)
+    assert sc["block_edge"] in (2, 3) and sc["block_parts"] in (1, 2, 4) and sc["lanes_per_atom"] in (1, 2, 4)
     assert sc["block_threads"] % 64 == 0 and 64 <= sc["block_threads"] <= 1024
     assert torch.equal(p0, p1) and torch.equal(v0, v1)
 

@@ -92,6 +92,20 @@ def test_neighbors_and_forces_match_oracle(case):
     _check_forces(g, pos, L, c_o, n_o)
 
 
+@pytest.mark.parametrize("lpa,lds", [(1, 0), (2, 0), (4, 0), (4, 64)])
+def test_short_list_capacity_and_lanes_per_atom(lpa, lds):
+    """A dilute gas with max_neighbors = 8 (a list area of three rows): the
+    force kernel's row look-ahead and the build's padding stay inside each
+    atom's area for every lanes-per-atom setting."""
+    pos = SplitMix64(11).next_double(3 * 300).reshape(300, 3) * 30.0
+    g = _gpu_system(pos, np.zeros_like(pos), 30.0, max_neighbors=8)
+    g.set_schedule(lanes_per_atom=lpa, lds_atoms=lds)
+    g.build_neighbors()
+    c_o, n_o = _check_lists(g, pos, 30.0)
+    assert c_o.max() <= 8
+    _check_forces(g, pos, 30.0, c_o, n_o)
+
+
 def test_fcc_lattice_sums_on_gpu():
     pos, L = fcc_positions(8, 0.8442)
     g = _gpu_system(pos, np.zeros_like(pos), L)
