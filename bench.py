@@ -63,7 +63,31 @@ def _traffic(workload: str):
 
 def _schedule(g) -> dict:
     info = g.info()
-    return {k: info[k] for k in ("block_edge", "block_parts", "lanes_per_atom", "block_threads", "lds_atoms")}
+    return {k: info[k] for k in ("block_edge", "block_parts", "lanes_per_atom", "block_threads", "build_threads",
+                                 "lds_atoms")}
+
+
+REBUILD_EVERY = 20  # list rebuild interval of every workload here
+
+
+def _warm_and_tune(g, warmup: int, schedule=None):
+    """Run the warmup steps and fix the schedule, both outside the timed
+    region.  Without a given schedule the autotuner runs after the largest
+    multiple of the rebuild interval within the warmup (a rebuild step, so the
+    fixed rebuild schedule is kept): on the initial lattice every list has the
+    same length, while a few steps later lengths spread as they do in the
+    timed steps, and every wavefront runs to the longest list among its
+    atoms, which changes which schedule is fastest."""
+    if schedule:  # fixed schedule, e.g. for profiling runs
+        g.set_schedule(**schedule)
+        g.integrate(warmup)
+        return
+    k = warmup // REBUILD_EVERY * REBUILD_EVERY
+    if k:
+        g.integrate(k)
+    g.autotune(repeats=5)
+    if warmup > k:
+        g.integrate(warmup - k)
 
 
 def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
@@ -76,11 +100,7 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     s = md_system(w["ncell"], w["rho"], w["T"], seed=w["seed"], jitter=w["jitter"])
     g = System(s.n, s.L, max_neighbors=128)
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
-    if schedule:  # fixed schedule, e.g. for profiling runs
-        g.set_schedule(**schedule)
-    else:  # schedule chosen before the warmup, outside the timed region
-        g.autotune(repeats=5)
-    g.integrate(warmup)
+    _warm_and_tune(g, warmup, schedule)
     g.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -147,9 +167,8 @@ def run_batched(steps: int = 200, warmup: int = 20, n_boxes: int = 512):
     g = System.batch([b.n for b in boxes], [b.L for b in boxes], dict(max_neighbors=128))
     g.set_state(torch.from_numpy(np.concatenate([b.pos() for b in boxes])),
                 torch.from_numpy(np.concatenate([b.vel() for b in boxes])))
-    g.autotune(repeats=5)
+    _warm_and_tune(g, warmup)
     sched = _schedule(g)
-    g.integrate(warmup)
     g.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -249,7 +268,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule for the primary workload: block edge, workgroups per block, lanes per "
-                         "atom, threads, e.g. 3,1,1,640 (default: autotune)")
+                         "atom, force threads[, build threads], e.g. 3,1,1,640 (default: autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the run, copy a 1 GiB buffer 3 times with torch: a kernel of known traffic "
                          "(1 GiB read + 1 GiB written per launch) to calibrate FETCH_SIZE / WRITE_SIZE counters")
@@ -274,8 +293,11 @@ def main():
         del src, dst
     sched = None
     if args.schedule:
-        e_, p_, l_, t_ = (int(v) for v in args.schedule.split(","))
-        sched = dict(block_edge=e_, block_parts=p_, lanes_per_atom=l_, threads=t_)
+        v_ = [int(v) for v in args.schedule.split(",")]
+        if len(v_) not in (4, 5):
+            ap.error("--schedule takes 4 or 5 comma-separated integers")
+        sched = dict(block_edge=v_[0], block_parts=v_[1], lanes_per_atom=v_[2], threads=v_[3],
+                     build_threads=v_[4] if len(v_) == 5 else 0)
     prim = run_gpu(args.workload, steps, args.warmup, sched)
     print(f"# primary {args.workload}: {prim['value']:.4g} atom-steps/s, {prim['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)

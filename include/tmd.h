@@ -79,12 +79,12 @@ typedef struct {
     int64_t step;            /* time-step counter of the current state */
     int32_t n_boxes;
     int32_t n_blocks;        /* blocks of cells, one workgroup each */
-    int32_t block_threads;   /* threads per block workgroup */
+    int32_t block_threads;   /* threads per force workgroup */
     int32_t lds_atoms;       /* atoms of a block neighborhood staged in LDS */
     int32_t block_edge;      /* cells per block edge (2 or 3) */
     int32_t block_parts;     /* workgroups per block (1, 2 or 4) */
     int32_t lanes_per_atom;  /* lanes sharing one atom's force sum (1, 2 or 4) */
-    int32_t reserved_;
+    int32_t build_threads;   /* threads per list-build (and adjoint) workgroup */
 } tmd_info;
 
 /* Kernel classes reported by tmd_get_timing(). */
@@ -205,9 +205,12 @@ tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
  * wavefront per atom in the force kernel, lane p taking the list's groups of
  * eight entries p, p + lanes_per_atom, ... (more parallelism for small
  * systems; 0 keeps the current value; a new value resets threads to its
- * default).  threads: threads per
- * block workgroup, a multiple of 64 in [64, 1024] (0 keeps the current
- * value).  lds_atoms: how many atoms of a block's neighborhood may be staged
+ * default).  threads: threads per force workgroup, a multiple of 64 in
+ * [64, 1024] (0 keeps the current value).  build_threads: threads per
+ * workgroup of the kernels that take one lane per atom (the list build,
+ * the adjoint's Hessian-vector product and tmd_get_neighbors), same range
+ * (0 keeps the current value; a new edge or block_parts resets it to its
+ * default).  lds_atoms: how many atoms of a block's neighborhood may be staged
  * in LDS, a multiple of 64 in [64, 4096] (0 keeps the current value; lowered
  * at the next state upload if the device's per-workgroup LDS cannot hold
  * twice that many 24-byte slots); blocks whose neighborhood holds more atoms
@@ -215,13 +218,19 @@ tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
  * stale (the next integrate rebuilds it; compute_forces needs
  * tmd_build_neighbors first).  TMD_EINVAL for other values. */
 tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms, int32_t block_edge,
-                            int32_t block_parts, int32_t lanes_per_atom);
+                            int32_t block_parts, int32_t lanes_per_atom, int32_t build_threads);
 
 /* Pick the schedule (block edge 2 or 3, workgroups per block 1, 2 or 4,
- * lanes per atom 1, 2 or 4, threads per block workgroup) with the
- * shortest time per step for the current positions - one force evaluation
- * plus 1/rebuild_every of a list build: times `repeats` force evaluations
- * and one build per candidate on `stream` with HIP events (synchronises).  Positions and velocities are not changed, but the list is
+ * lanes per atom 1, 2 or 4, threads per force and per build workgroup)
+ * with the shortest time per step for the current positions - one launch
+ * of the step kernel (force sum, kicks and drift) plus 1/rebuild_every of a
+ * list build: for each edge and workgroups per block, times `repeats`
+ * builds per build thread count and `repeats` step-kernel launches per
+ * (lanes, threads) candidate on `stream` with HIP events
+ * (synchronises; the launches work on spare copies of the state).  Tune
+ * on a state like the one the run will see: every wavefront runs to the
+ * longest list among its atoms, so a perfect lattice, where all lists have
+ * the same length, favours fewer lanes per atom than a liquid does.  Positions and velocities are not changed, but the list is
  * rebuilt at the current positions, as by tmd_build_neighbors(); call it
  * right after tmd_set_state() or at a rebuild step to keep the fixed
  * rebuild schedule. */

@@ -226,9 +226,10 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
 }
 
 // Threads per block workgroup: ~15% above the mean number of atoms one
-// workgroup takes (a block's atoms split over d.parts workgroups).
-int default_threads(const Dims &d) {
-    const double per_wg = double(d.nt) / (double(d.nblk) * d.parts) * d.lpa;
+// workgroup takes (a block's atoms split over d.parts workgroups) times the
+// lanes each atom gets.
+int default_threads(const Dims &d, int lanes) {
+    const double per_wg = double(d.nt) / (double(d.nblk) * d.parts) * lanes;
     return std::min(kMaxThreads, std::max(64, round_up(int(per_wg * 1.15), 64)));
 }
 
@@ -301,7 +302,8 @@ bool layout_blocks(tmd_system *s, int E) {
         d.parts = 1;
     if (d.lpa < 1)
         d.lpa = 1;
-    d.threads = default_threads(d);
+    d.threads = default_threads(d, d.lpa);
+    d.bthreads = default_threads(d, 1);
     s->blk_box.assign(size_t(blocks), 0);
     for (int32_t k = 0; k < d.nbox; ++k) {
         const Box &B = s->boxes[size_t(k)];
@@ -742,12 +744,14 @@ tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
     info->block_edge = s->d.edge;
     info->block_parts = s->d.parts;
     info->lanes_per_atom = s->d.lpa;
+    info->build_threads = s->d.bthreads;
     return TMD_OK;
 }
 
 tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, int32_t block_edge,
-                            int32_t block_parts, int32_t lanes_per_atom) {
-    if (!s || threads < 0 || threads > kMaxThreads || threads % 64 != 0 || lds_atoms < 0 || lds_atoms > kMaxCap ||
+                            int32_t block_parts, int32_t lanes_per_atom, int32_t build_threads) {
+    if (!s || threads < 0 || threads > kMaxThreads || threads % 64 != 0 || build_threads < 0 ||
+        build_threads > kMaxThreads || build_threads % 64 != 0 || lds_atoms < 0 || lds_atoms > kMaxCap ||
         lds_atoms % 64 != 0 || (block_edge != 0 && block_edge != 2 && block_edge != 3) ||
         (block_parts != 0 && block_parts != 1 && block_parts != 2 && block_parts != 4) ||
         (lanes_per_atom != 0 && lanes_per_atom != 1 && lanes_per_atom != 2 && lanes_per_atom != 4))
@@ -759,15 +763,18 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
     }
     if (block_parts != 0 && block_parts != s->d.parts) {
         s->d.parts = block_parts;  // the list does not depend on it
-        s->d.threads = default_threads(s->d);
+        s->d.threads = default_threads(s->d, s->d.lpa);
+        s->d.bthreads = default_threads(s->d, 1);
     }
     if (lanes_per_atom != 0 && lanes_per_atom != s->d.lpa) {
         s->d.lpa = lanes_per_atom;  // nor on this
-        s->d.threads = default_threads(s->d);
+        s->d.threads = default_threads(s->d, s->d.lpa);
         s->force_valid = false;      // forces are summed in another order
     }
     if (threads > 0)
         s->d.threads = threads;
+    if (build_threads > 0)
+        s->d.bthreads = build_threads;
     if (lds_atoms > 0 && lds_atoms != s->d.cap) {
         s->d.cap = lds_atoms;
         s->prepared = false;  // LDS attribute of the block kernels must follow
@@ -778,13 +785,25 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
     return TMD_OK;
 }
 
-// Mean duration (ms) of `repeats` force evaluations on the current list.
+// Mean duration (ms) of `repeats` launches of the kernel an integrate step
+// runs (force sum, two kicks and the drift) on the current list.  They read
+// the current positions and a copy of the velocities in the spare velocity
+// buffer, and write the spare position buffer: the state is not changed.
 static hipError_t time_force(tmd_system *s, int32_t repeats, hipStream_t hs, hipEvent_t a, hipEvent_t b, float &ms) {
-    hipError_t e = launch_force(s->d, s->b, s->cur, 0, false, hs);  // warm-up; the state is not changed
+    Buffers &bf = s->b;
+    const int c = s->cur.x, o = s->cur.o;
+    const size_t bytes = size_t(s->d.nt) * sizeof(double);
+    hipError_t e = hipMemcpyAsync(bf.vx[1 - o], bf.vx[o], bytes, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bf.vy[1 - o], bf.vy[o], bytes, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bf.vz[1 - o], bf.vz[o], bytes, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess)  // warm-up
+        e = launch_force_at(s->d, bf, bf.pos(c), bf.pos(1 - c), 1 - o, 2, false, hs);
     if (e == hipSuccess)
         e = hipEventRecord(a, hs);
     for (int32_t r = 0; r < repeats && e == hipSuccess; ++r)
-        e = launch_force(s->d, s->b, s->cur, 0, false, hs);
+        e = launch_force_at(s->d, bf, bf.pos(c), bf.pos(1 - c), 1 - o, 2, false, hs);
     if (e == hipSuccess)
         e = hipEventRecord(b, hs);
     if (e == hipSuccess)
@@ -825,32 +844,49 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     if (e != hipSuccess)
         return hip_fail(s, e, "autotune");
     float best = 1e30f;
-    int32_t best_edge = s->d.edge, best_t = s->d.threads, best_p = s->d.parts, best_l = s->d.lpa;
+    int32_t best_edge = s->d.edge, best_t = s->d.threads, best_p = s->d.parts, best_l = s->d.lpa,
+            best_bt = s->d.bthreads;
     for (int32_t E = 2; E <= kMaxEdge && e == hipSuccess; ++E) {
         layout_blocks(s, E);
         s->list_valid = s->force_valid = false;
         if ((st = rebuild(s, hs)) != TMD_OK)
             break;
-        for (int32_t c = 0; c < 3 * 3 && e == hipSuccess; ++c) {
-            const int32_t P = 1 << (c % 3), Lp = 1 << (c / 3);
+        for (int32_t P = 1; P <= kMaxParts && e == hipSuccess; P *= 2) {
             s->d.parts = P;
-            s->d.lpa = Lp;
-            const int32_t t0 = default_threads(s->d);
-            for (int32_t t = std::max(64, t0 - 128); t <= std::min(kMaxThreads, t0 + 128) && e == hipSuccess;
+            // the list build runs one lane per atom whatever the force
+            // kernel's lanes: its thread count is tuned on its own
+            float mb = 1e30f;
+            int32_t bt_best = default_threads(s->d, 1);
+            const int32_t b0 = bt_best;
+            for (int32_t t = std::max(64, b0 - 128); t <= std::min(kMaxThreads, b0 + 128) && e == hipSuccess;
                  t += 64) {
-                s->d.threads = t;
-                // cost per step: one force evaluation plus the list build's share
-                float ms = 0.0f, mb = 0.0f;
-                e = time_force(s, repeats, hs, a, b, ms);
-                if (e == hipSuccess)
-                    e = time_build(s, (repeats + 1) / 2, hs, a, b, mb);
-                ms += mb / float(s->rebuild_every);
-                if (e == hipSuccess && ms < best) {
-                    best = ms;
-                    best_edge = E;
-                    best_t = t;
-                    best_p = P;
-                    best_l = Lp;
+                s->d.bthreads = t;
+                float m = 0.0f;
+                e = time_build(s, repeats, hs, a, b, m);
+                if (e == hipSuccess && m < mb) {
+                    mb = m;
+                    bt_best = t;
+                }
+            }
+            s->d.bthreads = bt_best;
+            for (int32_t Lp = 1; Lp <= 4 && e == hipSuccess; Lp *= 2) {
+                s->d.lpa = Lp;
+                const int32_t t0 = default_threads(s->d, Lp);
+                for (int32_t t = std::max(64, t0 - 128); t <= std::min(kMaxThreads, t0 + 128) && e == hipSuccess;
+                     t += 64) {
+                    s->d.threads = t;
+                    // cost per step: one force evaluation plus the list build's share
+                    float ms = 0.0f;
+                    e = time_force(s, repeats, hs, a, b, ms);
+                    ms += mb / float(s->rebuild_every);
+                    if (e == hipSuccess && ms < best) {
+                        best = ms;
+                        best_edge = E;
+                        best_t = t;
+                        best_p = P;
+                        best_l = Lp;
+                        best_bt = bt_best;
+                    }
                 }
             }
         }
@@ -865,6 +901,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     s->d.parts = best_p;
     s->d.lpa = best_l;
     s->d.threads = best_t;
+    s->d.bthreads = best_bt;
     s->list_valid = s->force_valid = false;
     return rebuild(s, hs);
 }

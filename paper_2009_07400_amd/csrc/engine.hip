@@ -1392,7 +1392,7 @@ hipError_t launch_gather(const Dims &d, const double *const src[3], const int32_
 
 hipError_t launch_hvp(const Dims &d, Buffers &b, const Pos &x, const Pos &w, const Pos &lam_x, const Pos &wout,
                       double mult, bool drift_adj, double *partials, hipStream_t s) {
-    k_hvp<<<block_grid(d.nblk * d.parts), d.threads, 2 * hood_lds_bytes(d.cap), s>>>(
+    k_hvp<<<block_grid(d.nblk * d.parts), d.bthreads, 2 * hood_lds_bytes(d.cap), s>>>(
         d, b.boxes, b.blk_box, x, b.hood_tab, b.nbr_count, b.nbr, w, lam_x, wout, mult, drift_adj ? 1 : 0,
         partials);
     return hipGetLastError();
@@ -1458,7 +1458,7 @@ hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
 }
 
 hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
-    k_build<<<block_grid(d.nblk * d.parts), d.threads, hood_lds_bytes(d.cap), s>>>(
+    k_build<<<block_grid(d.nblk * d.parts), d.bthreads, hood_lds_bytes(d.cap), s>>>(
         d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.hood_tab, b.nbr_count, b.nbr, b.err);
     return hipGetLastError();
 }
@@ -1518,7 +1518,7 @@ hipError_t launch_reduce(const Dims &d, const Buffers &b, double *out, int row_l
 
 hipError_t launch_export_neighbors(const Dims &d, const Buffers &b, Cursor c, int32_t *counts, int32_t *ids,
                                    hipStream_t s) {
-    k_export_neighbors<<<block_grid(d.nblk), d.threads, 0, s>>>(d, b.boxes, b.blk_box, b.cell_start, b.nbr_count,
+    k_export_neighbors<<<block_grid(d.nblk), d.bthreads, 0, s>>>(d, b.boxes, b.blk_box, b.cell_start, b.nbr_count,
                                                                 b.nbr, b.orig[c.o], counts, ids);
     return hipGetLastError();
 }

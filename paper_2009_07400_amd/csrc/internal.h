@@ -60,7 +60,8 @@ struct Dims {
     int32_t cpb;      // E^3, cell slots per block
     int32_t maxnb;    // list capacity per atom
     int32_t cap;      // atoms a block neighborhood may stage in LDS
-    int32_t threads;  // threads per block workgroup (64..kMaxThreads, multiple of 64)
+    int32_t threads;  // threads per force workgroup (64..kMaxThreads, multiple of 64)
+    int32_t bthreads; // threads per workgroup of the one-lane-per-atom block kernels (list build, adjoint, export)
     int32_t nchunk;   // 4-entry list chunks per atom: ceil(maxnb / 4) + 1 (a spare chunk of padding)
     int32_t parts;    // workgroups per block (1, 2 or 4), each taking a share of the block's atoms
     int32_t lpa;      // lanes per atom in the force kernel (1, 2 or 4), each taking every lpa-th list chunk

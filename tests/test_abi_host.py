@@ -130,11 +130,19 @@ def test_batch_create_and_validation():
         abi.tmd_set_schedule(h, 0, 0, 0, 4)
         assert abi.tmd_get_info(h)["block_parts"] == 4
         assert abi.tmd_get_info(h)["lanes_per_atom"] == 1
+        b0 = abi.tmd_get_info(h)["build_threads"]
+        assert b0 % 64 == 0 and 64 <= b0 <= 1024
+        t0 = abi.tmd_get_info(h)["block_threads"]
         abi.tmd_set_schedule(h, 0, 0, 0, 0, 2)
-        assert abi.tmd_get_info(h)["lanes_per_atom"] == 2
-        for bad in ((100, 0, 0, 0, 0), (1088, 0, 0, 0, 0), (0, 100, 0, 0, 0), (0, 4160, 0, 0, 0), (-64, 0, 0, 0, 0),
-                    (0, 0, 4, 0, 0), (0, 0, 1, 0, 0), (0, 0, 0, 3, 0), (0, 0, 0, 8, 0), (0, 0, 0, -1, 0),
-                    (0, 0, 0, 0, 3), (0, 0, 0, 0, 8), (0, 0, 0, 0, -1)):
+        info = abi.tmd_get_info(h)
+        # a second lane per atom widens the force workgroups, not the build's
+        assert info["lanes_per_atom"] == 2 and info["build_threads"] == b0 and info["block_threads"] >= t0
+        abi.tmd_set_schedule(h, 0, 0, 0, 0, 0, 320)
+        assert abi.tmd_get_info(h)["build_threads"] == 320
+        for bad in ((100, 0, 0, 0, 0, 0), (1088, 0, 0, 0, 0, 0), (0, 100, 0, 0, 0, 0), (0, 4160, 0, 0, 0, 0),
+                    (-64, 0, 0, 0, 0, 0), (0, 0, 4, 0, 0, 0), (0, 0, 1, 0, 0, 0), (0, 0, 0, 3, 0, 0),
+                    (0, 0, 0, 8, 0, 0), (0, 0, 0, -1, 0, 0), (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 8, 0),
+                    (0, 0, 0, 0, -1, 0), (0, 0, 0, 0, 0, 100), (0, 0, 0, 0, 0, 1088), (0, 0, 0, 0, 0, -64)):
             with pytest.raises(abi.TmdError):
                 abi.tmd_set_schedule(h, *bad)
     finally:

@@ -120,12 +120,14 @@ def test_batch_equals_single_box_runs_bitwise():
         off += n
 
 
-@pytest.mark.parametrize("threads,lds,edge,parts,lpa", [
-    (64, 0, 2, 1, 1), (128, 0, 2, 1, 1), (192, 0, 2, 1, 1), (256, 0, 2, 1, 1), (0, 64, 2, 1, 1), (0, 0, 3, 1, 1),
-    (384, 0, 3, 1, 1), (1024, 0, 3, 1, 1), (0, 64, 3, 1, 1), (0, 0, 2, 2, 1), (64, 0, 2, 4, 1), (0, 0, 3, 2, 1),
-    (128, 0, 3, 4, 1), (0, 64, 3, 4, 1), (0, 0, 2, 1, 2), (128, 0, 2, 2, 2), (0, 64, 2, 1, 2), (0, 0, 3, 1, 2),
-    (256, 0, 3, 4, 2), (0, 64, 3, 2, 2), (0, 0, 2, 1, 4), (0, 64, 2, 2, 4), (512, 0, 3, 1, 4)])
-def test_schedule_does_not_change_trajectory(threads, lds, edge, parts, lpa):
+@pytest.mark.parametrize("threads,lds,edge,parts,lpa,bthreads", [
+    (64, 0, 2, 1, 1, 0), (128, 0, 2, 1, 1, 0), (192, 0, 2, 1, 1, 0), (256, 0, 2, 1, 1, 0), (0, 64, 2, 1, 1, 0),
+    (0, 0, 3, 1, 1, 0), (384, 0, 3, 1, 1, 0), (1024, 0, 3, 1, 1, 0), (0, 64, 3, 1, 1, 0), (0, 0, 2, 2, 1, 0),
+    (64, 0, 2, 4, 1, 0), (0, 0, 3, 2, 1, 0), (128, 0, 3, 4, 1, 0), (0, 64, 3, 4, 1, 0), (0, 0, 2, 1, 2, 0),
+    (128, 0, 2, 2, 2, 0), (0, 64, 2, 1, 2, 0), (0, 0, 3, 1, 2, 0), (256, 0, 3, 4, 2, 0), (0, 64, 3, 2, 2, 0),
+    (0, 0, 2, 1, 4, 0), (0, 64, 2, 2, 4, 0), (512, 0, 3, 1, 4, 0), (0, 0, 2, 1, 1, 64), (0, 64, 3, 1, 2, 64),
+    (0, 0, 3, 2, 1, 1024), (0, 64, 2, 1, 4, 1024)])
+def test_schedule_does_not_change_trajectory(threads, lds, edge, parts, lpa, bthreads):
     """Any schedule gives the trajectory of the default one bit for bit -
     against the default with the same lanes per atom (two lanes sum each
     atom's force as two interleaved halves, a different rounding)."""
@@ -136,7 +138,8 @@ def test_schedule_does_not_change_trajectory(threads, lds, edge, parts, lpa):
     ref.integrate(30)
     p0, v0, _ = ref.get_state()
     g = System(s.n, s.L)
-    g.set_schedule(threads=threads, lds_atoms=lds, block_edge=edge, block_parts=parts, lanes_per_atom=lpa)
+    g.set_schedule(threads=threads, lds_atoms=lds, block_edge=edge, block_parts=parts, lanes_per_atom=lpa,
+                   build_threads=bthreads)
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
     g.integrate(30)
     p1, v1, _ = g.get_state()
@@ -156,6 +159,7 @@ def test_autotune_keeps_state():
     g.sync()
     assert sc["block_edge"] in (2, 3) and sc["block_parts"] in (1, 2, 4) and sc["lanes_per_atom"] in (1, 2, 4)
     assert sc["block_threads"] % 64 == 0 and 64 <= sc["block_threads"] <= 1024
+    assert sc["build_threads"] % 64 == 0 and 64 <= sc["build_threads"] <= 1024
     assert torch.equal(p0, p1) and torch.equal(v0, v1)
 
 
