@@ -671,7 +671,7 @@ tmd_status tmd_get_state(const tmd_system *cs, double *const pos[3], double *con
     const int c = s->cur.x, o = s->cur.o;
     Timed t(s, TMD_T_COPY, hs);
     if (pos) {
-        hipError_t e = launch_unload(s->d, s->b.x[c], s->b.y[c], s->b.z[c], s->b.orig[o], pos, hs);
+        hipError_t e = launch_unload_pos(s->d, s->b, s->b.pos(c), s->b.orig[o], pos, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "get_state");
     }
@@ -991,6 +991,10 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
     carve_adj(s->dmax,R, T, static_cast<char *>(ws), &a);
     Buffers &b = s->b;
     hipError_t e = launch_fill_f64(a.acc, 0.0, 2 * s->d.nbox, hs);
+    // the recomputed positions of a segment go to the trajectory store, whose
+    // buffers need the NaN sentinel atom that list padding points at
+    if (e == hipSuccess)
+        e = launch_traj_sentinels(a.traj, s->d.ntp, s->d.nt, R, hs);
     double *const lo_x[3] = {a.lo, a.lo + nt, a.lo + 2 * nt};
     double *const lo_v[3] = {a.lo + 3 * nt, a.lo + 4 * nt, a.lo + 5 * nt};
     Pos wa = a.wa, wb = a.wb;

@@ -11,7 +11,8 @@
 namespace tmd {
 
 // Minimum-image difference along one axis: shift d by one box length when
-// |d| > L/2 (positions are kept in [0, L), so one shift suffices).
+// |d| > L/2 (positions lie within a fraction of a cell of [0, L), so one
+// shift suffices).
 __device__ __forceinline__ double mic(double d, double L, double halfL) {
     d = (d > halfL) ? d - L : d;
     d = (d < -halfL) ? d + L : d;
@@ -50,10 +51,20 @@ __device__ __forceinline__ double pair_delta(double xi, double yi, double zi, do
     return s;
 }
 
-// The same pair geometry with |d|^2 formed by fused multiply-adds, for the
-// kernels that evaluate forces and their derivatives: there |d|^2 only
+// Image of partner coordinate xj nearest to xi, given d = xi - xj: xj
+// shifted by one box length when |d| > L/2 (xj + 0.0 is xj itself).
+__device__ __forceinline__ double partner_image(double xj, double d, double L, double halfL) {
+    return xj + ((d > halfL) ? L : ((d < -halfL) ? -L : 0.0));
+}
+
+// The pair geometry of the kernels that evaluate forces and their
+// derivatives, with |d|^2 formed by fused multiply-adds: there it only
 // decides the cutoff test, and the force kernel and the adjoint's
-// Hessian-vector product must take that decision identically.
+// Hessian-vector product must take that decision identically.  Across a
+// face the difference is taken to the partner's nearest image, xi - (xj +/-
+// L), the same two roundings as in pair_delta_img() on a neighborhood copy
+// whose positions were moved to their images near the block (see
+// nearest_image()), so both give the same bits.
 __device__ __forceinline__ double pair_delta_fma(double xi, double yi, double zi, double xj, double yj, double zj,
                                                 double L, double halfL, double halfL2, double &dx, double &dy,
                                                 double &dz) {
@@ -62,12 +73,34 @@ __device__ __forceinline__ double pair_delta_fma(double xi, double yi, double zi
     dz = zi - zj;
     double s = fma(dz, dz, fma(dy, dy, dx * dx));
     if (s >= halfL2) {
-        dx = mic(dx, L, halfL);
-        dy = mic(dy, L, halfL);
-        dz = mic(dz, L, halfL);
+        dx = xi - partner_image(xj, dx, L, halfL);
+        dy = yi - partner_image(yj, dy, L, halfL);
+        dz = zi - partner_image(zj, dz, L, halfL);
         s = fma(dz, dz, fma(dy, dy, dx * dx));
     }
     return s;
+}
+
+// pair_delta_fma() for a partner position that already is the image nearest
+// to xi: the plain difference.
+__device__ __forceinline__ double pair_delta_img(double xi, double yi, double zi, double xj, double yj, double zj,
+                                                double &dx, double &dy, double &dz) {
+    dx = xi - xj;
+    dy = yi - yj;
+    dz = zi - zj;
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+// Image of coordinate x (in [0, L)) nearest to c: x shifted by one box
+// length when |x - c| > L/2.  A neighborhood copied this way around its
+// block's center holds, for every atom i of the block and every list partner
+// j, the image of j nearest to i - provided the box has at least E + 4 cells
+// per axis and atoms move less than a third of cutoff + skin between list
+// builds: then |image - c| <= E a / 2 + (cutoff + skin) + 3 drift < L / 2
+// for cells of side a >= cutoff + skin.
+__device__ __forceinline__ double nearest_image(double x, double c, double L, double halfL) {
+    const double d = x - c;
+    return x + ((d > halfL) ? -L : ((d < -halfL) ? L : 0.0));
 }
 
 // 1/s for s > 0: hardware reciprocal estimate refined by one Newton-Raphson
@@ -85,12 +118,17 @@ __device__ __forceinline__ double recip_exact(double s) {
     return fma(r, fma(-s, r, 1.0), r);
 }
 
-// Wrap a coordinate that moved by less than one box length into [0, L).
+// Wrap a coordinate less than one box length outside [0, L) into [0, L)
+// (a tiny negative p, for which p + L rounds to L, maps to 0), so that
+// wrapping twice changes nothing.
 __device__ __forceinline__ double wrap(double p, double L) {
     if (p >= L)
         p -= L;
-    if (p < 0.0)
+    if (p < 0.0) {
         p += L;
+        if (p >= L)
+            p = 0.0;
+    }
     return p;
 }
 

@@ -253,6 +253,38 @@ struct GlobalPos {
     }
 };
 
+// Periodic images of a neighborhood copy.  With `on`, every staged position
+// is moved to its image nearest to the block's center (nearest_image()), so
+// that for every atom of the block each list partner's copy is its image
+// nearest to that atom and the pair loops take plain differences (no
+// minimum-image test per pair).  `on` needs at least E + 4 cells per axis;
+// the list build stages without it, as its neighbor decisions take the
+// minimum image of the raw difference.
+struct HoodImage {
+    bool on;
+    double cx, cy, cz, L, halfL;
+};
+
+__device__ __forceinline__ HoodImage hood_image(const Box &B, int lb, bool want) {
+    HoodImage m;
+    m.on = want && B.nc >= B.edge + 4;
+    const int nbx = B.nbx;
+    const int bc[3] = {lb % nbx, (lb / nbx) % nbx, lb / (nbx * nbx)};
+    double c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int c0 = B.edge * bc[a];
+        const int e = min(B.edge, B.nc - c0);
+        c[a] = (double(c0) + 0.5 * double(e)) * B.side;
+    }
+    m.cx = c[0];
+    m.cy = c[1];
+    m.cz = c[2];
+    m.L = B.L;
+    m.halfL = B.halfL;
+    return m;
+}
+
 // Copy the neighborhood's positions into LDS (the global loads are
 // coalesced within each cell), and a NaN sentinel atom at slot `sent` (the
 // LDS capacity, the same slot for every block): list padding points there,
@@ -260,7 +292,7 @@ struct GlobalPos {
 // no test.  Ends with a workgroup barrier.
 __device__ __forceinline__ void hood_stage(const Hood &h, int total, int sent, const double *__restrict__ x,
                                            const double *__restrict__ y, const double *__restrict__ z,
-                                           lds_double *s) {
+                                           lds_double *s, const HoodImage &im) {
     // four slots per thread per round: the four searches, then all twelve
     // global loads in flight together, then the LDS writes.  Every memory
     // operation is unconditional: a slot past the end copies the last atom
@@ -282,6 +314,14 @@ __device__ __forceinline__ void hood_stage(const Hood &h, int total, int sent, c
             px[r] = x[g[r]];
             py[r] = y[g[r]];
             pz[r] = z[g[r]];
+        }
+        if (im.on) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                px[r] = nearest_image(px[r], im.cx, im.L, im.halfL);
+                py[r] = nearest_image(py[r], im.cy, im.L, im.halfL);
+                pz[r] = nearest_image(pz[r], im.cz, im.L, im.halfL);
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -326,6 +366,15 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c) {
 
 // ------------------------------------------------------------------ utility
 
+// NaN sentinel atom at slot nt of position buffers 1..count of a
+// trajectory store (buffer j holds x, y, z at stride np from
+// traj + 3 j np): 32-bit list padding points there.
+__global__ void k_traj_sentinels(double *traj, int64_t np, int nt, int count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 3 * count)
+        traj[(int64_t(t / 3 + 1) * 3 + t % 3) * np + nt] = __builtin_nan("");
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n)
@@ -369,21 +418,32 @@ __global__ __launch_bounds__(kAtomThreads) void k_load_state(Dims d, const Box *
     orig[i] = i;
 }
 
+// Scatter per-atom vectors back to original order; with boxes, they are
+// positions, wrapped into [0, L) on the way (they drift unwrapped between
+// list builds).
 __global__ __launch_bounds__(kAtomThreads) void k_unload(int n, const double *__restrict__ ax,
                                                          const double *__restrict__ ay,
                                                          const double *__restrict__ az,
                                                          const int32_t *__restrict__ orig, double *o0, double *o1,
-                                                         double *o2) {
+                                                         double *o2, const Box *__restrict__ boxes,
+                                                         const int32_t *__restrict__ atom_box) {
     const int p = blockIdx.x * kAtomThreads + threadIdx.x;
     if (p >= n)
         return;
     const int o = orig[p];
+    double a = ax[p], b = ay[p], c = az[p];
+    if (boxes) {
+        const double L = boxes[atom_box[p]].L;
+        a = wrap(a, L);
+        b = wrap(b, L);
+        c = wrap(c, L);
+    }
     if (o0)
-        o0[o] = ax[p];
+        o0[o] = a;
     if (o1)
-        o1[o] = ay[p];
+        o1[o] = b;
     if (o2)
-        o2[o] = az[p];
+        o2[o] = c;
 }
 
 // ------------------------------------------------------------------ binning
@@ -399,7 +459,8 @@ __global__ __launch_bounds__(kAtomThreads) void k_bin_count(Dims d, const Box *_
     if (i >= d.nt)
         return;
     const Box &B = boxes[atom_box[i]];
-    const double px = x[i], py = y[i], pz = z[i];
+    // positions drift unwrapped between list builds
+    const double px = wrap(x[i], B.L), py = wrap(y[i], B.L), pz = wrap(z[i], B.L);
     if (!(isfinite(px) && isfinite(py) && isfinite(pz)))
         atomicOr(err, kErrNonFinite);
     const int c = cell_slot(B, cell_coord(px, B.side, B.nc), cell_coord(py, B.side, B.nc),
@@ -508,7 +569,8 @@ __global__ __launch_bounds__(kAtomThreads) void k_scatter(int n, const int32_t *
 // place is its cell start plus the number of cell members with a smaller
 // original id.  Then positions, velocities and ids move to that place.
 __global__ __launch_bounds__(kAtomThreads) void k_rank_permute(
-    int n, const int32_t *__restrict__ tmp_idx, const int32_t *__restrict__ cell_of,
+    int n, const Box *__restrict__ boxes, const int32_t *__restrict__ atom_box, const int32_t *__restrict__ tmp_idx,
+    const int32_t *__restrict__ cell_of,
     const int32_t *__restrict__ cell_start, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
     const double *__restrict__ vz, const int32_t *__restrict__ orig, double *x2, double *y2, double *z2,
@@ -524,9 +586,10 @@ __global__ __launch_bounds__(kAtomThreads) void k_rank_permute(
     for (int r = b; r < e; ++r)
         rank += int(orig[tmp_idx[r]] < key);
     const int dst = b + rank;
-    x2[dst] = x[p];
-    y2[dst] = y[p];
-    z2[dst] = z[p];
+    const double L = boxes[atom_box[dst]].L;  // source and destination slots lie in one box
+    x2[dst] = wrap(x[p], L);
+    y2[dst] = wrap(y[p], L);
+    z2[dst] = wrap(z[p], L);
     vx2[dst] = vx[p];
     vy2[dst] = vy[p];
     vz2[dst] = vz[p];
@@ -570,7 +633,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     const bool fits = total <= d.cap;
     lds_double *S = (lds_double *)lds;
     if (fits)
-        hood_stage(h, total, d.cap, x, y, z, S);
+        hood_stage(h, total, d.cap, x, y, z, S, hood_image(B, lb, false));
     // list padding points at the NaN sentinel: LDS slot cap, or global slot nt
     const int sentinel = fits ? d.cap : d.nt;
     uint16_t *nbr16 = reinterpret_cast<uint16_t *>(nbr);
@@ -709,14 +772,18 @@ __device__ __forceinline__ void fetch2(const POS &pos, int j0, int j1, Duo &q) {
 // use fused multiply-adds here: it decides only the cutoff test, whose pairs
 // at s within an ulp of cutoff^2 have a vanishing share (the neighbor sets
 // themselves come from the build's unfused sum).  mf6 and mu6 are -f6 and
-// -u6.  A NaN sentinel entry fails both tests and adds nothing.
-template <bool THERMO>
+// -u6.  A NaN sentinel entry fails both tests and adds nothing.  IMG: the
+// partner positions come from a neighborhood copy moved to its images near
+// the block (HoodImage), so the difference needs no minimum-image test.
+template <bool THERMO, bool IMG>
 __device__ __forceinline__ void eval2(const Duo &q, double xi, double yi, double zi, const Box &B, double mf6,
                                       double mu6, double &ax, double &ay, double &az, double &u, double &w) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         double dx, dy, dz;
-        const double s = pair_delta_fma(xi, yi, zi, q.x[m], q.y[m], q.z[m], B.L, B.halfL, B.halfL2, dx, dy, dz);
+        // with IMG the partner positions already are the images nearest to i
+        const double s = IMG ? pair_delta_img(xi, yi, zi, q.x[m], q.y[m], q.z[m], dx, dy, dz)
+                             : pair_delta_fma(xi, yi, zi, q.x[m], q.y[m], q.z[m], B.L, B.halfL, B.halfL2, dx, dy, dz);
         if (s < B.rc2) {
             const double sr2 = recip(s);
             const double q3 = sr2 * sr2 * sr2;
@@ -732,69 +799,34 @@ __device__ __forceinline__ void eval2(const Duo &q, double xi, double yi, double
     }
 }
 
-// Sum over one atom's list (c entries in chunks of four).  Index chunks are
-// read with 16-byte non-temporal loads (the list is streamed once per step
-// and should not displace positions from the caches) about three chunks
-// ahead of use, the positions of two entries two entries ahead.  The loop
-// body covers four chunks so that every in-flight value lands in the
-// register that consumes it (no copies that would force an early wait), and
-// all its memory operations are unconditional, so the wait counters stay
-// exact.  A chunk index past the atom's last chunk reads the chunk after it,
-// which the build fills with NaN sentinel entries (as it fills the rest of
-// the last chunk): such entries add nothing, so every lane runs the same
-// straight-line body until no lane of the wavefront has chunks left.  POS
-// reads positions from the LDS copy of the neighborhood or from global
-// memory.
-template <bool THERMO, class POS>
-__device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int p, int L, int c, const POS &pos,
+// Sum over one atom's list of 32-bit global indices (c entries in chunks of
+// four), for blocks whose neighborhood does not fit in LDS: positions come
+// from global memory.  With L lanes per atom the list is dealt in groups of
+// eight entries (two chunks), lane p taking groups p, p + L, ... in order -
+// the split and order of the 16-bit list's eight-entry chunks, so both give
+// the same sums.  Every group below ceil(c / 8) is whole: the build pads a
+// 32-bit list with NaN sentinel entries (global slot nt) through the chunk
+// after its last one, and a sentinel adds nothing.  A plain loop: this path
+// is rare, and a deeper pipeline here would set the register budget of the
+// whole kernel.
+template <bool THERMO>
+__device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int p, int L, int c, const GlobalPos &pos,
                                          double xi, double yi, double zi, const Box &B, double mf6, double mu6,
                                          double &ax, double &ay, double &az, double &u, double &w) {
-    const int nch = (c + 3) >> 2;
-    // with L lanes per atom the list is dealt in groups of eight entries (two
-    // chunks), lane p taking groups p, p + L, ... - the same split as the
-    // 16-bit list's eight-entry chunks, so both give the same sums
-    auto idx = [&](int k) { return 2 * (p + L * (k >> 1)) + (k & 1); };
-    auto ld = [&](int k) {
-        const int q = idx(k);
-        return __builtin_nontemporal_load(chunks + (q < nch ? q : nch) * 64);
-    };
-    // issue the look-ahead loads in chunk order (consumed oldest first)
-    v4i i0 = ld(0);
-    __builtin_amdgcn_sched_barrier(0);
-    v4i i1 = ld(1);
-    __builtin_amdgcn_sched_barrier(0);
-    v4i i2 = ld(2);
-    __builtin_amdgcn_sched_barrier(0);
-    v4i i3 = ld(3);
-    Duo P, Q;
-    fetch2(pos, i0[0], i0[1], P);
-    for (int k = 0;; k += 4) {
-        fetch2(pos, i0[2], i0[3], Q);
-        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2(pos, i1[0], i1[1], P);
-        i0 = ld(k + 4);
-        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2(pos, i1[2], i1[3], Q);
-        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2(pos, i2[0], i2[1], P);
-        i1 = ld(k + 5);
-        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2(pos, i2[2], i2[3], Q);
-        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2(pos, i3[0], i3[1], P);
-        i2 = ld(k + 6);
-        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2(pos, i3[2], i3[3], Q);
-        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2(pos, i0[0], i0[1], P);
-        i3 = ld(k + 7);
-        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        if (!__any(idx(k + 4) < nch))
-            break;
+    const int ng = (c + 7) >> 3;
+    for (int g = p; g < ng; g += L) {
+        const v4i e0 = __builtin_nontemporal_load(chunks + (2 * g) * 64);
+        const v4i e1 = __builtin_nontemporal_load(chunks + (2 * g + 1) * 64);
+        Duo q;
+        fetch2(pos, e0[0], e0[1], q);
+        eval2<THERMO, false>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, e0[2], e0[3], q);
+        eval2<THERMO, false>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, e1[0], e1[1], q);
+        eval2<THERMO, false>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2(pos, e1[2], e1[3], q);
+        eval2<THERMO, false>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
     }
-    // retire the unused look-ahead reads here, so the next atom's loop
-    // starts from an exactly known set of outstanding operations
-    __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) expcnt(7) lgkmcnt(0)
 }
 
 // Two LDS-slot entries packed in one 32-bit word of a 16-bit list.
@@ -815,7 +847,7 @@ __device__ __forceinline__ void fetch2w(const LdsPos &pos, int word, Duo &q) {
 // load them before the count is known.  The only exit
 // is at the end of the body: a loop with several exits loses the exact wait
 // counts at its head.
-template <bool THERMO>
+template <bool THERMO, bool IMG>
 __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int p, int L, int c,
                                            const LdsPos &pos, double xi, double yi, double zi, const Box &B,
                                            double mf6, double mu6, double &ax, double &ay, double &az, double &u,
@@ -830,23 +862,23 @@ __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i
     fetch2w(pos, i0[0], P);
     for (int k = 0;; k += 2) {
         fetch2w(pos, i0[1], Q);
-        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2w(pos, i0[2], P);
-        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2w(pos, i0[3], Q);
-        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2w(pos, i1[0], P);
         i0 = ld(k + 2);
-        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2w(pos, i1[1], Q);
-        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2w(pos, i1[2], P);
-        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2w(pos, i1[3], Q);
-        eval2<THERMO>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2w(pos, i0[0], P);
         i1 = ld(k + 3);
-        eval2<THERMO>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         if (!__any(p + L * (k + 2) < nch))
             break;
     }
@@ -890,6 +922,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     const bool fits = total <= d.cap;
     const LdsPos spos{(lds_double *)lds};
     const GlobalPos gpos{x, y, z};
+    const HoodImage im = hood_image(B, b - B.block_off, fits);
     // The operands of a lane's next atom (position, list length, velocity)
     // are loaded one pass ahead - those of the first pass before the staging
     // barrier, so their latency overlaps the staging.  Past the block's last
@@ -926,7 +959,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     if (hi > lo)
         load_atom(i);
     if (fits)
-        hood_stage(h, total, d.cap, x, y, z, spos.s);
+        hood_stage(h, total, d.cap, x, y, z, spos.s, im);
     // have every kernel argument in registers before the atom loop: a scalar
     // load still in flight at the pair loop's head costs it exact LDS waits
     asm volatile("" ::"s"(err), "s"(partials), "s"(xo), "s"(fx));
@@ -934,8 +967,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     for (; i < hi; i += T) {
         double ax = 0.0, ay = 0.0, az = 0.0;
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
-        if (fits)
-            pair_sum16<THERMO>(chunks, r0, r1, p, L, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        if (im.on)
+            pair_sum16<THERMO, true>(chunks, r0, r1, p, L, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        else if (fits)
+            pair_sum16<THERMO, false>(chunks, r0, r1, p, L, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         else
             pair_sum<THERMO>(chunks, p, L, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         // combine the L partial sums of the group (a butterfly: addition
@@ -962,8 +997,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
                 a = a + B.h * ax;
                 bb = bb + B.h * ay;
                 c = c + B.h * az;
-                const double nx = wrap(xi + B.dt * a, B.L), ny = wrap(yi + B.dt * bb, B.L),
-                             nz = wrap(zi + B.dt * c, B.L);
+                // not wrapped: between list builds an atom stays next to its
+                // block's cells (the binning wraps)
+                const double nx = xi + B.dt * a, ny = yi + B.dt * bb, nz = zi + B.dt * c;
                 xo[i] = nx;
                 yo[i] = ny;
                 zo[i] = nz;
@@ -1006,7 +1042,7 @@ __global__ __launch_bounds__(kAtomThreads) void k_drift(Dims d, const Box *__res
     vx[i] = a;
     vy[i] = b;
     vz[i] = c;
-    const double nx = wrap(x[i] + B.dt * a, B.L), ny = wrap(y[i] + B.dt * b, B.L), nz = wrap(z[i] + B.dt * c, B.L);
+    const double nx = x[i] + B.dt * a, ny = y[i] + B.dt * b, nz = z[i] + B.dt * c;  // wrapped at binning
     xo[i] = nx;
     yo[i] = ny;
     zo[i] = nz;
@@ -1095,7 +1131,7 @@ __device__ __forceinline__ lds_double *lds_slot6(lds_double *base, int slot) {
 }
 
 __device__ __forceinline__ void hood_stage6(const Hood &h, int total, int sent, const Pos &x, const Pos &w,
-                                            lds_double *s) {
+                                            lds_double *s, const HoodImage &im) {
     // as hood_stage: four slots per thread per round, unconditional memory
     // operations, a slot past the end copied into the scratch slot sent + 1
     constexpr int R = 4;
@@ -1118,6 +1154,14 @@ __device__ __forceinline__ void hood_stage6(const Hood &h, int total, int sent, 
             v[r][3] = w.x[g[r]];
             v[r][4] = w.y[g[r]];
             v[r][5] = w.z[g[r]];
+        }
+        if (im.on) {  // the force kernel's images (same positions, same shifts)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                v[r][0] = nearest_image(v[r][0], im.cx, im.L, im.halfL);
+                v[r][1] = nearest_image(v[r][1], im.cy, im.L, im.halfL);
+                v[r][2] = nearest_image(v[r][2], im.cz, im.L, im.halfL);
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1165,13 +1209,16 @@ struct HvpConst {
 //   (J w)_i += f(s) u + 2 f'(s) (d . u) d,  u = w_i - w_j,
 //   pe += (df/deps) (w_i . d),  ps += (df/dsigma) (w_i . d),
 // with q = sr2^3, f = sr2 q (f12 q - f6), 2 f' = sr2^2 q (g8 - g14 q),
-// df/deps = sr2 q (e12 q - e6), df/dsigma = sr2 q (h12 q - h6).
+// df/deps = sr2 q (e12 q - e6), df/dsigma = sr2 q (h12 q - h6).  IMG as in
+// eval2.
+template <bool IMG>
 __device__ __forceinline__ void hvp_pair(double xj, double yj, double zj, double wxj, double wyj, double wzj,
                                          double xi, double yi, double zi, double wxi, double wyi, double wzi,
                                          const Box &B, const HvpConst &k, double &gx, double &gy, double &gz,
                                          double &pe, double &ps) {
     double dx, dy, dz;
-    const double s = pair_delta_fma(xi, yi, zi, xj, yj, zj, B.L, B.halfL, B.halfL2, dx, dy, dz);
+    const double s = IMG ? pair_delta_img(xi, yi, zi, xj, yj, zj, dx, dy, dz)
+                         : pair_delta_fma(xi, yi, zi, xj, yj, zj, B.L, B.halfL, B.halfL2, dx, dy, dz);
     if (s < B.rc2) {
         const double sr2 = recip_exact(s);
         const double q3 = sr2 * sr2 * sr2;
@@ -1192,6 +1239,7 @@ __device__ __forceinline__ void hvp_pair(double xj, double yj, double zj, double
 }
 
 // hvp terms over a 16-bit list, with pair_sum16's loop discipline.
+template <bool IMG>
 __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int c, lds_double *S,
                                           double xi, double yi, double zi, double wxi, double wyi, double wzi,
                                           const Box &B, const HvpConst &k, double &gx, double &gy, double &gz,
@@ -1201,8 +1249,8 @@ __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0
     auto ev = [&](const Duo6 &q) {
 #pragma unroll
         for (int m = 0; m < 2; ++m)
-            hvp_pair(q.x[m], q.y[m], q.z[m], q.wx[m], q.wy[m], q.wz[m], xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz,
-                     pe, ps);
+            hvp_pair<IMG>(q.x[m], q.y[m], q.z[m], q.wx[m], q.wy[m], q.wz[m], xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy,
+                          gz, pe, ps);
     };
     Duo6 P, Q;
     fetch2w6(S, i0[0], P);
@@ -1258,8 +1306,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     lds_double *S = (lds_double *)lds;
+    const HoodImage im = hood_image(B, b - B.block_off, fits);
     if (fits)
-        hood_stage6(h, total, d.cap, x, w, S);
+        hood_stage6(h, total, d.cap, x, w, S, im);
     asm volatile("" ::"s"(partials), "s"(wout.x), "s"(lam.x));
     double pe = 0.0, ps = 0.0, unused = 0.0;
     int lo, hi;
@@ -1270,14 +1319,17 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
         double gx = 0.0, gy = 0.0, gz = 0.0;
         const int c = cnt[i];
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
-        if (fits) {
-            hvp_sum16(chunks, __builtin_nontemporal_load(chunks), __builtin_nontemporal_load(chunks + 64), c, S, xi,
-                      yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
+        if (im.on) {
+            hvp_sum16<true>(chunks, __builtin_nontemporal_load(chunks), __builtin_nontemporal_load(chunks + 64), c, S,
+                            xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
+        } else if (fits) {
+            hvp_sum16<false>(chunks, __builtin_nontemporal_load(chunks), __builtin_nontemporal_load(chunks + 64), c, S,
+                             xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
         } else {
             for (int kk = 0; kk < c; ++kk) {
                 const int j = nbr[nbr_index(i, kk, d.nchunk)];
-                hvp_pair(x.x[j], x.y[j], x.z[j], w.x[j], w.y[j], w.z[j], xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy,
-                         gz, pe, ps);
+                hvp_pair<false>(x.x[j], x.y[j], x.z[j], w.x[j], w.y[j], w.z[j], xi, yi, zi, wxi, wyi, wzi, B, k, gx,
+                                gy, gz, pe, ps);
             }
         }
         const double cc = mult * B.h;
@@ -1404,6 +1456,13 @@ hipError_t launch_grad_reduce(const Dims &d, const Buffers &b, const double *par
     return hipGetLastError();
 }
 
+hipError_t launch_traj_sentinels(double *traj, int64_t np, int nt, int count, hipStream_t s) {
+    if (count <= 0)
+        return hipSuccess;
+    k_traj_sentinels<<<(3 * count + 255) / 256, 256, 0, s>>>(traj, np, nt, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
     if (n <= 0)
         return hipSuccess;
@@ -1434,7 +1493,15 @@ hipError_t launch_load_state(const Dims &d, const double *const pos[3], const do
 
 hipError_t launch_unload(const Dims &d, const double *ax, const double *ay, const double *az, const int32_t *orig,
                          double *const out[3], hipStream_t s) {
-    k_unload<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, ax, ay, az, orig, out[0], out[1], out[2]);
+    k_unload<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, ax, ay, az, orig, out[0], out[1], out[2], nullptr,
+                                                         nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_unload_pos(const Dims &d, const Buffers &b, const Pos &p, const int32_t *orig, double *const out[3],
+                             hipStream_t s) {
+    k_unload<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, p.x, p.y, p.z, orig, out[0], out[1], out[2], b.boxes,
+                                                         b.atom_box);
     return hipGetLastError();
 }
 
@@ -1450,7 +1517,8 @@ hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
     k_scan_sums<<<1, 1024, 0, s>>>(b.scan_sums, nt, b.cell_start, d.ncs);
     k_scan_add<<<(d.ncs + 255) / 256, 256, 0, s>>>(b.cell_start, b.scan_sums, d.ncs);
     k_scatter<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.cell_of, b.slot, b.cell_start, b.tmp_idx);
-    k_rank_permute<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.tmp_idx, b.cell_of, b.cell_start, b.x[xc],
+    k_rank_permute<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.boxes, b.atom_box, b.tmp_idx, b.cell_of,
+                                                               b.cell_start, b.x[xc],
                                                                b.y[xc], b.z[xc], b.vx[o], b.vy[o], b.vz[o],
                                                                b.orig[o], b.x[xn], b.y[xn], b.z[xn], b.vx[on],
                                                                b.vy[on], b.vz[on], b.orig[on]);

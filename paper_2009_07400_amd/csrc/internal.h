@@ -133,6 +133,9 @@ hipError_t launch_load_state(const Dims &d, const double *const pos[3], const do
                              Cursor c, hipStream_t s);
 hipError_t launch_unload(const Dims &d, const double *ax, const double *ay, const double *az, const int32_t *orig,
                          double *const out[3], hipStream_t s);
+// launch_unload for positions, wrapped into [0, L) on the way.
+hipError_t launch_unload_pos(const Dims &d, const Buffers &b, const Pos &p, const int32_t *orig, double *const out[3],
+                             hipStream_t s);
 hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s);  // both halves flip
 hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s);
 // mode 0: F only (stored); 1: F + kick (stored, end of integrate);
@@ -159,6 +162,9 @@ hipError_t launch_hvp(const Dims &d, Buffers &b, const Pos &x, const Pos &w, con
 hipError_t launch_grad_reduce(const Dims &d, const Buffers &b, const double *partials, double mult, double *acc,
                               hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+// NaN sentinel atom (slot nt) in position buffers 1..count of a trajectory
+// store laid out as [count + 1][3][np].
+hipError_t launch_traj_sentinels(double *traj, int64_t np, int nt, int count, hipStream_t s);
 // a[i] = acc[2 i], b[i] = acc[2 i + 1] for i < n (either output nullable).
 hipError_t launch_split_pairs(const double *acc, int n, double *a, double *b, hipStream_t s);
 // Per-box deterministic sums of the block partials: rows of (U, W) when

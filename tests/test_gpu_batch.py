@@ -148,6 +148,32 @@ def test_schedule_does_not_change_trajectory(threads, lds, edge, parts, lpa, bth
     assert torch.equal(p0, p1) and torch.equal(v0, v1)
 
 
+@pytest.mark.parametrize("lpa,sched", [(1, dict(block_edge=2)), (1, dict(block_edge=3)), (1, dict(lds_atoms=64)),
+                                        (1, dict(block_edge=3, block_parts=2)), (2, dict(lds_atoms=64)),
+                                        (2, dict(block_edge=3, threads=512)), (4, dict(block_edge=2, lds_atoms=64))])
+def test_image_path_schedules_bitwise(lpa, sched):
+    """8 cells per axis (>= E + 4 for both block edges): blocks stage their
+    neighborhood moved to periodic images near the block and take plain
+    differences; a neighborhood too large for LDS (lds_atoms=64) takes the
+    partner's nearest image per pair from global memory instead.  Both give
+    the same trajectory bit for bit, at either block edge."""
+    s = md_system(14, seed=23)
+    ref = System(s.n, s.L)
+    assert ref.info()["cells_per_axis"] == 8
+    ref.set_schedule(lanes_per_atom=lpa)
+    ref.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
+    ref.integrate(30)
+    p0, v0, _ = ref.get_state()
+    g = System(s.n, s.L)
+    g.set_schedule(lanes_per_atom=lpa, **sched)
+    g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
+    g.integrate(30)
+    p1, v1, _ = g.get_state()
+    g.sync()
+    ref.sync()
+    assert torch.equal(p0, p1) and torch.equal(v0, v1)
+
+
 def test_autotune_keeps_state():
     s = md_system(10, seed=22)
     g = System(s.n, s.L)
