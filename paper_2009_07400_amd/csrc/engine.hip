@@ -253,8 +253,9 @@ struct GlobalPos {
     }
 };
 
-// Periodic images of a neighborhood copy.  With `on`, every staged position
-// is moved to its image nearest to the block's center (nearest_image()), so
+// Periodic images of a neighborhood copy (the role of the shifted ghost
+// copies of Sec. 4.3).  With `on`, every staged position is moved to its
+// image nearest to the block's center (nearest_image()), so
 // that for every atom of the block each list partner's copy is its image
 // nearest to that atom and the pair loops take plain differences (no
 // minimum-image test per pair).  `on` needs at least E + 4 cells per axis;
