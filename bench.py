@@ -64,7 +64,7 @@ def _traffic(workload: str):
 def _schedule(g) -> dict:
     info = g.info()
     return {k: info[k] for k in ("block_edge", "block_parts", "lanes_per_atom", "block_threads", "build_threads",
-                                 "lds_atoms")}
+                                 "build_lanes", "lds_atoms")}
 
 
 REBUILD_EVERY = 20  # list rebuild interval of every workload here
@@ -268,7 +268,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule for the primary workload: block edge, workgroups per block, lanes per "
-                         "atom, force threads[, build threads], e.g. 3,1,1,640 (default: autotune)")
+                         "atom, force threads[, build threads[, build lanes]], e.g. 3,1,1,640 (default: autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the run, copy a 1 GiB buffer 3 times with torch: a kernel of known traffic "
                          "(1 GiB read + 1 GiB written per launch) to calibrate FETCH_SIZE / WRITE_SIZE counters")
@@ -294,10 +294,10 @@ def main():
     sched = None
     if args.schedule:
         v_ = [int(v) for v in args.schedule.split(",")]
-        if len(v_) not in (4, 5):
-            ap.error("--schedule takes 4 or 5 comma-separated integers")
+        if len(v_) not in (4, 5, 6):
+            ap.error("--schedule takes 4 to 6 comma-separated integers")
         sched = dict(block_edge=v_[0], block_parts=v_[1], lanes_per_atom=v_[2], threads=v_[3],
-                     build_threads=v_[4] if len(v_) == 5 else 0)
+                     build_threads=v_[4] if len(v_) >= 5 else 0, build_lanes=v_[5] if len(v_) == 6 else 0)
     prim = run_gpu(args.workload, steps, args.warmup, sched)
     print(f"# primary {args.workload}: {prim['value']:.4g} atom-steps/s, {prim['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)

@@ -85,6 +85,8 @@ typedef struct {
     int32_t block_parts;     /* workgroups per block (1, 2 or 4) */
     int32_t lanes_per_atom;  /* lanes sharing one atom's force sum (1, 2 or 4) */
     int32_t build_threads;   /* threads per list-build (and adjoint) workgroup */
+    int32_t build_lanes;     /* lanes per atom in the list build (1 or 2) */
+    int32_t reserved_;
 } tmd_info;
 
 /* Kernel classes reported by tmd_get_timing(). */
@@ -209,8 +211,10 @@ tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
  * [64, 1024] (0 keeps the current value).  build_threads: threads per
  * workgroup of the kernels that take one lane per atom (the list build,
  * the adjoint's Hessian-vector product and tmd_get_neighbors), same range
- * (0 keeps the current value; a new edge or block_parts resets it to its
- * default).  lds_atoms: how many atoms of a block's neighborhood may be staged
+ * (0 keeps the current value; a new edge, block_parts or build_lanes
+ * resets it to its default).  build_lanes: 1 or 2 lanes per atom in the
+ * list build, the two lanes testing alternate candidates (0 keeps the
+ * current value); both write the same list.  lds_atoms: how many atoms of a block's neighborhood may be staged
  * in LDS, a multiple of 64 in [64, 4096] (0 keeps the current value; lowered
  * at the next state upload if the device's per-workgroup LDS cannot hold
  * twice that many 24-byte slots); blocks whose neighborhood holds more atoms
@@ -218,14 +222,16 @@ tmd_status tmd_get_info(const tmd_system *sys, tmd_info *info);
  * stale (the next integrate rebuilds it; compute_forces needs
  * tmd_build_neighbors first).  TMD_EINVAL for other values. */
 tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms, int32_t block_edge,
-                            int32_t block_parts, int32_t lanes_per_atom, int32_t build_threads);
+                            int32_t block_parts, int32_t lanes_per_atom, int32_t build_threads,
+                            int32_t build_lanes);
 
 /* Pick the schedule (block edge 2 or 3, workgroups per block 1, 2 or 4,
- * lanes per atom 1, 2 or 4, threads per force and per build workgroup)
+ * lanes per atom 1, 2 or 4, threads per force and per build workgroup,
+ * lanes per atom of the build 1 or 2)
  * with the shortest time per step for the current positions - one launch
  * of the step kernel (force sum, kicks and drift) plus 1/rebuild_every of a
  * list build: for each edge and workgroups per block, times `repeats`
- * builds per build thread count and `repeats` step-kernel launches per
+ * builds per (build lanes, build threads) and `repeats` step-kernel launches per
  * (lanes, threads) candidate on `stream` with HIP events
  * (synchronises; the launches work on spare copies of the state).  Tune
  * on a state like the one the run will see: every wavefront runs to the

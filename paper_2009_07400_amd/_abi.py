@@ -56,6 +56,8 @@ class TmdInfo(C.Structure):
         ("block_parts", C.c_int32),
         ("lanes_per_atom", C.c_int32),
         ("build_threads", C.c_int32),
+        ("build_lanes", C.c_int32),
+        ("reserved_", C.c_int32),
     ]
 
 
@@ -93,7 +95,7 @@ def load_library():
         "tmd_get_neighbors": (_S, [_P, _P, _P, C.c_int64, _P]),
         "tmd_sync": (_S, [_P, _P]),
         "tmd_get_info": (_S, [_P, C.POINTER(TmdInfo)]),
-        "tmd_set_schedule": (_S, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+        "tmd_set_schedule": (_S, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "tmd_set_lj_params": (_S, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]),
         "tmd_adjoint_workspace_size": (_S, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
         "tmd_adjoint_forward": (_S, [_P, C.c_int32, _P, C.c_size_t, _P]),
@@ -209,9 +211,9 @@ def tmd_get_info(handle) -> dict:
 
 
 def tmd_set_schedule(handle, threads: int, lds_atoms: int, block_edge: int = 0, block_parts: int = 0,
-                     lanes_per_atom: int = 0, build_threads: int = 0) -> None:
+                     lanes_per_atom: int = 0, build_threads: int = 0, build_lanes: int = 0) -> None:
     _check(load_library().tmd_set_schedule(handle, threads, lds_atoms, block_edge, block_parts, lanes_per_atom,
-                                           build_threads),
+                                           build_threads, build_lanes),
            handle)
 
 

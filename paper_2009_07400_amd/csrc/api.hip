@@ -292,7 +292,7 @@ bool layout_blocks(tmd_system *s, int E) {
     const int need = int(1.15 * worst) + 32;
     d.cap = std::min(kMaxCap, round_up(int(1.3 * worst) + 64, 64));
     for (int wg = 8; wg >= 1; --wg) {
-        const int c = ((kLdsPerCu / wg - kStaticLds) / 24 - 2) / 64 * 64;  // + sentinel and scratch slots
+        const int c = ((kLdsPerCu / wg - kStaticLds) / 24 - 2 - kHoodPad) / 64 * 64;  // + slots past the capacity
         if (c >= need) {
             d.cap = std::min(kMaxCap, c);
             break;
@@ -302,8 +302,10 @@ bool layout_blocks(tmd_system *s, int E) {
         d.parts = 1;
     if (d.lpa < 1)
         d.lpa = 1;
+    if (d.blanes < 1)
+        d.blanes = 1;
     d.threads = default_threads(d, d.lpa);
-    d.bthreads = default_threads(d, 1);
+    d.bthreads = default_threads(d, d.blanes);
     s->blk_box.assign(size_t(blocks), 0);
     for (int32_t k = 0; k < d.nbox; ++k) {
         const Box &B = s->boxes[size_t(k)];
@@ -745,12 +747,14 @@ tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
     info->block_parts = s->d.parts;
     info->lanes_per_atom = s->d.lpa;
     info->build_threads = s->d.bthreads;
+    info->build_lanes = s->d.blanes;
     return TMD_OK;
 }
 
 tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, int32_t block_edge,
-                            int32_t block_parts, int32_t lanes_per_atom, int32_t build_threads) {
+                            int32_t block_parts, int32_t lanes_per_atom, int32_t build_threads, int32_t build_lanes) {
     if (!s || threads < 0 || threads > kMaxThreads || threads % 64 != 0 || build_threads < 0 ||
+        (build_lanes != 0 && build_lanes != 1 && build_lanes != 2) ||
         build_threads > kMaxThreads || build_threads % 64 != 0 || lds_atoms < 0 || lds_atoms > kMaxCap ||
         lds_atoms % 64 != 0 || (block_edge != 0 && block_edge != 2 && block_edge != 3) ||
         (block_parts != 0 && block_parts != 1 && block_parts != 2 && block_parts != 4) ||
@@ -764,7 +768,11 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
     if (block_parts != 0 && block_parts != s->d.parts) {
         s->d.parts = block_parts;  // the list does not depend on it
         s->d.threads = default_threads(s->d, s->d.lpa);
-        s->d.bthreads = default_threads(s->d, 1);
+        s->d.bthreads = default_threads(s->d, s->d.blanes);
+    }
+    if (build_lanes != 0 && build_lanes != s->d.blanes) {
+        s->d.blanes = build_lanes;  // nor on this: both lane counts write the same list
+        s->d.bthreads = default_threads(s->d, s->d.blanes);
     }
     if (lanes_per_atom != 0 && lanes_per_atom != s->d.lpa) {
         s->d.lpa = lanes_per_atom;  // nor on this
@@ -845,7 +853,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
         return hip_fail(s, e, "autotune");
     float best = 1e30f;
     int32_t best_edge = s->d.edge, best_t = s->d.threads, best_p = s->d.parts, best_l = s->d.lpa,
-            best_bt = s->d.bthreads;
+            best_bt = s->d.bthreads, best_bl = s->d.blanes;
     for (int32_t E = 2; E <= kMaxEdge && e == hipSuccess; ++E) {
         layout_blocks(s, E);
         s->list_valid = s->force_valid = false;
@@ -853,22 +861,27 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
             break;
         for (int32_t P = 1; P <= kMaxParts && e == hipSuccess; P *= 2) {
             s->d.parts = P;
-            // the list build runs one lane per atom whatever the force
-            // kernel's lanes: its thread count is tuned on its own
+            // the list build's lanes per atom and threads are tuned on their
+            // own (the build and the force kernel share only the blocks)
             float mb = 1e30f;
-            int32_t bt_best = default_threads(s->d, 1);
-            const int32_t b0 = bt_best;
-            for (int32_t t = std::max(64, b0 - 128); t <= std::min(kMaxThreads, b0 + 128) && e == hipSuccess;
-                 t += 64) {
-                s->d.bthreads = t;
-                float m = 0.0f;
-                e = time_build(s, repeats, hs, a, b, m);
-                if (e == hipSuccess && m < mb) {
-                    mb = m;
-                    bt_best = t;
+            int32_t bt_best = s->d.bthreads, bl_best = s->d.blanes;
+            for (int32_t BL = 1; BL <= 2 && e == hipSuccess; ++BL) {
+                s->d.blanes = BL;
+                const int32_t b0 = default_threads(s->d, BL);
+                for (int32_t t = std::max(64, b0 - 128); t <= std::min(kMaxThreads, b0 + 128) && e == hipSuccess;
+                     t += 64) {
+                    s->d.bthreads = t;
+                    float m = 0.0f;
+                    e = time_build(s, repeats, hs, a, b, m);
+                    if (e == hipSuccess && m < mb) {
+                        mb = m;
+                        bt_best = t;
+                        bl_best = BL;
+                    }
                 }
             }
             s->d.bthreads = bt_best;
+            s->d.blanes = bl_best;
             for (int32_t Lp = 1; Lp <= 4 && e == hipSuccess; Lp *= 2) {
                 s->d.lpa = Lp;
                 const int32_t t0 = default_threads(s->d, Lp);
@@ -886,6 +899,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
                         best_p = P;
                         best_l = Lp;
                         best_bt = bt_best;
+                        best_bl = bl_best;
                     }
                 }
             }
@@ -902,6 +916,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     s->d.lpa = best_l;
     s->d.threads = best_t;
     s->d.bthreads = best_bt;
+    s->d.blanes = best_bl;
     s->list_valid = s->force_valid = false;
     return rebuild(s, hs);
 }

@@ -606,11 +606,14 @@ __device__ __forceinline__ Box block_box(const Dims &d, const Box *__restrict__ 
     return boxes[d.nbox == 1 ? 0 : blk_box[b]];
 }
 
-// One workgroup per block, one lane per atom: every j != i in the distinct
-// cells of i's 27-cell stencil with s < (cutoff + skin)^2 enters i's list.
-// Candidates come from the LDS copy of the neighborhood (lanes of one cell
-// read the same candidate, a broadcast); list entries are 16-bit LDS slots,
-// or 32-bit global indices when the neighborhood did not fit.
+// One workgroup per block, BL lanes per atom (1 or 2): every j != i in the
+// distinct cells of i's 27-cell stencil with s < (cutoff + skin)^2 enters
+// i's list.  Candidates come from the LDS copy of the neighborhood (lanes of
+// one cell read the same candidate, a broadcast); list entries are 16-bit
+// LDS slots, or 32-bit global indices when the neighborhood did not fit.
+// Both lane counts write the same list: entries in the order of the
+// stencil's runs and, within a run, of the LDS slots.
+template <int BL>
 __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__restrict__ boxes,
                                                        const int32_t *__restrict__ blk_box,
                                                        const double *__restrict__ x, const double *__restrict__ y,
@@ -640,7 +643,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     uint16_t *nbr16 = reinterpret_cast<uint16_t *>(nbr);
     int n[3], co[3][kAxis];
     hood_axes(B, lb, n, co);
-    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int p = threadIdx.x & (BL - 1);  // lane of the atom's pair (BL = 2)
+    for (int i = lo + threadIdx.x / BL; i < hi; i += blockDim.x / BL) {
         const double xi = x[i], yi = y[i], zi = z[i];
         const int cx = cell_coord(xi, B.side, B.nc), cy = cell_coord(yi, B.side, B.nc),
                   cz = cell_coord(zi, B.side, B.nc);
@@ -679,6 +683,46 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                     for (int q = 0; q < nrun; ++q) {
                         const int u0 = row + (run ? lo : st[0][q]), u1 = row + (run ? hi : st[0][q]);
                         const int beg = h.off[u0], end = h.off[u1 + 1];
+                        if (BL == 2) {
+                            // the atom's two lanes test alternate slots, four each
+                            // per round of eight (reads up to seven slots past the
+                            // run's end: other atoms, the sentinel or the pad slots
+                            // after it, all failing the slot test); the accepted
+                            // slots of both, exchanged as bit masks, take their
+                            // places in slot order
+                            for (int t0 = beg; t0 < end; t0 += 8) {
+                                const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t0 + p), 24u);
+                                double px[4], py[4], pz[4];
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    const lds_double *q = (const lds_double *)(pb + r * 48);
+                                    px[r] = q[0];
+                                    py[r] = q[1];
+                                    pz[r] = q[2];
+                                }
+                                unsigned mine = 0;  // bit 2r + p: slot t0 + 2r + p accepted
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    double dx, dy, dz;
+                                    const double s = pair_delta(xi, yi, zi, px[r], py[r], pz[r], B.L, B.halfL,
+                                                                B.halfL2, dx, dy, dz);
+                                    const int t = t0 + 2 * r + p;
+                                    mine |= (s < B.rl2 && t < end && t != self) ? (1u << (2 * r + p)) : 0u;
+                                }
+                                const unsigned m8 = mine | unsigned(__shfl_xor(int(mine), 1, 64));
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    const int j = 2 * r + p;
+                                    if (mine & (1u << j)) {
+                                        const int pos = c + __popc(m8 & ((1u << j) - 1u));
+                                        if (pos < d.maxnb)
+                                            nbr16[nbr_index16(i, pos, d.nchunk)] = uint16_t(t0 + j);
+                                    }
+                                }
+                                c += __popc(m8);
+                            }
+                            continue;
+                        }
                         // four candidates per round, their LDS reads issued together;
                         // past the end of the run a candidate is the NaN sentinel
                         for (int t0 = beg; t0 < end; t0 += 4) {
@@ -709,7 +753,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                         }
                     }
                 }
-        } else {
+        } else if (p == 0) {  // (global gathers: the atom's first lane alone)
             for (int kz = 0; kz < ns[2]; ++kz)
                 for (int ky = 0; ky < ns[1]; ++ky)
                     for (int kx = 0; kx < ns[0]; ++kx) {
@@ -729,6 +773,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                         }
                     }
         }
+        if (p != 0)
+            continue;  // the pair's first lane holds the same count and finishes the list
         const int stored = c < d.maxnb ? c : d.maxnb;
         cnt[i] = stored;
         // pad the last chunk and one whole chunk after it (every list has
@@ -1407,7 +1453,8 @@ __global__ void k_split_pairs(const double *__restrict__ acc, int n, double *a, 
 hipError_t prepare_kernels(const Dims &d) {
     const int bytes = int(hood_lds_bytes(d.cap));
     const void *fns[] = {
-        reinterpret_cast<const void *>(&k_build),
+        reinterpret_cast<const void *>(&k_build<1>),
+        reinterpret_cast<const void *>(&k_build<2>),
         reinterpret_cast<const void *>(&k_force<0, false, 1>),
         reinterpret_cast<const void *>(&k_force<0, true, 1>),
         reinterpret_cast<const void *>(&k_force<1, false, 1>),
@@ -1527,8 +1574,14 @@ hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
 }
 
 hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
-    k_build<<<block_grid(d.nblk * d.parts), d.bthreads, hood_lds_bytes(d.cap), s>>>(
-        d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.hood_tab, b.nbr_count, b.nbr, b.err);
+    if (d.blanes == 2)
+        k_build<2><<<block_grid(d.nblk * d.parts), d.bthreads, hood_lds_bytes(d.cap), s>>>(
+            d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.hood_tab, b.nbr_count, b.nbr,
+            b.err);
+    else
+        k_build<1><<<block_grid(d.nblk * d.parts), d.bthreads, hood_lds_bytes(d.cap), s>>>(
+            d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.hood_tab, b.nbr_count, b.nbr,
+            b.err);
     return hipGetLastError();
 }
 

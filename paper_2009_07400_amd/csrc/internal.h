@@ -65,6 +65,7 @@ struct Dims {
     int32_t nchunk;   // 4-entry list chunks per atom: ceil(maxnb / 4) + 1 (a spare chunk of padding)
     int32_t parts;    // workgroups per block (1, 2 or 4), each taking a share of the block's atoms
     int32_t lpa;      // lanes per atom in the force kernel (1, 2 or 4), each taking every lpa-th list chunk
+    int32_t blanes;   // lanes per atom in the list build (1 or 2)
 };
 
 // Neighbor list layout: neighbor-major within tiles of 64 atoms (one
@@ -124,7 +125,12 @@ inline int scan_blocks(int ncell) { return (ncell + kScanTile - 1) / kScanTile; 
 inline int block_grid(int nblk) { return round_up(nblk, kNumXcd); }
 // LDS bytes of a block workgroup staging `cap` atoms plus the NaN sentinel
 // and one scratch slot.
-inline size_t hood_lds_bytes(int cap) { return size_t(cap + 2) * 3 * sizeof(double); }
+// LDS slots past a neighborhood copy's capacity: the NaN sentinel (slot cap),
+// a scratch slot for the staging's unconditional writes (cap + 1), and
+// kHoodPad slots that the two-lane list build may read past a run's end
+// (unused values, masked out) so that its candidate reads need no clamping.
+constexpr int kHoodPad = 8;
+inline size_t hood_lds_bytes(int cap) { return size_t(cap + 2 + kHoodPad) * 3 * sizeof(double); }
 
 // Launchers (engine.hip).  All enqueue on `s` and return the launch status.
 hipError_t prepare_kernels(const Dims &d);

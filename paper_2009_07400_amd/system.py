@@ -148,21 +148,24 @@ class System:
         return abi.tmd_get_info(self._h)
 
     def set_schedule(self, threads: int = 0, lds_atoms: int = 0, block_edge: int = 0, block_parts: int = 0,
-                     lanes_per_atom: int = 0, build_threads: int = 0) -> None:
+                     lanes_per_atom: int = 0, build_threads: int = 0, build_lanes: int = 0) -> None:
         """Threads per force workgroup, LDS staging capacity, cells per block
-        edge, workgroups per block, lanes per atom and threads per list-build
-        workgroup (0 = keep)."""
-        abi.tmd_set_schedule(self._h, threads, lds_atoms, block_edge, block_parts, lanes_per_atom, build_threads)
+        edge, workgroups per block, lanes per atom, threads per list-build
+        workgroup and lanes per atom of the list build (0 = keep)."""
+        abi.tmd_set_schedule(self._h, threads, lds_atoms, block_edge, block_parts, lanes_per_atom, build_threads,
+                             build_lanes)
 
     def autotune(self, repeats: int = 5):
         """Times each schedule (block edge, workgroups per block, lanes per
         atom, force and build threads) by one force evaluation plus a list
         build's share per step and keeps the fastest; returns a dict of
         block_edge, block_parts, lanes_per_atom, block_threads and
-        build_threads.  Rebuilds the list at the current positions."""
+        build_threads and build_lanes.  Rebuilds the list at the current
+        positions."""
         abi.tmd_autotune(self._h, repeats, _stream())
         info = self.info()
-        return {k: info[k] for k in ("block_edge", "block_parts", "lanes_per_atom", "block_threads", "build_threads")}
+        return {k: info[k] for k in ("block_edge", "block_parts", "lanes_per_atom", "block_threads", "build_threads",
+                                     "build_lanes")}
 
     def set_lj_params(self, epsilon, sigma) -> None:
         """Per-box epsilon and sigma (sequences of n_boxes floats, or scalars)."""

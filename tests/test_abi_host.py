@@ -139,10 +139,16 @@ def test_batch_create_and_validation():
         assert info["lanes_per_atom"] == 2 and info["build_threads"] == b0 and info["block_threads"] >= t0
         abi.tmd_set_schedule(h, 0, 0, 0, 0, 0, 320)
         assert abi.tmd_get_info(h)["build_threads"] == 320
-        for bad in ((100, 0, 0, 0, 0, 0), (1088, 0, 0, 0, 0, 0), (0, 100, 0, 0, 0, 0), (0, 4160, 0, 0, 0, 0),
-                    (-64, 0, 0, 0, 0, 0), (0, 0, 4, 0, 0, 0), (0, 0, 1, 0, 0, 0), (0, 0, 0, 3, 0, 0),
-                    (0, 0, 0, 8, 0, 0), (0, 0, 0, -1, 0, 0), (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 8, 0),
-                    (0, 0, 0, 0, -1, 0), (0, 0, 0, 0, 0, 100), (0, 0, 0, 0, 0, 1088), (0, 0, 0, 0, 0, -64)):
+        assert abi.tmd_get_info(h)["build_lanes"] == 1
+        abi.tmd_set_schedule(h, 0, 0, 0, 0, 0, 0, 2)
+        info = abi.tmd_get_info(h)
+        # two lanes per atom in the build reset its threads to their (wider) default
+        assert info["build_lanes"] == 2 and info["build_threads"] >= b0
+        for bad in ((100, 0, 0, 0, 0, 0, 0), (1088, 0, 0, 0, 0, 0, 0), (0, 100, 0, 0, 0, 0, 0),
+                    (0, 4160, 0, 0, 0, 0, 0), (-64, 0, 0, 0, 0, 0, 0), (0, 0, 4, 0, 0, 0, 0), (0, 0, 1, 0, 0, 0, 0),
+                    (0, 0, 0, 3, 0, 0, 0), (0, 0, 0, 8, 0, 0, 0), (0, 0, 0, -1, 0, 0, 0), (0, 0, 0, 0, 3, 0, 0),
+                    (0, 0, 0, 0, 8, 0, 0), (0, 0, 0, 0, -1, 0, 0), (0, 0, 0, 0, 0, 100, 0), (0, 0, 0, 0, 0, 1088, 0),
+                    (0, 0, 0, 0, 0, -64, 0), (0, 0, 0, 0, 0, 0, 3), (0, 0, 0, 0, 0, 0, 4), (0, 0, 0, 0, 0, 0, -1)):
             with pytest.raises(abi.TmdError):
                 abi.tmd_set_schedule(h, *bad)
     finally:

@@ -126,7 +126,8 @@ def test_batch_equals_single_box_runs_bitwise():
     (64, 0, 2, 4, 1, 0), (0, 0, 3, 2, 1, 0), (128, 0, 3, 4, 1, 0), (0, 64, 3, 4, 1, 0), (0, 0, 2, 1, 2, 0),
     (128, 0, 2, 2, 2, 0), (0, 64, 2, 1, 2, 0), (0, 0, 3, 1, 2, 0), (256, 0, 3, 4, 2, 0), (0, 64, 3, 2, 2, 0),
     (0, 0, 2, 1, 4, 0), (0, 64, 2, 2, 4, 0), (512, 0, 3, 1, 4, 0), (0, 0, 2, 1, 1, 64), (0, 64, 3, 1, 2, 64),
-    (0, 0, 3, 2, 1, 1024), (0, 64, 2, 1, 4, 1024)])
+    (0, 0, 3, 2, 1, 1024), (0, 64, 2, 1, 4, 1024), (0, 0, 2, 1, 1, -2), (0, 0, 3, 2, 2, -2), (0, 64, 2, 1, 1, -2),
+    (64, 0, 3, 4, 1, -2)])
 def test_schedule_does_not_change_trajectory(threads, lds, edge, parts, lpa, bthreads):
     """Any schedule gives the trajectory of the default one bit for bit -
     against the default with the same lanes per atom (two lanes sum each
@@ -138,8 +139,9 @@ def test_schedule_does_not_change_trajectory(threads, lds, edge, parts, lpa, bth
     ref.integrate(30)
     p0, v0, _ = ref.get_state()
     g = System(s.n, s.L)
+    # bthreads -2: two lanes per atom in the list build, at its default threads
     g.set_schedule(threads=threads, lds_atoms=lds, block_edge=edge, block_parts=parts, lanes_per_atom=lpa,
-                   build_threads=bthreads)
+                   build_threads=max(bthreads, 0), build_lanes=2 if bthreads == -2 else 0)
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
     g.integrate(30)
     p1, v1, _ = g.get_state()
@@ -150,7 +152,8 @@ def test_schedule_does_not_change_trajectory(threads, lds, edge, parts, lpa, bth
 
 @pytest.mark.parametrize("lpa,sched", [(1, dict(block_edge=2)), (1, dict(block_edge=3)), (1, dict(lds_atoms=64)),
                                         (1, dict(block_edge=3, block_parts=2)), (2, dict(lds_atoms=64)),
-                                        (2, dict(block_edge=3, threads=512)), (4, dict(block_edge=2, lds_atoms=64))])
+                                        (2, dict(block_edge=3, threads=512)), (4, dict(block_edge=2, lds_atoms=64)),
+                                        (1, dict(build_lanes=2)), (2, dict(block_edge=3, build_lanes=2))])
 def test_image_path_schedules_bitwise(lpa, sched):
     """8 cells per axis (>= E + 4 for both block edges): blocks stage their
     neighborhood moved to periodic images near the block and take plain
@@ -185,7 +188,7 @@ def test_autotune_keeps_state():
     g.sync()
     assert sc["block_edge"] in (2, 3) and sc["block_parts"] in (1, 2, 4) and sc["lanes_per_atom"] in (1, 2, 4)
     assert sc["block_threads"] % 64 == 0 and 64 <= sc["block_threads"] <= 1024
-    assert sc["build_threads"] % 64 == 0 and 64 <= sc["build_threads"] <= 1024
+    assert sc["build_threads"] % 64 == 0 and 64 <= sc["build_threads"] <= 1024 and sc["build_lanes"] in (1, 2)
     assert torch.equal(p0, p1) and torch.equal(v0, v1)
 
 

@@ -84,22 +84,24 @@ CASES = {
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_neighbors_and_forces_match_oracle(case):
+@pytest.mark.parametrize("build_lanes", [1, 2])
+def test_neighbors_and_forces_match_oracle(case, build_lanes):
     pos, vel, L = CASES[case]()
     g = _gpu_system(pos, vel, L, max_neighbors=256)
+    g.set_schedule(build_lanes=build_lanes)
     g.build_neighbors()
     c_o, n_o = _check_lists(g, pos, L)
     _check_forces(g, pos, L, c_o, n_o)
 
 
-@pytest.mark.parametrize("lpa,lds", [(1, 0), (2, 0), (4, 0), (4, 64)])
-def test_short_list_capacity_and_lanes_per_atom(lpa, lds):
+@pytest.mark.parametrize("lpa,lds,bl", [(1, 0, 1), (2, 0, 1), (4, 0, 1), (4, 64, 1), (1, 0, 2), (2, 64, 2)])
+def test_short_list_capacity_and_lanes_per_atom(lpa, lds, bl):
     """A dilute gas with max_neighbors = 8 (a list area of three rows): the
     force kernel's row look-ahead and the build's padding stay inside each
-    atom's area for every lanes-per-atom setting."""
+    atom's area for every lanes-per-atom setting of either kernel."""
     pos = SplitMix64(11).next_double(3 * 300).reshape(300, 3) * 30.0
     g = _gpu_system(pos, np.zeros_like(pos), 30.0, max_neighbors=8)
-    g.set_schedule(lanes_per_atom=lpa, lds_atoms=lds)
+    g.set_schedule(lanes_per_atom=lpa, lds_atoms=lds, build_lanes=bl)
     g.build_neighbors()
     c_o, n_o = _check_lists(g, pos, 30.0)
     assert c_o.max() <= 8
@@ -202,9 +204,11 @@ def test_rebuild_schedule_and_small_box_trajectory():
     assert np.abs(v - r["v"]).max() < POS_TOL
 
 
-def test_error_overflow_is_deferred():
+@pytest.mark.parametrize("build_lanes", [1, 2])
+def test_error_overflow_is_deferred(build_lanes):
     s = md_system(5)
     g = _gpu_system(s.pos(), s.vel(), s.L, max_neighbors=8)
+    g.set_schedule(build_lanes=build_lanes)
     g.build_neighbors()
     with pytest.raises(TmdError) as e:
         g.sync()
