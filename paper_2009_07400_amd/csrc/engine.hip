@@ -43,8 +43,8 @@ __device__ __forceinline__ int xcd_remap() {
 // a contiguous share of its atoms (and staging the whole neighborhood).
 __device__ __forceinline__ bool block_part(const Dims &d, int &b, int &part) {
     const int wg = xcd_remap();
-    b = wg / d.parts;
-    part = wg - b * d.parts;
+    b = wg >> (d.parts >> 1);  // parts is 1, 2 or 4
+    part = wg & (d.parts - 1);
     return b < d.nblk;
 }
 
@@ -183,10 +183,33 @@ __device__ __forceinline__ void hood_store(const Hood &h, int b, int32_t *__rest
         tab[int64_t(b) * kHoodWords + t] = src[t];
 }
 
-__device__ __forceinline__ void hood_load(const int32_t *__restrict__ tab, int b, Hood &h) {
+// The stored table read in two halves: hood_fetch() issues the global loads
+// into registers (at least 64 threads, so four words each cover it), and
+// hood_commit() writes them to LDS and ends with a workgroup barrier.  Loads
+// issued in between (the box descriptor) share the table's round trip.
+struct HoodWords {
+    int v[kHoodWords / 64];
+};
+
+__device__ __forceinline__ void hood_fetch(const int32_t *__restrict__ tab, int b, HoodWords &w) {
+    constexpr int n = int(sizeof(Hood) / 4);
+    const int32_t *src = tab + int64_t(b) * kHoodWords;
+#pragma unroll
+    for (int k = 0; k < kHoodWords / 64; ++k) {
+        const int t = threadIdx.x + k * int(blockDim.x);
+        w.v[k] = t < n ? src[t] : 0;
+    }
+}
+
+__device__ __forceinline__ void hood_commit(const HoodWords &w, Hood &h) {
+    constexpr int n = int(sizeof(Hood) / 4);
     int *dst = reinterpret_cast<int *>(&h);
-    for (int t = threadIdx.x; t < int(sizeof(Hood) / 4); t += blockDim.x)
-        dst[t] = tab[int64_t(b) * kHoodWords + t];
+#pragma unroll
+    for (int k = 0; k < kHoodWords / 64; ++k) {
+        const int t = threadIdx.x + k * int(blockDim.x);
+        if (t < n)
+            dst[t] = w.v[k];
+    }
     __syncthreads();
 }
 
@@ -959,12 +982,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     int b, part;
     if (!block_part(d, b, part))
         return;
+    HoodWords hw;
+    hood_fetch(hood_tab, b, hw);
     const Box B = block_box(d, boxes, blk_box, b);
     // -f6 and -u6 live in vector registers: each fma of the pair loop that
     // uses them already reads one scalar operand
     double mf6 = -B.f6, mu6 = -B.u6;
     asm volatile("" : "+v"(mf6), "+v"(mu6));
-    hood_load(hood_tab, b, h);
+    hood_commit(hw, h);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     const LdsPos spos{(lds_double *)lds};
@@ -1346,10 +1371,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
     int b, part;
     if (!block_part(d, b, part))
         return;
+    HoodWords hw;
+    hood_fetch(hood_tab, b, hw);
     const Box B = block_box(d, boxes, blk_box, b);
     HvpConst k{-B.f6, -B.e6, -B.h6, B.g8};
     asm volatile("" : "+v"(k.mf6), "+v"(k.me6), "+v"(k.mh6), "+v"(k.g8));
-    hood_load(hood_tab, b, h);
+    hood_commit(hw, h);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     lds_double *S = (lds_double *)lds;
