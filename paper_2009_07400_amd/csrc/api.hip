@@ -23,6 +23,7 @@ struct tmd_system {
     Dims d{};
     Dims dmax{};               // sizes the workspace for either block edge
     bool tables_dirty = true;  // box / block tables changed since the last upload
+    bool counts_clear = false; // cell counts left at zero by the last binning
     int32_t rebuild_every = 20;
     size_t ws_need = 0;
     Buffers b{};
@@ -207,7 +208,8 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
     hipError_t e;
     {
         Timed t(s, TMD_T_BINNING, st);
-        e = launch_bin(s->d, s->b, s->cur, st);
+        e = launch_bin(s->d, s->b, s->cur, s->counts_clear, st);
+        s->counts_clear = e == hipSuccess && s->d.ncs <= kScanOne;
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "binning");
@@ -313,6 +315,7 @@ bool layout_blocks(tmd_system *s, int E) {
     }
     s->tables_dirty = true;
     s->prepared = false;
+    s->counts_clear = false;
     return true;
 }
 
@@ -532,6 +535,7 @@ tmd_status tmd_bind_workspace(tmd_system *s, void *dev, size_t bytes) {
     if (bytes < s->ws_need || (reinterpret_cast<uintptr_t>(dev) % kAlign) != 0)
         return fail(s, TMD_EWORKSPACE, "workspace must be 256-byte aligned and at least tmd_workspace_size bytes");
     carve(s->dmax, static_cast<char *>(dev), &s->b);
+    s->counts_clear = false;
     s->tables_dirty = true;
     s->bound = true;
     s->gen++;

@@ -575,6 +575,49 @@ __global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nt, int32
         out[n] = sh[1023];
 }
 
+// The whole scan in one workgroup, for up to kScanOne counts: each thread
+// loads a contiguous run of at most kScanOne / 1024 of them at once, the
+// workgroup scans the run totals, and each thread writes its run's offsets
+// to cell_start[0..n] and clears its counts for the next binning (so that
+// binning needs no separate fill).
+__global__ __launch_bounds__(1024) void k_scan_one(int32_t *counts, int32_t *out, int n) {
+    constexpr int M = kScanOne / 1024;
+    __shared__ int32_t sh[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;  // <= M
+    const int b0 = t * per;
+    int v[M], tot = 0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        v[q] = (q < per && b0 + q < n) ? counts[b0 + q] : 0;
+        tot += v[q];
+    }
+    // run totals scanned within each wavefront, then across the 16 of them
+    const int lane = t & 63, wv = t >> 6;
+    const int incl = wave_prefix_incl(tot);
+    if (lane == 63)
+        sh[wv] = incl;
+    __syncthreads();
+    if (wv == 0) {
+        const int w = lane < 16 ? sh[lane] : 0;
+        const int wi = wave_prefix_incl(w);
+        if (lane < 16)
+            sh[16 + lane] = wi - w;
+    }
+    __syncthreads();
+    int run = sh[16 + wv] + incl - tot;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        if (q < per && b0 + q < n) {
+            out[b0 + q] = run;
+            counts[b0 + q] = 0;
+        }
+        run += v[q];
+    }
+    if (t == 1023)
+        out[n] = run;
+}
+
 __global__ __launch_bounds__(256) void k_scan_add(int32_t *out, const int32_t *__restrict__ sums, int n) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n)
@@ -591,32 +634,41 @@ __global__ __launch_bounds__(kAtomThreads) void k_scatter(int n, const int32_t *
 
 // Atomic arrival order inside a cell is not reproducible: each atom's final
 // place is its cell start plus the number of cell members with a smaller
-// original id.  Then positions, velocities and ids move to that place.
+// original id.  Then positions, velocities and ids move to that place.  The
+// ids of the workgroup's own arrival slots are staged in LDS first, so only
+// cells that straddle a workgroup boundary read members from global memory.
 __global__ __launch_bounds__(kAtomThreads) void k_rank_permute(
-    int n, const Box *__restrict__ boxes, const int32_t *__restrict__ atom_box, const int32_t *__restrict__ tmp_idx,
+    int n, int nbox, const Box *__restrict__ boxes, const int32_t *__restrict__ atom_box, const int32_t *__restrict__ tmp_idx,
     const int32_t *__restrict__ cell_of,
     const int32_t *__restrict__ cell_start, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
     const double *__restrict__ vz, const int32_t *__restrict__ orig, double *x2, double *y2, double *z2,
     double *vx2, double *vy2, double *vz2, int32_t *orig2) {
-    const int q = blockIdx.x * kAtomThreads + threadIdx.x;
+    __shared__ int32_t keys[kAtomThreads];
+    const int q0 = blockIdx.x * kAtomThreads, q = q0 + threadIdx.x;
+    const int p = q < n ? tmp_idx[q] : 0;
+    const int key = q < n ? orig[p] : 0;
+    keys[threadIdx.x] = key;
+    __syncthreads();
     if (q >= n)
         return;
-    const int p = tmp_idx[q];
-    const int key = orig[p];
+    // everything that depends only on the source slot is requested at once
     const int c = cell_of[p];
+    const double L = boxes[nbox == 1 ? 0 : atom_box[p]].L;  // a box keeps its slot range
+    const double px = x[p], py = y[p], pz = z[p], pvx = vx[p], pvy = vy[p], pvz = vz[p];
     const int b = cell_start[c], e = cell_start[c + 1];
     int rank = 0;
-    for (int r = b; r < e; ++r)
-        rank += int(orig[tmp_idx[r]] < key);
+    for (int r = b; r < e; ++r) {
+        const int kr = (r >= q0 && r < q0 + kAtomThreads) ? keys[r - q0] : orig[tmp_idx[r]];
+        rank += int(kr < key);
+    }
     const int dst = b + rank;
-    const double L = boxes[atom_box[dst]].L;  // source and destination slots lie in one box
-    x2[dst] = wrap(x[p], L);
-    y2[dst] = wrap(y[p], L);
-    z2[dst] = wrap(z[p], L);
-    vx2[dst] = vx[p];
-    vy2[dst] = vy[p];
-    vz2[dst] = vz[p];
+    x2[dst] = wrap(px, L);
+    y2[dst] = wrap(py, L);
+    z2[dst] = wrap(pz, L);
+    vx2[dst] = pvx;
+    vy2[dst] = pvy;
+    vz2[dst] = pvz;
     orig2[dst] = key;
 }
 
@@ -1580,19 +1632,25 @@ hipError_t launch_unload_pos(const Dims &d, const Buffers &b, const Pos &p, cons
     return hipGetLastError();
 }
 
-hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
+hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, bool counts_clear, hipStream_t s) {
     const int xc = c.x, xn = 1 - c.x, o = c.o, on = 1 - c.o;
-    hipError_t e = launch_fill_i32(b.cell_count, 0, d.ncs, s);
-    if (e != hipSuccess)
-        return e;
+    if (!counts_clear) {
+        const hipError_t e = launch_fill_i32(b.cell_count, 0, d.ncs, s);
+        if (e != hipSuccess)
+            return e;
+    }
     k_bin_count<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, b.x[xc], b.y[xc], b.z[xc],
                                                             b.cell_of, b.slot, b.cell_count, b.err);
-    const int nt = scan_blocks(d.ncs);
-    k_scan_tiles<<<nt, 256, 0, s>>>(b.cell_count, b.cell_start, b.scan_sums, d.ncs);
-    k_scan_sums<<<1, 1024, 0, s>>>(b.scan_sums, nt, b.cell_start, d.ncs);
-    k_scan_add<<<(d.ncs + 255) / 256, 256, 0, s>>>(b.cell_start, b.scan_sums, d.ncs);
+    if (d.ncs <= kScanOne) {
+        k_scan_one<<<1, 1024, 0, s>>>(b.cell_count, b.cell_start, d.ncs);
+    } else {
+        const int nt = scan_blocks(d.ncs);
+        k_scan_tiles<<<nt, 256, 0, s>>>(b.cell_count, b.cell_start, b.scan_sums, d.ncs);
+        k_scan_sums<<<1, 1024, 0, s>>>(b.scan_sums, nt, b.cell_start, d.ncs);
+        k_scan_add<<<(d.ncs + 255) / 256, 256, 0, s>>>(b.cell_start, b.scan_sums, d.ncs);
+    }
     k_scatter<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.cell_of, b.slot, b.cell_start, b.tmp_idx);
-    k_rank_permute<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.boxes, b.atom_box, b.tmp_idx, b.cell_of,
+    k_rank_permute<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, d.nbox, b.boxes, b.atom_box, b.tmp_idx, b.cell_of,
                                                                b.cell_start, b.x[xc],
                                                                b.y[xc], b.z[xc], b.vx[o], b.vy[o], b.vz[o],
                                                                b.orig[o], b.x[xn], b.y[xn], b.z[xn], b.vx[on],

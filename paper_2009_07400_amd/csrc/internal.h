@@ -8,6 +8,7 @@
 namespace tmd {
 
 constexpr int kScanTile = 1024;    // elements per workgroup in the cell-count scan
+constexpr int kScanOne = 32768;    // cell slots up to which one workgroup scans (and clears) the counts
 constexpr int kPartialStride = 4;  // doubles per block partial: U, W, KE, pad
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kMaxEdge = 3;        // cells per block edge: 2 or 3
@@ -142,7 +143,10 @@ hipError_t launch_unload(const Dims &d, const double *ax, const double *ay, cons
 // launch_unload for positions, wrapped into [0, L) on the way.
 hipError_t launch_unload_pos(const Dims &d, const Buffers &b, const Pos &p, const int32_t *orig, double *const out[3],
                              hipStream_t s);
-hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, hipStream_t s);  // both halves flip
+// Binning (both halves flip).  counts_clear: the cell counts are known to be
+// zero (left so by the previous binning's one-workgroup scan), which skips
+// clearing them first.
+hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, bool counts_clear, hipStream_t s);
 hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s);
 // mode 0: F only (stored); 1: F + kick (stored, end of integrate);
 // 2: F + kick + kick + drift into positions 1 - c.x
