@@ -274,7 +274,7 @@ def main():
                          "(1 GiB read + 1 GiB written per launch) to calibrate FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
