@@ -982,7 +982,8 @@ __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i
     };
     Duo P, Q;
     fetch2w(pos, i0[0], P);
-    for (int k = 0;; k += 2) {
+    int k = 0;
+    for (;; k += 2) {
         fetch2w(pos, i0[1], Q);
         eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2w(pos, i0[2], P);
@@ -1001,8 +1002,20 @@ __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i
         fetch2w(pos, i0[0], P);
         i1 = ld(k + 3);
         eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        if (!__any(p + L * (k + 2) < nch))
+        if (!__any(p + L * (k + 3) < nch))
             break;
+    }
+    // fewer than two of the lane's chunks remain: the first of them (in i0,
+    // its first two positions in P) runs here if any lane still has it, so
+    // an odd chunk count does not cost a chunk of sentinels
+    if (__any(p + L * (k + 2) < nch)) {
+        fetch2w(pos, i0[1], Q);
+        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2w(pos, i0[2], P);
+        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetch2w(pos, i0[3], Q);
+        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
     }
     __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) expcnt(7) lgkmcnt(0)
 }
@@ -1378,7 +1391,8 @@ __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0
     };
     Duo6 P, Q;
     fetch2w6(S, i0[0], P);
-    for (int kk = 0;; kk += 2) {
+    int kk = 0;
+    for (;; kk += 2) {
         fetch2w6(S, i0[1], Q);
         ev(P);
         fetch2w6(S, i0[2], P);
@@ -1397,8 +1411,17 @@ __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0
         fetch2w6(S, i0[0], P);
         i1 = ld(kk + 3);
         ev(Q);
-        if (!__any(kk + 2 < nch))
+        if (!__any(kk + 3 < nch))
             break;
+    }
+    if (__any(kk + 2 < nch)) {  // an odd last chunk, as in pair_sum16
+        fetch2w6(S, i0[1], Q);
+        ev(P);
+        fetch2w6(S, i0[2], P);
+        ev(Q);
+        fetch2w6(S, i0[3], Q);
+        ev(P);
+        ev(Q);
     }
     __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) expcnt(7) lgkmcnt(0)
 }
