@@ -227,12 +227,14 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
     return TMD_OK;
 }
 
-// Threads per block workgroup: ~15% above the mean number of atoms one
-// workgroup takes (a block's atoms split over d.parts workgroups) times the
-// lanes each atom gets.
+// Threads per block workgroup: the mean number of atoms one workgroup takes
+// (a block's atoms split over d.parts workgroups) times the lanes each atom
+// gets, rounded up to whole wavefronts.  (More threads than that leave waves
+// idle in most blocks and, at two workgroups per CU, unevenly spread over
+// the SIMDs; the few fuller blocks take a second pass.)
 int default_threads(const Dims &d, int lanes) {
     const double per_wg = double(d.nt) / (double(d.nblk) * d.parts) * lanes;
-    return std::min(kMaxThreads, std::max(64, round_up(int(per_wg * 1.15), 64)));
+    return std::min(kMaxThreads, std::max(64, round_up(int(per_wg + 0.5), 64)));
 }
 
 // LJ 12-6 constants of one box (Sec. 3.2, Eq. 2) in the forms the kernels use.
@@ -267,8 +269,8 @@ double expected_hood_atoms(const Box &B, int E) {
 // it: the LDS capacity is the largest per-workgroup share of a CU's LDS that
 // still holds at least 15% more atoms than the largest mean neighborhood
 // population (liquid density fluctuations over ~1000 atoms are a few
-// percent; rarer blocks fall back to global gathers), threads ~15% above the
-// mean block population.  Returns false when the cell slots overflow int32.
+// percent; rarer blocks fall back to global gathers), threads the mean block
+// population rounded up to whole wavefronts.  Returns false when the cell slots overflow int32.
 bool layout_blocks(tmd_system *s, int E) {
     int64_t blocks = 0;
     double worst = 0.0;
