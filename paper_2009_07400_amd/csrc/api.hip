@@ -60,6 +60,7 @@ constexpr size_t kAlign = 256;
 constexpr int kMaxCap = 4096;       // atoms staged per block neighborhood (96 KB of LDS at most)
 constexpr int kLdsPerCu = 163840;   // gfx950: 160 KB of LDS per compute unit
 constexpr int kStaticLds = 1536;    // static LDS of a block kernel (neighborhood tables, reductions), rounded up
+static_assert(kForceLdsTail <= kStaticLds, "the force kernel's table and scratch fit the static LDS allowance");
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -729,6 +730,8 @@ tmd_status tmd_sync(tmd_system *s, tmd_stream stream) {
                                               std::to_string(s->d.maxnb));
     if (w[0] & kErrOutOfBox)
         return fail(s, TMD_EINVAL, "set_state: a coordinate lies outside [-L, 2L)");
+    if (w[0] & kErrLdsLayout)
+        return fail(s, TMD_EHIP, "internal: the force kernel's dynamic LDS does not start at address 0");
     return TMD_OK;
 }
 

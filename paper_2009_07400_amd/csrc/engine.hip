@@ -174,6 +174,11 @@ __device__ __forceinline__ void hood_setup(const Box &B, int lb, const int32_t *
 
 static_assert(sizeof(Hood) <= kHoodWords * 4, "neighborhood table");
 
+// The force kernel's dynamic LDS after the neighborhood copy: the table
+// (rounded up to whole doubles), then block_sum3's scratch.
+constexpr int kHoodBytes8 = int((sizeof(Hood) + 7) / 8 * 8);
+static_assert(kHoodBytes8 + 3 * (kMaxThreads / 64) * 8 <= kForceLdsTail, "force kernel LDS tail");
+
 // The list build stores each block's table (hood_setup's result) in HBM; the
 // kernels that run on that list read it back in one coalesced round trip
 // instead of recomputing it from cell_start.  Ends with a workgroup barrier.
@@ -365,9 +370,9 @@ __device__ __forceinline__ void hood_stage(const Hood &h, int total, int sent, c
     __syncthreads();
 }
 
-// Deterministic workgroup sum of three values; valid in thread 0.
-__device__ __forceinline__ void block_sum3(double &a, double &b, double &c) {
-    __shared__ double red[3][kMaxThreads / 64];
+// Deterministic workgroup sum of three values; valid in thread 0.  red is
+// LDS scratch of 3 * kMaxThreads / 64 doubles.
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double (*red)[kMaxThreads / 64]) {
     a = wave_sum(a);
     b = wave_sum(b);
     c = wave_sum(c);
@@ -386,6 +391,11 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c) {
             c += red[2][w];
         }
     }
+}
+
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c) {
+    __shared__ double red[3][kMaxThreads / 64];
+    block_sum3(a, b, c, red);
 }
 
 // ------------------------------------------------------------------ utility
@@ -951,14 +961,35 @@ __device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int p, 
     }
 }
 
-// Two LDS-slot entries packed in one 32-bit word of a 16-bit list.
-__device__ __forceinline__ void fetch2w(const LdsPos &pos, int word, Duo &q) {
-    const unsigned w = unsigned(word);
-    pos.get(int(w & 0xffffu), q.x[0], q.y[0], q.z[0]);
-    pos.get(int(w >> 16), q.x[1], q.y[1], q.z[1]);
+// Two LDS-slot entries packed in one 32-bit word of a 16-bit list, read
+// from a neighborhood copy at LDS address 0 (the force kernel's layout):
+// each slot's address, slot * 24, is one SDWA multiply that selects its half
+// of the word, so a pair costs one address instruction (an added base would
+// cost a second: the compiler does not fold the copy's base address into
+// the reads' offset fields).  The three coordinates are three 8-byte reads:
+// merged into a 16-byte read (x, y) plus z, two lanes whose slots differ by
+// 11 or 21 modulo 32 collide in the LDS banks, and neighbors of adjacent
+// atoms often sit that close; volatile keeps the compiler from merging them.
+__device__ __forceinline__ void fetch2w(int word, Duo &q) {
+    unsigned o0, o1;
+    asm("v_mul_u32_u24_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:DWORD"
+        : "=v"(o0)
+        : "v"(word), "v"(24));
+    asm("v_mul_u32_u24_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:DWORD"
+        : "=v"(o1)
+        : "v"(word), "v"(24));
+    const volatile lds_double *a = reinterpret_cast<const volatile lds_double *>(uintptr_t(o0));
+    const volatile lds_double *b = reinterpret_cast<const volatile lds_double *>(uintptr_t(o1));
+    q.x[0] = a[0];
+    q.y[0] = a[1];
+    q.z[0] = a[2];
+    q.x[1] = b[0];
+    q.y[1] = b[1];
+    q.z[1] = b[2];
 }
 
-// pair_sum over a list of 16-bit LDS slots (eight entries per chunk): half
+// pair_sum over a list of 16-bit LDS slots (eight entries per chunk) of a
+// neighborhood copy at LDS address 0: half
 // the bytes of the 32-bit list per entry.  The body covers two chunks, with
 // the same look-ahead discipline (index chunks one to two chunks ahead,
 // positions two entries ahead, unconditional memory operations, the chunk
@@ -971,9 +1002,8 @@ __device__ __forceinline__ void fetch2w(const LdsPos &pos, int word, Duo &q) {
 // counts at its head.
 template <bool THERMO, bool IMG>
 __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int p, int L, int c,
-                                           const LdsPos &pos, double xi, double yi, double zi, const Box &B,
-                                           double mf6, double mu6, double &ax, double &ay, double &az, double &u,
-                                           double &w) {
+                                           double xi, double yi, double zi, const Box &B, double mf6, double mu6,
+                                           double &ax, double &ay, double &az, double &u, double &w) {
     const int nch = (c + 7) >> 3;
     // this lane's k-th chunk is chunk p + L k of the atom's list
     auto ld = [&](int k) {
@@ -981,25 +1011,25 @@ __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i
         return __builtin_nontemporal_load(chunks + (q < nch ? q : nch) * 64);
     };
     Duo P, Q;
-    fetch2w(pos, i0[0], P);
+    fetch2w(i0[0], P);
     int k = 0;
     for (;; k += 2) {
-        fetch2w(pos, i0[1], Q);
+        fetch2w(i0[1], Q);
         eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(pos, i0[2], P);
+        fetch2w(i0[2], P);
         eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(pos, i0[3], Q);
+        fetch2w(i0[3], Q);
         eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(pos, i1[0], P);
+        fetch2w(i1[0], P);
         i0 = ld(k + 2);
         eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(pos, i1[1], Q);
+        fetch2w(i1[1], Q);
         eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(pos, i1[2], P);
+        fetch2w(i1[2], P);
         eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(pos, i1[3], Q);
+        fetch2w(i1[3], Q);
         eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(pos, i0[0], P);
+        fetch2w(i0[0], P);
         i1 = ld(k + 3);
         eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         if (!__any(p + L * (k + 3) < nch))
@@ -1009,11 +1039,11 @@ __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i
     // its first two positions in P) runs here if any lane still has it, so
     // an odd chunk count does not cost a chunk of sentinels
     if (__any(p + L * (k + 2) < nch)) {
-        fetch2w(pos, i0[1], Q);
+        fetch2w(i0[1], Q);
         eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(pos, i0[2], P);
+        fetch2w(i0[2], P);
         eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(pos, i0[3], Q);
+        fetch2w(i0[3], Q);
         eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
     }
@@ -1042,11 +1072,19 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
                                                        double *__restrict__ fz, double *__restrict__ xo,
                                                        double *__restrict__ yo, double *__restrict__ zo,
                                                        double *__restrict__ partials, int32_t *err) {
-    __shared__ Hood h;
+    // no static LDS: the neighborhood copy starts at LDS address 0, where
+    // the pair loop's slot addresses point, and the table and reduction
+    // scratch follow it
     extern __shared__ double lds[];
+    const int tail = (d.cap + 2 + kHoodPad) * 24;
+    Hood &h = *reinterpret_cast<Hood *>(reinterpret_cast<char *>(lds) + tail);
+    double(*red)[kMaxThreads / 64] =
+        reinterpret_cast<double(*)[kMaxThreads / 64]>(reinterpret_cast<char *>(lds) + tail + kHoodBytes8);
     int b, part;
     if (!block_part(d, b, part))
         return;
+    if (threadIdx.x == 0 && unsigned(uintptr_t((lds_char *)lds)) != 0u)
+        atomicOr(err, kErrLdsLayout);
     HoodWords hw;
     hood_fetch(hood_tab, b, hw);
     const Box B = block_box(d, boxes, blk_box, b);
@@ -1105,9 +1143,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
         double ax = 0.0, ay = 0.0, az = 0.0;
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
         if (im.on)
-            pair_sum16<THERMO, true>(chunks, r0, r1, p, L, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+            pair_sum16<THERMO, true>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         else if (fits)
-            pair_sum16<THERMO, false>(chunks, r0, r1, p, L, ci, spos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+            pair_sum16<THERMO, false>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         else
             pair_sum<THERMO>(chunks, p, L, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         // combine the L partial sums of the group (a butterfly: addition
@@ -1150,7 +1188,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
         load_atom(i + T);
     }
     if (THERMO) {
-        block_sum3(u, w, ke);
+        block_sum3(u, w, ke, red);
         if (threadIdx.x == 0) {
             const int q = b * d.parts + part;
             partials[q * kPartialStride + 0] = u;
@@ -1577,7 +1615,11 @@ hipError_t prepare_kernels(const Dims &d) {
         reinterpret_cast<const void *>(&k_force<2, true, 4>),
     };
     for (const void *f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        // the force kernels add their table and scratch to the dynamic LDS
+        const bool build = f == reinterpret_cast<const void *>(&k_build<1>) ||
+                           f == reinterpret_cast<const void *>(&k_build<2>);
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           build ? bytes : int(force_lds_bytes(d.cap)));
         if (e != hipSuccess)
             return e;
     }
@@ -1695,7 +1737,7 @@ hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
 
 template <int MODE, bool THERMO, int L>
 static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
-    k_force<MODE, THERMO, L><<<block_grid(d.nblk * d.parts), d.threads, hood_lds_bytes(d.cap), s>>>(
+    k_force<MODE, THERMO, L><<<block_grid(d.nblk * d.parts), d.threads, force_lds_bytes(d.cap), s>>>(
         d, b.boxes, b.blk_box, in.x, in.y, in.z, b.hood_tab, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
         b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
 }

@@ -22,6 +22,7 @@ constexpr int kHoodWords = 256;    // int32 words of one block's stored neighbor
 constexpr int kErrOverflow = 1;
 constexpr int kErrNonFinite = 2;
 constexpr int kErrOutOfBox = 4;  // set_state got a coordinate outside [-L, 2L)
+constexpr int kErrLdsLayout = 8; // the force kernel's dynamic LDS does not start at address 0
 
 // One periodic cubic box.  Cells are numbered block-major: a block is E x E x
 // E cells (E = 2 or 3; thinner at the high faces when E does not divide the
@@ -132,6 +133,12 @@ inline int block_grid(int nblk) { return round_up(nblk, kNumXcd); }
 // (unused values, masked out) so that its candidate reads need no clamping.
 constexpr int kHoodPad = 8;
 inline size_t hood_lds_bytes(int cap) { return size_t(cap + 2 + kHoodPad) * 3 * sizeof(double); }
+
+// The force kernel keeps no static LDS: its dynamic LDS holds the
+// neighborhood copy from address 0, then its neighborhood table and
+// reduction scratch in kForceLdsTail bytes.
+constexpr int kForceLdsTail = 1536;
+inline size_t force_lds_bytes(int cap) { return hood_lds_bytes(cap) + kForceLdsTail; }
 
 // Launchers (engine.hip).  All enqueue on `s` and return the launch status.
 hipError_t prepare_kernels(const Dims &d);
