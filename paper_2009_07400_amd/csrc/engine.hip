@@ -251,8 +251,8 @@ __device__ __forceinline__ void hood_find_n(const Hood &h, const int (&t)[R], in
 }
 
 // LDS copy of a neighborhood: packed (x, y, z) triples, 24 bytes per slot,
-// addressed with 32-bit LDS pointers (one 24-bit multiply-add per atom, then
-// ds_read2_b64 + ds_read_b64 with immediate offsets).
+// addressed with 32-bit LDS pointers (one 24-bit multiply or multiply-add
+// per atom, then reads with immediate offsets).
 typedef __attribute__((address_space(3))) double lds_double;
 typedef __attribute__((address_space(3))) char lds_char;
 
