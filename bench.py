@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, AMD published
 METRIC = "atom-steps/s (FP64 LJ) at 131k & 3.5M atoms; batched, adjoint vs plain"
 KERNEL_SRC = os.path.join(ROOT, "paper_2009_07400_amd", "csrc", "engine.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
@@ -90,6 +91,37 @@ def _warm_and_tune(g, warmup: int, schedule=None):
         g.integrate(warmup - k)
 
 
+def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int) -> dict:
+    """Roofline figures of the binning and list-build kernels, per call (one
+    call = one rebuild: the binning bucket sums its four to eight launches).
+
+    Binning moves 132 algorithmic bytes per atom (read x and the atom id,
+    28; the permutation reads x, v and id and writes them, 52 + 52).  The
+    list build reads x (24) and writes the count (4) and the list (4 bytes
+    per entry at the method's index width) and tests 27 cells' worth of
+    candidates per atom, 8 FP64 operations each (3 differences, 3 squares,
+    2 sums): it is bound by FP64 issue, so its fraction is taken against the
+    FP64 vector peak, with the HBM fraction beside it."""
+    out = {}
+    if tm.get("binning", (0, 0))[1]:
+        ms, calls = tm["binning"]
+        t = ms / calls * 1e-3
+        b = 132.0 * n
+        out["binning"] = {"bound": "hbm", "achieved": b / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": b / t / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_call": b, "avg_call_us": t * 1e6}
+    if tm.get("neighbor", (0, 0))[1]:
+        ms, calls = tm["neighbor"]
+        t = ms / calls * 1e-3
+        b = (28.0 + 4.0 * mean_list) * n
+        cand = 27.0 * n / n_cells
+        fl = 8.0 * cand * n
+        out["neighbor"] = {"bound": "alu", "achieved": fl / t / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": fl / t / 1e12 / FP64_PEAK_TFLOPS, "candidates_per_atom": cand,
+                           "hbm_achieved_gbs": b / t / 1e9, "hbm_frac": b / t / 1e9 / HBM_PEAK_GBS,
+                           "alg_bytes_per_call": b, "avg_call_us": t * 1e6}
+    return out
+
+
 def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     import torch
 
@@ -118,6 +150,7 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     tm = g.get_timing()
     g.set_timing(False)
     mean_list = float(g.neighbor_counts().double().mean().item())
+    n_cells = int(g.info()["n_cells"])
     g.sync()
     ms, launches = tm["force"]
     avg_s = ms / max(launches, 1) * 1e-3
@@ -148,6 +181,7 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": avg_s * 1e6,
         },
+        "build_rooflines": _build_rooflines(tm, s.n, mean_list, n_cells),
     }
     g.close()
     return res
@@ -318,6 +352,7 @@ def main():
                    "neighbor_list": "full", "max_neighbors": 128},
         "roofline": prim["roofline"],
         "kernel_avg_ms": prim["kernel_ms"],
+        "build_rooflines": prim["build_rooflines"],
         "mean_list_length": prim["mean_list_length"],
         "schedule": prim["schedule"],
     }
@@ -327,6 +362,7 @@ def main():
         out["secondary"] = {"c2": {"workload": WORKLOADS["c2"]["name"], "value": sec["value"],
                                    "ms_per_step": sec["ms_per_step"], "steps": sec["steps"],
                                    "roofline": sec["roofline"], "kernel_avg_ms": sec["kernel_ms"],
+                                   "build_rooflines": sec["build_rooflines"],
                                    "mean_list_length": sec["mean_list_length"], "schedule": sec["schedule"]}}
         bat = run_batched()
         print(f"# secondary batched: {bat['value']:.4g} atom-steps/s, {bat['speedup_vs_sequential']:.1f}x "

@@ -1,0 +1,51 @@
+"""Host-side logic of bench.py: the roofline arithmetic of the binning and
+list-build kernels, and the one-GPU contract.  No GPU is used."""
+
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_build_rooflines_arithmetic():
+    b = _bench()
+    n, n_cells, mean_list = 1000, 40, 75.0
+    # 25 rebuilds: binning 2 ms in all (80 us each), list build 50 ms (2 ms each)
+    tm = {"force": (10.0, 100), "binning": (2.0, 25), "neighbor": (50.0, 25)}
+    r = b._build_rooflines(tm, n, mean_list, n_cells)
+    assert r["binning"]["avg_call_us"] == pytest.approx(80.0)
+    assert r["binning"]["alg_bytes_per_call"] == pytest.approx(132.0 * n)
+    assert r["binning"]["achieved"] == pytest.approx(132.0 * n / 80e-6 / 1e9)
+    assert r["binning"]["frac"] == pytest.approx(r["binning"]["achieved"] / 8000.0)
+    nb = r["neighbor"]
+    assert nb["bound"] == "alu" and nb["unit"] == "TFLOP/s"
+    assert nb["candidates_per_atom"] == pytest.approx(27.0 * n / n_cells)
+    assert nb["achieved"] == pytest.approx(8.0 * 27.0 * n / n_cells * n / 2e-3 / 1e12)
+    assert nb["frac"] == pytest.approx(nb["achieved"] / 78.6)
+    assert nb["alg_bytes_per_call"] == pytest.approx((28.0 + 4.0 * mean_list) * n)
+    assert nb["hbm_frac"] == pytest.approx(nb["hbm_achieved_gbs"] / 8000.0)
+
+
+def test_build_rooflines_skip_kernels_not_run():
+    b = _bench()
+    assert b._build_rooflines({"force": (1.0, 10), "neighbor": (0.0, 0)}, 10, 1.0, 1) == {}
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert p.returncode == 2
+    out = json.loads(p.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
