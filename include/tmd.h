@@ -86,7 +86,8 @@ typedef struct {
     int32_t lanes_per_atom;  /* lanes sharing one atom's force sum (1, 2 or 4) */
     int32_t build_threads;   /* threads per list-build (and adjoint) workgroup */
     int32_t build_lanes;     /* lanes per atom in the list build (1 or 2) */
-    int32_t reserved_;
+    int32_t graph_captures;  /* rebuild intervals captured as graphs (tmd_set_graphs) */
+    int64_t graph_launches;  /* rebuild intervals run as graph launches */
 } tmd_info;
 
 /* Kernel classes reported by tmd_get_timing(). */
@@ -290,6 +291,21 @@ tmd_status tmd_adjoint_backward(tmd_system *sys, void *ws, size_t bytes, const d
  * accumulators. */
 tmd_status tmd_set_timing(tmd_system *sys, int32_t enable);
 tmd_status tmd_get_timing(tmd_system *sys, double *ms, int64_t *launches);
+
+/* Graph mode for tmd_integrate (off by default).  While enabled, and while
+ * thermo_every == 0 and timing is off, tmd_integrate() runs every whole
+ * rebuild interval that starts after a step number divisible by
+ * rebuild_every and ends before its last step as one HIP graph launch on
+ * `stream`: rebuild_every - 1 fused steps, the binning and list build, and
+ * the fused step after them.  The first such interval is captured on a
+ * stream the library creates and owns; as the interval flips which copy of
+ * the double-buffered state is current, runs alternate between two graphs.
+ * A graph is keyed by everything it bakes in (schedule, workspace pointers,
+ * current copies, interval) and recaptured when any of it changes.  Results
+ * are bit-identical to graph mode off.  Disabling releases the graphs;
+ * tmd_destroy() releases them and the capture stream.  The graphs hold no
+ * memsets and no host work. */
+tmd_status tmd_set_graphs(tmd_system *sys, int32_t enable);
 
 /* Static description of a status code. */
 const char *tmd_status_string(tmd_status status);

@@ -57,7 +57,8 @@ class TmdInfo(C.Structure):
         ("lanes_per_atom", C.c_int32),
         ("build_threads", C.c_int32),
         ("build_lanes", C.c_int32),
-        ("reserved_", C.c_int32),
+        ("graph_captures", C.c_int32),
+        ("graph_launches", C.c_int64),
     ]
 
 
@@ -102,6 +103,7 @@ def load_library():
         "tmd_adjoint_backward": (_S, [_P, _P, C.c_size_t, _P, _P, _P, _P, _P, _P, _P]),
         "tmd_autotune": (_S, [_P, C.c_int32, _P]),
         "tmd_set_timing": (_S, [_P, C.c_int32]),
+        "tmd_set_graphs": (_S, [_P, C.c_int32]),
         "tmd_get_timing": (_S, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "tmd_status_string": (C.c_char_p, [_S]),
         "tmd_last_error": (C.c_char_p, [_P]),
@@ -247,6 +249,10 @@ def tmd_autotune(handle, repeats: int, stream: int) -> None:
 
 def tmd_set_timing(handle, enable: bool) -> None:
     _check(load_library().tmd_set_timing(handle, 1 if enable else 0), handle)
+
+
+def tmd_set_graphs(handle, enable: bool) -> None:
+    _check(load_library().tmd_set_graphs(handle, 1 if enable else 0), handle)
 
 
 def tmd_get_timing(handle) -> dict:

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <new>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -52,6 +53,23 @@ struct tmd_system {
     std::vector<hipEvent_t> pool;
     double t_ms[TMD_T_COUNT] = {};
     int64_t t_n[TMD_T_COUNT] = {};
+
+    // Rebuild intervals of tmd_integrate captured as HIP graphs
+    // (tmd_set_graphs).  A graph bakes in the launch parameters, the buffer
+    // pointers and which copy of the double-buffered state each launch reads,
+    // so it is keyed by all of them; an interval flips the copies, so runs
+    // alternate between two graphs.
+    struct Seg {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec = nullptr;
+        Cursor cur_after;
+        bool counts_clear_after = false;
+    };
+    bool graphs = false;
+    hipStream_t cap_stream = nullptr;  // capture only: the graphs run on the caller's stream
+    std::vector<Seg> segs;
+    int32_t graph_captures = 0;
+    int64_t graph_launches = 0;
 };
 
 namespace {
@@ -496,6 +514,110 @@ tmd_status upload_tables(tmd_system *s, hipStream_t hs) {
     return e == hipSuccess ? TMD_OK : hip_fail(s, e, "table upload");
 }
 
+// What a captured interval bakes in: launch parameters, buffers, the copies
+// the state starts in, whether the cell counts start at zero, the interval.
+std::vector<unsigned char> seg_key(const tmd_system *s) {
+    std::vector<unsigned char> k(sizeof(Dims) + sizeof(Buffers) + sizeof(Cursor) + 2 * sizeof(int32_t));
+    unsigned char *p = k.data();
+    std::memcpy(p, &s->d, sizeof(Dims));
+    p += sizeof(Dims);
+    std::memcpy(p, &s->b, sizeof(Buffers));
+    p += sizeof(Buffers);
+    std::memcpy(p, &s->cur, sizeof(Cursor));
+    p += sizeof(Cursor);
+    const int32_t extra[2] = {s->counts_clear ? 1 : 0, s->rebuild_every};
+    std::memcpy(p, extra, sizeof(extra));
+    return k;
+}
+
+void drop_segs(tmd_system *s) {
+    for (auto &g : s->segs)
+        (void)hipGraphExecDestroy(g.exec);
+    s->segs.clear();
+}
+
+// One rebuild interval of tmd_integrate's loop, starting right after a step
+// whose number is a multiple of the interval: interval - 1 fused steps, the
+// rebuild, and the fused step after it.
+tmd_status enqueue_interval(tmd_system *s, hipStream_t hs) {
+    for (int32_t k = 1; k <= s->rebuild_every; ++k) {
+        if (k == s->rebuild_every) {
+            const tmd_status st = rebuild(s, hs);
+            if (st != TMD_OK)
+                return st;
+        }
+        const hipError_t e = launch_force(s->d, s->b, s->cur, 2, false, hs);
+        if (e != hipSuccess)
+            return hip_fail(s, e, "force");
+        s->cur.x = 1 - s->cur.x;
+    }
+    return TMD_OK;
+}
+
+// enqueue_interval() as one graph launch on hs: replayed when an interval
+// with the same key was captured before, else captured on the system's own
+// stream, instantiated and launched.  The host-side state advances as the
+// eager path's would.
+tmd_status run_interval(tmd_system *s, hipStream_t hs) {
+    if (s->tables_dirty || !s->prepared) {
+        const tmd_status u = upload_tables(s, hs);  // never inside a capture
+        if (u != TMD_OK)
+            return u;
+    }
+    const std::vector<unsigned char> key = seg_key(s);
+    for (auto &g : s->segs)
+        if (g.key == key) {
+            const hipError_t e = hipGraphLaunch(g.exec, hs);
+            if (e != hipSuccess)
+                return hip_fail(s, e, "graph launch");
+            s->graph_launches++;
+            s->cur = g.cur_after;
+            s->counts_clear = g.counts_clear_after;
+            s->list_valid = true;
+            s->force_valid = false;
+            s->gen++;
+            return TMD_OK;
+        }
+    if (s->segs.size() >= 2)
+        drop_segs(s);  // parameters or buffers changed: the old graphs are stale
+    hipError_t e = hipSuccess;
+    if (!s->cap_stream)
+        e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return hip_fail(s, e, "graph capture");
+    const Cursor cur0 = s->cur;
+    const bool clear0 = s->counts_clear, list0 = s->list_valid, force0 = s->force_valid;
+    const tmd_status st = enqueue_interval(s, s->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s->cap_stream, &graph);
+    tmd_system::Seg g;
+    g.key = key;
+    g.cur_after = s->cur;
+    g.counts_clear_after = s->counts_clear;
+    if (st == TMD_OK && e == hipSuccess)
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (graph)
+        (void)hipGraphDestroy(graph);
+    if (st != TMD_OK || e != hipSuccess) {
+        // nothing ran: put the host-side state back
+        s->cur = cur0;
+        s->counts_clear = clear0;
+        s->list_valid = list0;
+        s->force_valid = force0;
+        if (g.exec)
+            (void)hipGraphExecDestroy(g.exec);
+        return st != TMD_OK ? st : hip_fail(s, e, "graph capture");
+    }
+    e = hipGraphLaunch(g.exec, hs);
+    s->segs.push_back(std::move(g));
+    s->graph_captures++;
+    if (e == hipSuccess)
+        s->graph_launches++;
+    return e == hipSuccess ? TMD_OK : hip_fail(s, e, "graph launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -641,8 +763,16 @@ tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, d
     const int64_t rb = s->rebuild_every;
     const int64_t row_stride = int64_t(s->d.nbox) * 5;
     TimedRun run(s, TMD_T_FORCE, hs);
+    const bool graphs = s->graphs && thermo_every == 0 && !s->timing;
     for (int32_t k = 1; k <= n_steps; ++k) {
         const int64_t stepk = s->step + k;
+        if (graphs && (stepk - 1) % rb == 0 && int64_t(k) - 1 + rb <= int64_t(n_steps) - 1) {
+            // a whole rebuild interval before the last step: one graph launch
+            if ((st = run_interval(s, hs)) != TMD_OK)
+                return st;
+            k += int32_t(rb) - 1;
+            continue;
+        }
         if (stepk % rb == 0) {
             run.close();
             if ((st = rebuild(s, hs)) != TMD_OK)
@@ -757,6 +887,8 @@ tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
     info->lanes_per_atom = s->d.lpa;
     info->build_threads = s->d.bthreads;
     info->build_lanes = s->d.blanes;
+    info->graph_captures = s->graph_captures;
+    info->graph_launches = s->graph_launches;
     return TMD_OK;
 }
 
@@ -1113,6 +1245,15 @@ tmd_status tmd_set_timing(tmd_system *s, int32_t enable) {
     return TMD_OK;
 }
 
+tmd_status tmd_set_graphs(tmd_system *s, int32_t enable) {
+    if (!s)
+        return TMD_EINVAL;
+    s->graphs = enable != 0;
+    if (!s->graphs)
+        drop_segs(s);
+    return TMD_OK;
+}
+
 tmd_status tmd_get_timing(tmd_system *s, double *ms, int64_t *launches) {
     if (!s || !ms || !launches)
         return TMD_EINVAL;
@@ -1148,6 +1289,9 @@ void tmd_destroy(tmd_system *s) {
     }
     for (hipEvent_t e : s->pool)
         (void)hipEventDestroy(e);
+    drop_segs(s);
+    if (s->cap_stream)
+        (void)hipStreamDestroy(s->cap_stream);
     delete s;
 }
 

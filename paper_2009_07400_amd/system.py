@@ -199,6 +199,11 @@ class System:
         self._keep = [lx, lv]
         return gx.t(), gv.t(), ge, gs
 
+    def set_graphs(self, enable: bool) -> None:
+        """Run whole rebuild intervals of integrate() as captured HIP graphs
+        (bit-identical results; see tmd_set_graphs)."""
+        abi.tmd_set_graphs(self._h, enable)
+
     def set_timing(self, enable: bool) -> None:
         abi.tmd_set_timing(self._h, enable)
 

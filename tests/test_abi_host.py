@@ -51,6 +51,20 @@ def test_create_and_info():
         assert info["workspace_bytes"] == abi.tmd_workspace_size(h)
         # the list alone needs max_neighbors int32 per padded atom
         assert info["workspace_bytes"] > info["n_padded"] * 128 * 4
+        assert info["graph_captures"] == 0 and info["graph_launches"] == 0
+    finally:
+        abi.tmd_destroy(h)
+
+
+def test_graph_mode_switch_needs_no_gpu():
+    # enabling captures nothing until tmd_integrate; disabling drops nothing
+    h = _create()
+    try:
+        abi.tmd_set_graphs(h, True)
+        abi.tmd_set_graphs(h, False)
+        abi.tmd_set_graphs(h, True)
+        info = abi.tmd_get_info(h)
+        assert info["graph_captures"] == 0 and info["graph_launches"] == 0
     finally:
         abi.tmd_destroy(h)
 
@@ -175,4 +189,5 @@ def test_null_arguments():
     p = make_params()
     assert lib.tmd_create(C.byref(p), 10, 13.4, C.byref(out)) == abi.TMD_OK
     assert lib.tmd_set_timing(out, 1) == abi.TMD_OK
+    assert lib.tmd_set_graphs(None, 1) == abi.TMD_EINVAL
     lib.tmd_destroy(out)
