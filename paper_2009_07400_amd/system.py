@@ -12,6 +12,7 @@ from typing import Sequence
 import torch
 
 from . import _abi as abi
+from . import tune_cache
 
 
 def _stream() -> int:
@@ -155,17 +156,35 @@ class System:
         abi.tmd_set_schedule(self._h, threads, lds_atoms, block_edge, block_parts, lanes_per_atom, build_threads,
                              build_lanes)
 
-    def autotune(self, repeats: int = 5):
+    def autotune(self, repeats: int = 5, cache: str | None = None):
         """Times each schedule (block edge, workgroups per block, lanes per
         atom, force and build threads) by one force evaluation plus a list
         build's share per step and keeps the fastest; returns a dict of
-        block_edge, block_parts, lanes_per_atom, block_threads and
-        build_threads and build_lanes.  Rebuilds the list at the current
-        positions."""
+        block_edge, block_parts, lanes_per_atom, block_threads, build_threads,
+        build_lanes and lds_atoms, and "cached".  Rebuilds the list at the
+        current positions.
+
+        With ``cache`` (a JSON file path), a schedule stored there for the
+        same device, library build and system shape is applied instead of
+        tuning ("cached": True; the list is rebuilt at the next step), and
+        a fresh pick is stored."""
+        key = None
+        if cache is not None:
+            key = tune_cache.system_key(torch.cuda.get_device_name(self.device), tune_cache.file_digest(abi.LIB_PATH),
+                                        self.box_atoms, self.box_lengths, self.params)
+            hit = tune_cache.lookup(cache, key)
+            if hit is not None:
+                self.set_schedule(threads=hit["block_threads"], lds_atoms=hit["lds_atoms"],
+                                  block_edge=hit["block_edge"], block_parts=hit["block_parts"],
+                                  lanes_per_atom=hit["lanes_per_atom"], build_threads=hit["build_threads"],
+                                  build_lanes=hit["build_lanes"])
+                return dict(hit, cached=True)
         abi.tmd_autotune(self._h, repeats, _stream())
         info = self.info()
-        return {k: info[k] for k in ("block_edge", "block_parts", "lanes_per_atom", "block_threads", "build_threads",
-                                     "build_lanes")}
+        sched = {k: info[k] for k in tune_cache.SCHEDULE_KEYS}
+        if key is not None:
+            tune_cache.store(cache, key, sched)
+        return dict(sched, cached=False)
 
     def set_lj_params(self, epsilon, sigma) -> None:
         """Per-box epsilon and sigma (sequences of n_boxes floats, or scalars)."""

@@ -192,6 +192,26 @@ def test_autotune_keeps_state():
     assert torch.equal(p0, p1) and torch.equal(v0, v1)
 
 
+def test_autotune_cache_applies_the_stored_schedule(tmp_path):
+    s = md_system(10, seed=23)
+    cache = str(tmp_path / "tune.json")
+    picks = []
+    for _ in range(2):
+        g = System(s.n, s.L)
+        g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
+        g.integrate(5)
+        picks.append((g.autotune(repeats=2, cache=cache), g.info()))
+        g.integrate(25)  # runs on the applied schedule (list rebuilt)
+        g.sync()
+        g.close()
+    (first, info1), (second, info2) = picks
+    assert first["cached"] is False and second["cached"] is True
+    keys = ("block_threads", "lds_atoms", "block_edge", "block_parts", "lanes_per_atom", "build_threads",
+            "build_lanes")
+    assert {k: first[k] for k in keys} == {k: second[k] for k in keys}
+    assert all(info1[k] == info2[k] for k in keys)
+
+
 def test_replica_workload_generator_batch_small():
     """A slice of the 512-box replica workload (first 12 boxes) through the
     batch path, 40 steps, each box against the oracle."""
