@@ -390,6 +390,7 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
         B.L = L;
         B.halfL = 0.5 * L;
         B.halfL2 = B.halfL * B.halfL;
+        B.invL = 1.0 / L;
         B.side = L / B.nc;
         B.rc2 = p.cutoff * p.cutoff;
         B.rl2 = r * r;

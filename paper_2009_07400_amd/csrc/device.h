@@ -51,34 +51,32 @@ __device__ __forceinline__ double pair_delta(double xi, double yi, double zi, do
     return s;
 }
 
-// Image of partner coordinate xj nearest to xi, given d = xi - xj: xj
-// shifted by one box length when |d| > L/2 (xj + 0.0 is xj itself).
-__device__ __forceinline__ double partner_image(double xj, double d, double L, double halfL) {
-    return xj + ((d > halfL) ? L : ((d < -halfL) ? -L : 0.0));
+// Difference along one axis to the partner's nearest image, xi - (xj + n L)
+// with n = rint((xi - xj) / L) in {-1, 0, 1} (positions stay within a
+// fraction of a cell of [0, L)): n L is exact, so the shifted partner xj +/-
+// L is rounded once, as nearest_image() rounds it.  The shift differs from a
+// test of |xi - xj| > L/2 only where (xi - xj) / L rounds across 1/2, that is
+// |xi - xj| within an ulp or two of L/2, beyond every cutoff (the library
+// requires cutoff + skin < L/2), where the pair adds nothing either way.
+__device__ __forceinline__ double mic_delta(double xi, double xj, double L, double invL) {
+    return xi - fma(rint((xi - xj) * invL), L, xj);
 }
 
 // The pair geometry of the kernels that evaluate forces and their
 // derivatives, with |d|^2 formed by fused multiply-adds: there it only
 // decides the cutoff test, and the force kernel and the adjoint's
-// Hessian-vector product must take that decision identically.  Across a
-// face the difference is taken to the partner's nearest image, xi - (xj +/-
-// L), the same two roundings as in pair_delta_img() on a neighborhood copy
-// whose positions were moved to their images near the block (see
-// nearest_image()), so both give the same bits.
+// Hessian-vector product must take that decision identically.  The
+// difference is taken to the partner's nearest image (mic_delta()), the
+// same two roundings as in pair_delta_img() on a neighborhood copy whose
+// positions were moved to their images near the block (see
+// nearest_image()), so both give the same bits.  Branch-free: in small
+// boxes most wavefronts have a lane whose partner lies across a face.
 __device__ __forceinline__ double pair_delta_fma(double xi, double yi, double zi, double xj, double yj, double zj,
-                                                double L, double halfL, double halfL2, double &dx, double &dy,
-                                                double &dz) {
-    dx = xi - xj;
-    dy = yi - yj;
-    dz = zi - zj;
-    double s = fma(dz, dz, fma(dy, dy, dx * dx));
-    if (s >= halfL2) {
-        dx = xi - partner_image(xj, dx, L, halfL);
-        dy = yi - partner_image(yj, dy, L, halfL);
-        dz = zi - partner_image(zj, dz, L, halfL);
-        s = fma(dz, dz, fma(dy, dy, dx * dx));
-    }
-    return s;
+                                                double L, double invL, double &dx, double &dy, double &dz) {
+    dx = mic_delta(xi, xj, L, invL);
+    dy = mic_delta(yi, yj, L, invL);
+    dz = mic_delta(zi, zj, L, invL);
+    return fma(dz, dz, fma(dy, dy, dx * dx));
 }
 
 // pair_delta_fma() for a partner position that already is the image nearest

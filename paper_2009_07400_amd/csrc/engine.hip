@@ -915,7 +915,7 @@ __device__ __forceinline__ void eval2(const Duo &q, double xi, double yi, double
         double dx, dy, dz;
         // with IMG the partner positions already are the images nearest to i
         const double s = IMG ? pair_delta_img(xi, yi, zi, q.x[m], q.y[m], q.z[m], dx, dy, dz)
-                             : pair_delta_fma(xi, yi, zi, q.x[m], q.y[m], q.z[m], B.L, B.halfL, B.halfL2, dx, dy, dz);
+                             : pair_delta_fma(xi, yi, zi, q.x[m], q.y[m], q.z[m], B.L, B.invL, dx, dy, dz);
         if (s < B.rc2) {
             const double sr2 = recip(s);
             const double q3 = sr2 * sr2 * sr2;
@@ -1393,7 +1393,7 @@ __device__ __forceinline__ void hvp_pair(double xj, double yj, double zj, double
                                          double &pe, double &ps) {
     double dx, dy, dz;
     const double s = IMG ? pair_delta_img(xi, yi, zi, xj, yj, zj, dx, dy, dz)
-                         : pair_delta_fma(xi, yi, zi, xj, yj, zj, B.L, B.halfL, B.halfL2, dx, dy, dz);
+                         : pair_delta_fma(xi, yi, zi, xj, yj, zj, B.L, B.invL, dx, dy, dz);
     if (s < B.rc2) {
         const double sr2 = recip_exact(s);
         const double q3 = sr2 * sr2 * sr2;

@@ -35,6 +35,7 @@ struct Box {
     int32_t nblocks, edge;   // blocks of this box; E
     double L, halfL, side;   // box, half box, cell side L / nc
     double halfL2;           // (L/2)^2
+    double invL;             // 1 / L
     double rc2, rl2;         // cutoff^2, (cutoff + skin)^2
     double eps, sigma6;      // LJ parameters
     double eps48, eps24;     // 48 eps and 24 eps: f = sr2 sr6 (48 eps sr6 - 24 eps)
