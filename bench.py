@@ -257,6 +257,11 @@ def run_adjoint(steps: int = 200, replicas: int = 64):
     v0 = torch.from_numpy(np.concatenate([r.vel() for r in reps]))
     g = System.batch([r.n for r in reps], [r.L for r in reps], dict(max_neighbors=128))
     lam = torch.randn(total, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(5))
+    # one schedule for both runs, tuned a rebuild interval into the run
+    g.set_state(x0, v0)
+    g.integrate(20)
+    g.autotune(repeats=3)
+    sched = _schedule(g)
     for _ in range(2):  # second pass is the timed one
         g.set_state(x0, v0)
         g.sync()
@@ -281,7 +286,8 @@ def run_adjoint(steps: int = 200, replicas: int = 64):
                         "checkpoints at every rebuild (20)",
             "value": total * steps / (t2 - t0), "unit": "atom-steps/s (forward + reverse per step)",
             "plain_value": total * steps / t_plain, "adjoint_over_plain_time": (t2 - t0) / t_plain,
-            "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3, "plain_ms": t_plain * 1e3}
+            "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3, "plain_ms": t_plain * 1e3,
+            "schedule": sched}
 
 
 def run_cpu_baseline(workload: str, sample_steps: int):
