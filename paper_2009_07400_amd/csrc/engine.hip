@@ -698,6 +698,52 @@ __device__ __forceinline__ Box block_box(const Dims &d, const Box *__restrict__ 
 // LDS slots, or 32-bit global indices when the neighborhood did not fit.
 // Both lane counts write the same list: entries in the order of the
 // stencil's runs and, within a run, of the LDS slots.
+// One run of consecutive LDS slots [beg, end) of atom i's stencil, one lane
+// per atom: four candidates per round, their LDS reads issued together and
+// unconditional (up to three slots past the run's end: other atoms, the
+// sentinel, pad or unused slots, all failing the t < end test).  Accepted
+// slots go to the 16-bit list at wp, entry c.  MIC: the neighborhood may
+// wrap the box, so the difference takes the minimum image; without it no
+// raw difference along an axis exceeds L/2 and the image test is dropped
+// (it could only recompute the same value).
+template <bool MIC>
+__device__ __forceinline__ void build_run1(lds_double *S, int beg, int end, int self, double xi, double yi,
+                                           double zi, const Box &B, int maxnb, uint16_t *&wp, int &c) {
+    for (int t0 = beg; t0 < end; t0 += 4) {
+        const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t0), 24u);
+        double px[4], py[4], pz[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const lds_double *q = (const lds_double *)(pb + r * 24);
+            px[r] = q[0];
+            py[r] = q[1];
+            pz[r] = q[2];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double dx, dy, dz;
+            double s;
+            if (MIC) {
+                s = pair_delta(xi, yi, zi, px[r], py[r], pz[r], B.L, B.halfL, B.halfL2, dx, dy, dz);
+            } else {
+                dx = xi - px[r];
+                dy = yi - py[r];
+                dz = zi - pz[r];
+                s = dist2(dx, dy, dz);
+            }
+            const int t = t0 + r;
+            if (s < B.rl2 && t < end && t != self) {
+                // entry c of the 16-bit list: the next element, or the
+                // first element of the next 16-byte row of the tile
+                if (c < maxnb)
+                    *wp = uint16_t(t);
+                wp += ((c & 7) == 7) ? 505 : 1;
+                ++c;
+            }
+        }
+    }
+}
+
 template <int BL>
 __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__restrict__ boxes,
                                                        const int32_t *__restrict__ blk_box,
@@ -728,6 +774,18 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     uint16_t *nbr16 = reinterpret_cast<uint16_t *>(nbr);
     int n[3], co[3][kAxis];
     hood_axes(B, lb, n, co);
+    // no neighborhood cell range wraps the box and each spans at most half
+    // of it: no raw difference along an axis exceeds L/2
+    bool interior = true;
+    {
+        const int nbx = B.nbx;
+        const int bc[3] = {lb % nbx, (lb / nbx) % nbx, lb / (nbx * nbx)};
+        for (int a = 0; a < 3; ++a) {
+            const int c0 = B.edge * bc[a];
+            const int e = min(B.edge, B.nc - c0);
+            interior &= c0 >= 1 && c0 + e <= B.nc - 1 && 2 * (e + 2) <= B.nc;
+        }
+    }
     const int p = threadIdx.x & (BL - 1);  // lane of the atom's pair (BL = 2)
     for (int i = lo + threadIdx.x / BL; i < hi; i += blockDim.x / BL) {
         const double xi = x[i], yi = y[i], zi = z[i];
@@ -808,34 +866,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                             }
                             continue;
                         }
-                        // four candidates per round, their LDS reads issued together;
-                        // past the end of the run a candidate is the NaN sentinel
-                        for (int t0 = beg; t0 < end; t0 += 4) {
-                            int tt[4];
-                            double px[4], py[4], pz[4];
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                tt[r] = t0 + r < end ? t0 + r : d.cap;
-                                const lds_double *p = lds_slot(S, tt[r]);
-                                px[r] = p[0];
-                                py[r] = p[1];
-                                pz[r] = p[2];
-                            }
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                double dx, dy, dz;
-                                const double s = pair_delta(xi, yi, zi, px[r], py[r], pz[r], B.L, B.halfL, B.halfL2,
-                                                            dx, dy, dz);
-                                if (s < B.rl2 && tt[r] != self) {
-                                    // entry c of the 16-bit list: the next element, or the
-                                    // first element of the next 16-byte row of the tile
-                                    if (c < d.maxnb)
-                                        *wp = uint16_t(tt[r]);
-                                    wp += ((c & 7) == 7) ? 505 : 1;
-                                    ++c;
-                                }
-                            }
-                        }
+                        if (interior)
+                            build_run1<false>(S, beg, end, self, xi, yi, zi, B, d.maxnb, wp, c);
+                        else
+                            build_run1<true>(S, beg, end, self, xi, yi, zi, B, d.maxnb, wp, c);
                     }
                 }
         } else if (p == 0) {  // (global gathers: the atom's first lane alone)
