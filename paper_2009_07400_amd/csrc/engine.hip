@@ -1447,14 +1447,19 @@ __device__ __forceinline__ void hvp_pair(double xj, double yj, double zj, double
     }
 }
 
-// hvp terms over a 16-bit list, with pair_sum16's loop discipline.
+// hvp terms over a 16-bit list, with pair_sum16's loop discipline and its
+// split of the list over L lanes per atom (lane p walks chunks p, p + L,
+// ...; i0 and i1 are the lane's first two chunks).
 template <bool IMG>
-__device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int c, lds_double *S,
-                                          double xi, double yi, double zi, double wxi, double wyi, double wzi,
-                                          const Box &B, const HvpConst &k, double &gx, double &gy, double &gz,
-                                          double &pe, double &ps) {
+__device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int p, int L, int c,
+                                          lds_double *S, double xi, double yi, double zi, double wxi, double wyi,
+                                          double wzi, const Box &B, const HvpConst &k, double &gx, double &gy,
+                                          double &gz, double &pe, double &ps) {
     const int nch = (c + 7) >> 3;
-    auto ld = [&](int kk) { return __builtin_nontemporal_load(chunks + (kk < nch ? kk : nch) * 64); };
+    auto ld = [&](int kk) {
+        const int q = p + L * kk;
+        return __builtin_nontemporal_load(chunks + (q < nch ? q : nch) * 64);
+    };
     auto ev = [&](const Duo6 &q) {
 #pragma unroll
         for (int m = 0; m < 2; ++m)
@@ -1483,10 +1488,10 @@ __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0
         fetch2w6(S, i0[0], P);
         i1 = ld(kk + 3);
         ev(Q);
-        if (!__any(kk + 3 < nch))
+        if (!__any(p + L * (kk + 3) < nch))
             break;
     }
-    if (__any(kk + 2 < nch)) {  // an odd last chunk, as in pair_sum16
+    if (__any(p + L * (kk + 2) < nch)) {  // an odd last chunk, as in pair_sum16
         fetch2w6(S, i0[1], Q);
         ev(P);
         fetch2w6(S, i0[2], P);
@@ -1506,7 +1511,11 @@ __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0
 // workgroup's partial sums of w_i . dF_i/deps and w_i . dF_i/dsigma go to
 // `partials`.  With drift_adj the adjoint of the drift before this force
 // evaluation follows: wout_i = w_i + dt lam_x_i.  The neighborhood is staged
-// with w (48 bytes per slot).
+// with w (48 bytes per slot).  L lanes per atom split its list as the force
+// kernel's lanes do (groups of eight entries dealt in turn, on the 32-bit
+// path too, so both paths give the same sums) and combine their sums by a
+// butterfly; the atom's first lane writes.
+template <int L>
 __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restrict__ boxes,
                                                      const int32_t *__restrict__ blk_box, Pos x,
                                                      const int32_t *__restrict__ hood_tab,
@@ -1534,25 +1543,42 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
     double pe = 0.0, ps = 0.0, unused = 0.0;
     int lo, hi;
     h.share(part, d.parts, lo, hi);
-    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int p = threadIdx.x & (L - 1);
+    const int T = blockDim.x / L;
+    for (int i = lo + threadIdx.x / L; i < hi; i += T) {
         const double xi = x.x[i], yi = x.y[i], zi = x.z[i];
         const double wxi = w.x[i], wyi = w.y[i], wzi = w.z[i];
         double gx = 0.0, gy = 0.0, gz = 0.0;
         const int c = cnt[i];
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
-        if (im.on) {
-            hvp_sum16<true>(chunks, __builtin_nontemporal_load(chunks), __builtin_nontemporal_load(chunks + 64), c, S,
-                            xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
-        } else if (fits) {
-            hvp_sum16<false>(chunks, __builtin_nontemporal_load(chunks), __builtin_nontemporal_load(chunks + 64), c, S,
-                             xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
+        if (fits) {
+            // rows p and p + L (at most row 7): every 16-bit list fills them
+            const v4i r0 = __builtin_nontemporal_load(chunks + min(p, d.nchunk - 1) * 64);
+            const v4i r1 = __builtin_nontemporal_load(chunks + min(p + L, d.nchunk - 1) * 64);
+            if (im.on)
+                hvp_sum16<true>(chunks, r0, r1, p, L, c, S, xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
+            else
+                hvp_sum16<false>(chunks, r0, r1, p, L, c, S, xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
         } else {
-            for (int kk = 0; kk < c; ++kk) {
-                const int j = nbr[nbr_index(i, kk, d.nchunk)];
-                hvp_pair<false>(x.x[j], x.y[j], x.z[j], w.x[j], w.y[j], w.z[j], xi, yi, zi, wxi, wyi, wzi, B, k, gx,
-                                gy, gz, pe, ps);
-            }
+            // groups of eight entries dealt in turn, as on the 16-bit path;
+            // past the count the 32-bit list holds sentinels (global slot nt)
+            // through the chunk after its last one, which add nothing
+            const int ng = (c + 7) >> 3;
+            for (int g = p; g < ng; g += L)
+                for (int e = 0; e < 8; ++e) {
+                    const int j = nbr[nbr_index(i, 8 * g + e, d.nchunk)];
+                    hvp_pair<false>(x.x[j], x.y[j], x.z[j], w.x[j], w.y[j], w.z[j], xi, yi, zi, wxi, wyi, wzi, B, k,
+                                    gx, gy, gz, pe, ps);
+                }
         }
+#pragma unroll
+        for (int o = 1; o < L; o <<= 1) {
+            gx += __shfl_xor(gx, o, 64);
+            gy += __shfl_xor(gy, o, 64);
+            gz += __shfl_xor(gz, o, 64);
+        }
+        if (p != 0)
+            continue;
         const double cc = mult * B.h;
         const double lx = lam.x[i] + cc * gx, ly = lam.y[i] + cc * gy, lz = lam.z[i] + cc * gz;
         lam.x[i] = lx;
@@ -1657,8 +1683,13 @@ hipError_t prepare_kernels(const Dims &d) {
         if (e != hipSuccess)
             return e;
     }
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hvp), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               2 * bytes);
+    for (const void *f : {reinterpret_cast<const void *>(&k_hvp<1>), reinterpret_cast<const void *>(&k_hvp<2>),
+                          reinterpret_cast<const void *>(&k_hvp<4>)}) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * bytes);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_gather(const Dims &d, const double *const src[3], const int32_t *orig, const Pos &dst,
@@ -1668,11 +1699,32 @@ hipError_t launch_gather(const Dims &d, const double *const src[3], const int32_
     return hipGetLastError();
 }
 
+// Lanes per atom of the reverse kernel: the most (up to four) whose lanes
+// for a workgroup's mean atom count fit one workgroup; threads: those lanes
+// for the mean atom count, in whole wavefronts.  Its 48-byte LDS slots often
+// leave room for one workgroup per CU only, which more lanes fill with
+// wavefronts.
+static void hvp_shape(const Dims &d, int &lanes, int &threads) {
+    const double per_wg = double(d.nt) / (double(d.nblk) * d.parts);
+    lanes = per_wg * 4.0 <= double(kMaxThreads) ? 4 : (per_wg * 2.0 <= double(kMaxThreads) ? 2 : 1);
+    threads = std::min(kMaxThreads, std::max(64, round_up(int(per_wg * lanes + 0.5), 64)));
+}
+
 hipError_t launch_hvp(const Dims &d, Buffers &b, const Pos &x, const Pos &w, const Pos &lam_x, const Pos &wout,
                       double mult, bool drift_adj, double *partials, hipStream_t s) {
-    k_hvp<<<block_grid(d.nblk * d.parts), d.bthreads, 2 * hood_lds_bytes(d.cap), s>>>(
-        d, b.boxes, b.blk_box, x, b.hood_tab, b.nbr_count, b.nbr, w, lam_x, wout, mult, drift_adj ? 1 : 0,
-        partials);
+    int L = 1, threads = 64;
+    hvp_shape(d, L, threads);
+    const size_t lds = 2 * hood_lds_bytes(d.cap);
+    const int grid = block_grid(d.nblk * d.parts), da = drift_adj ? 1 : 0;
+    if (L == 4)
+        k_hvp<4><<<grid, threads, lds, s>>>(d, b.boxes, b.blk_box, x, b.hood_tab, b.nbr_count, b.nbr, w, lam_x, wout,
+                                            mult, da, partials);
+    else if (L == 2)
+        k_hvp<2><<<grid, threads, lds, s>>>(d, b.boxes, b.blk_box, x, b.hood_tab, b.nbr_count, b.nbr, w, lam_x, wout,
+                                            mult, da, partials);
+    else
+        k_hvp<1><<<grid, threads, lds, s>>>(d, b.boxes, b.blk_box, x, b.hood_tab, b.nbr_count, b.nbr, w, lam_x, wout,
+                                            mult, da, partials);
     return hipGetLastError();
 }
 
