@@ -260,16 +260,6 @@ __device__ __forceinline__ lds_double *lds_slot(lds_double *base, int slot) {
     return (lds_double *)((lds_char *)base + __umul24(unsigned(slot), 24u));
 }
 
-struct LdsPos {
-    lds_double *s;
-    __device__ __forceinline__ void get(int j, double &x, double &y, double &z) const {
-        const lds_double *a = lds_slot(s, j);
-        x = a[0];
-        y = a[1];
-        z = a[2];
-    }
-};
-
 struct GlobalPos {
     const double *__restrict__ x;
     const double *__restrict__ y;
@@ -1129,7 +1119,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     hood_commit(hw, h);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
-    const LdsPos spos{(lds_double *)lds};
+    lds_double *const S = (lds_double *)lds;
     const GlobalPos gpos{x, y, z};
     const HoodImage im = hood_image(B, b - B.block_off, fits);
     // The operands of a lane's next atom (position, list length, velocity)
@@ -1168,7 +1158,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     if (hi > lo)
         load_atom(i);
     if (fits)
-        hood_stage(h, total, d.cap, x, y, z, spos.s, im);
+        hood_stage(h, total, d.cap, x, y, z, S, im);
     // have every kernel argument in registers before the atom loop: a scalar
     // load still in flight at the pair loop's head costs it exact LDS waits
     asm volatile("" ::"s"(err), "s"(partials), "s"(xo), "s"(fx));
