@@ -122,6 +122,17 @@ def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int) -> dict:
     return out
 
 
+def _force_flops(n: int, mean_list: float, avg_s: float, rc: float = 2.5, rl: float = 2.8) -> dict:
+    """Nominal FP64 work of the force kernel beside its HBM roofline: 8
+    operations per listed pair (difference, |d|^2, cutoff test) and 15 more
+    per interacting pair (reciprocal, force factor, accumulation), the
+    interacting share of the list taken as (rc / rl)^3 (uniform density)."""
+    n_int = mean_list * (rc / rl) ** 3
+    fl = (8.0 * mean_list + 15.0 * n_int) * n
+    return {"fp64_flops_per_launch": fl, "fp64_tflops": fl / avg_s / 1e12,
+            "fp64_frac": fl / avg_s / 1e12 / FP64_PEAK_TFLOPS}
+
+
 def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     import torch
 
@@ -180,6 +191,7 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
             "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": avg_s * 1e6,
+            **_force_flops(s.n, mean_list, avg_s),
         },
         "build_rooflines": _build_rooflines(tm, s.n, mean_list, n_cells),
     }

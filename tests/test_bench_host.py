@@ -38,6 +38,15 @@ def test_build_rooflines_arithmetic():
     assert nb["hbm_frac"] == pytest.approx(nb["hbm_achieved_gbs"] / 8000.0)
 
 
+def test_force_flops_arithmetic():
+    b = _bench()
+    r = b._force_flops(1000, 75.0, 1e-3)
+    n_int = 75.0 * (2.5 / 2.8) ** 3
+    assert r["fp64_flops_per_launch"] == pytest.approx((8 * 75.0 + 15 * n_int) * 1000)
+    assert r["fp64_tflops"] == pytest.approx(r["fp64_flops_per_launch"] / 1e-3 / 1e12)
+    assert r["fp64_frac"] == pytest.approx(r["fp64_tflops"] / 78.6)
+
+
 def test_build_rooflines_skip_kernels_not_run():
     b = _bench()
     assert b._build_rooflines({"force": (1.0, 10), "neighbor": (0.0, 0)}, 10, 1.0, 1) == {}
