@@ -1107,6 +1107,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     int b, part;
     if (!block_part(d, b, part))
         return;
+    // the prologue (table, staging) waits on memory while the other
+    // workgroup on the CU runs its pair loop: its waves issue first, so the
+    // loads go out early, and drop back to normal priority for the loop
+    __builtin_amdgcn_s_setprio(2);
     if (threadIdx.x == 0 && unsigned(uintptr_t((lds_char *)lds)) != 0u)
         atomicOr(err, kErrLdsLayout);
     HoodWords hw;
@@ -1162,6 +1166,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     // have every kernel argument in registers before the atom loop: a scalar
     // load still in flight at the pair loop's head costs it exact LDS waits
     asm volatile("" ::"s"(err), "s"(partials), "s"(xo), "s"(fx));
+    __builtin_amdgcn_s_setprio(0);
     double u = 0.0, w = 0.0, ke = 0.0;
     for (; i < hi; i += T) {
         double ax = 0.0, ay = 0.0, az = 0.0;
