@@ -233,7 +233,9 @@ tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms,
  * of the step kernel (force sum, kicks and drift) plus 1/rebuild_every of a
  * list build: for each edge and workgroups per block, times `repeats`
  * builds per (build lanes, build threads) and `repeats` step-kernel launches per
- * (lanes, threads) candidate on `stream` with HIP events
+ * (lanes, threads) candidate, threads from one lane group per mean block
+ * atom (in whole wavefronts) up to two wavefronts more, on `stream` with HIP
+ * events
  * (synchronises; the launches work on spare copies of the state).  Tune
  * on a state like the one the run will see: every wavefront runs to the
  * longest list among its atoms, so a perfect lattice, where all lists have

@@ -1030,9 +1030,13 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
             s->d.blanes = bl_best;
             for (int32_t Lp = 1; Lp <= 4 && e == hipSuccess; Lp *= 2) {
                 s->d.lpa = Lp;
+                // from one lane group per mean block atom (in whole
+                // wavefronts) up to two wavefronts more: fewer threads put
+                // most blocks through a partial second pass, which launches
+                // timed back to back on unchanged inputs can rank first
+                // although it is slower in a run
                 const int32_t t0 = default_threads(s->d, Lp);
-                for (int32_t t = std::max(64, t0 - 128); t <= std::min(kMaxThreads, t0 + 128) && e == hipSuccess;
-                     t += 64) {
+                for (int32_t t = t0; t <= std::min(kMaxThreads, t0 + 128) && e == hipSuccess; t += 64) {
                     s->d.threads = t;
                     // cost per step: one force evaluation plus the list build's share
                     float ms = 0.0f;
