@@ -8,9 +8,8 @@
  * header, table or helper with the HIP library.
  *
  * What it computes, and where the paper defines it:
- *   - LJ 12-6 pair force (Sec. 3.2, Eq. 2, and the compute_potential example
- *     in Sec. 4.2): with s = |x_ij|^2, sr2 = 1/s, sr6 = sigma^6 sr2^3,
- *     f = 48 eps sr6 (sr6 - 1/2) sr2 and F_ij = f x_ij.
+ *   - LJ 12-6 pair force (Sec. 3.2, Eq. 2): with s = |x_ij|^2 and
+ *     q = (sigma^2 / s)^3, f = 24 eps q (2 q - 1) / s and F_ij = f x_ij.
  *   - LJ pair energy (the potential written beside Eq. 2): 4 eps (sr6^2 - sr6),
  *     unshifted; virial W = 1/2 sum_i sum_j s f(s).
  *   - Periodic boundaries in all directions (Sec. 3.2): minimum image per
@@ -55,22 +54,21 @@ int orc_num_threads(void)
 /* Pair terms                                                          */
 /* ------------------------------------------------------------------ */
 
-/* Scalar LJ force factor f(s) with F_ij = f(s) * x_ij (Sec. 4.2 listing). */
+/* Scalar LJ force factor f(s) with F_ij = f(s) * x_ij, s = |x_ij|^2, as
+ * Sec. 3.2 Eq. 2 writes it: 24 eps (sigma/r)^6 [2 (sigma/r)^6 - 1] / r^2. */
 double orc_pair_force(double s, double eps, double sigma)
 {
-    double sigma6 = pow(sigma, 6.0);
-    double sr2 = 1.0 / s;
-    double sr6 = sr2 * sr2 * sr2 * sigma6;
-    return 48.0 * sr6 * (sr6 - 0.5) * sr2 * eps;
+    double t = sigma * sigma / s; /* (sigma/r)^2 */
+    double q = t * t * t;         /* (sigma/r)^6 */
+    return 24.0 * eps * q * (2.0 * q - 1.0) / s;
 }
 
 /* LJ pair energy 4 eps [(sigma/r)^12 - (sigma/r)^6] (beside Eq. 2). */
 double orc_pair_energy(double s, double eps, double sigma)
 {
-    double sigma6 = pow(sigma, 6.0);
-    double sr2 = 1.0 / s;
-    double sr6 = sr2 * sr2 * sr2 * sigma6;
-    return 4.0 * eps * (sr6 * sr6 - sr6);
+    double t = sigma * sigma / s;
+    double q = t * t * t;
+    return 4.0 * eps * (q * q - q);
 }
 
 /* d f / d s = -336 eps sigma^12 s^-8 + 96 eps sigma^6 s^-5 */

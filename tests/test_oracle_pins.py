@@ -60,17 +60,19 @@ def test_force_zero_at_potential_minimum():
         assert abs(oracle.pair_force(r * r, 1.0, sigma) * r) < 1e-13
 
 
-def test_force_at_cutoff_and_eq2_equivalence():
-    # Eq. 2 written out: 24 eps (sigma/r)^6 [2 (sigma/r)^6 - 1] / r^2 times x_ij
+def test_force_at_cutoff_and_listing_equivalence():
+    # closed value at the cutoff: |F(2.5)| = 24 (2 * 2.5^-12 - 2.5^-6) / 2.5
     r = 2.5
-    expect = 24.0 * r ** -6 * (2.0 * r ** -6 - 1.0) / r ** 2 * r
-    assert oracle.pair_force(r * r) * r == pytest.approx(expect, rel=1e-14)
     assert oracle.pair_force(r * r) * r == pytest.approx(-0.0389994774528, abs=1e-12)
+    # the oracle follows Eq. 2; the compute_potential example of Sec. 4.2
+    # writes the same factor as 48 sr6 (sr6 - 1/2) sr2 eps with sr2 = 1/s and
+    # sr6 = sr2^3 sigma^6, an algebraically different evaluation
     for s in np.linspace(0.7, 6.5, 37):
         for eps, sig in ((1.0, 1.0), (1.05, 0.98), (0.5, 1.2)):
-            q = (sig * sig / s) ** 3
-            eq2 = 24.0 * eps * q * (2.0 * q - 1.0) / s
-            assert oracle.pair_force(s, eps, sig) == pytest.approx(eq2, rel=1e-13)
+            sr2 = 1.0 / s
+            sr6 = sr2 * sr2 * sr2 * sig ** 6
+            listing = 48.0 * sr6 * (sr6 - 0.5) * sr2 * eps
+            assert oracle.pair_force(s, eps, sig) == pytest.approx(listing, rel=1e-13)
 
 
 def test_force_is_minus_energy_gradient():
@@ -173,6 +175,31 @@ def test_cell_list_equals_all_pairs(case):
     s = (d * d).sum(-1)
     np.fill_diagonal(s, np.inf)
     assert (c1 == (s < 2.8 ** 2).sum(1)).all()
+
+
+@pytest.mark.parametrize("case", ["liquid6", "jitter5", "nc2", "uniform"])
+def test_atom_neighbors_equals_all_pairs(case):
+    """orc_atom_neighbors (the per-atom list checker used at full size) against
+    the cell-list build and an independent numpy all-pairs distance matrix,
+    for every atom of the box."""
+    if case == "liquid6":
+        x, L = _liquid(7)
+    elif case == "jitter5":
+        s = md_system(5, jitter=0.3, seed=7)
+        x, L = s.pos(), s.L
+    elif case == "nc2":
+        x, L = _liquid(4)
+    else:
+        L = 12.0
+        x = _uniform(900, L, 11)
+    c, nb, _ = oracle.build_list(x[:, 0], x[:, 1], x[:, 2], L, 2.8, maxnb=400)
+    d = _mic_np(x[:, None, :] - x[None, :, :], L)
+    s2 = (d * d).sum(-1)
+    np.fill_diagonal(s2, np.inf)
+    for i in range(x.shape[0]):
+        got = oracle.atom_neighbors(x[:, 0], x[:, 1], x[:, 2], L, 2.8, i)
+        assert np.array_equal(got, nb[i, : c[i]]), i
+        assert np.array_equal(got, np.nonzero(s2[i] < 2.8 ** 2)[0]), i
 
 
 # ---------------------------------------------------------------- forces
