@@ -194,3 +194,32 @@ def test_jvp_matches_force_differences():
     u = np.random.default_rng(4).standard_normal(x.shape)
     ju = oracle.jvp(x[:, 0], x[:, 1], x[:, 2], s.L, c, nb, u)
     assert np.sum(u * jw) == pytest.approx(np.sum(ju * w), rel=1e-12)
+
+
+@pytest.mark.slow
+def test_adjoint_workload_rounding_floor():
+    """Bar of the GPU test on the 64 x 4,000-atom adjoint workload (200 steps,
+    rebuild 20, loss against the trajectory at eps = 1.05, sigma = 0.98 from
+    the same start): on replica 0 (seed 3000), moving every start coordinate
+    by one ulp moves x_T by ~1e-13 and the gradients by ~1e-13 relative, so
+    two correct implementations that round differently stay far inside 1e-9
+    over this horizon (no pair crosses the cutoff between the two runs)."""
+    s = md_system(10, 0.8442, 1.0, seed=3000)
+    x0, v0, L, steps = s.pos(), s.vel(), s.L, 200
+    tgt = oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, L, steps, eps=1.05, sigma=0.98, thermo=False)["x"]
+
+    def grads(x):
+        r = oracle.run(x[:, 0], x[:, 1], x[:, 2], v0[:, 0], v0[:, 1], v0[:, 2], L, steps, thermo=False,
+                       hashes=True)
+        d = r["x"] - tgt
+        d -= L * np.round(d / L)
+        return r, oracle.adjoint(x, v0, L, steps, 2 * d, np.zeros_like(d))
+
+    r0, (gx0, _, ge0, gs0) = grads(x0)
+    r1, (gx1, _, ge1, gs1) = grads(np.nextafter(x0, np.inf))
+    assert np.array_equal(r0["hashes"], r1["hashes"])  # same interacting pairs at every step
+    dxT = r1["x"] - r0["x"]
+    assert np.abs(dxT - L * np.round(dxT / L)).max() < 1e-11
+    assert np.abs(gx1 - gx0).max() <= 1e-11 * np.abs(gx0).max()
+    assert ge1 == pytest.approx(ge0, rel=1e-11)
+    assert gs1 == pytest.approx(gs0, rel=1e-11)
