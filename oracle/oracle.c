@@ -50,6 +50,27 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops from here on (timing runs only). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* Wall-clock seconds, for the per-phase times of orc_run. */
+static double wall(void)
+{
+#ifdef _OPENMP
+    return omp_get_wtime();
+#else
+    return 0.0;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Pair terms                                                          */
 /* ------------------------------------------------------------------ */
@@ -263,6 +284,32 @@ long orc_atom_neighbors(int n, const double *x, const double *y, const double *z
 /* ------------------------------------------------------------------ */
 
 /*
+ * Totals over atoms (energy, virial, kinetic energy) are compensated sums
+ * (Neumaier's variant of Kahan summation): the quantities are exact sums
+ * over pairs or atoms, and adding 10^5 to 10^7 similar per-atom terms left
+ * to right drifts from that sum by ~1e-12 relative (on a perfect lattice
+ * every term is the same and the rounding errors add up).
+ */
+typedef struct {
+    double sum, comp;
+} ksum_t;
+
+static void ksum_add(ksum_t *k, double v)
+{
+    double t = k->sum + v;
+    if (fabs(k->sum) >= fabs(v))
+        k->comp += (k->sum - t) + v;
+    else
+        k->comp += (v - t) + k->sum;
+    k->sum = t;
+}
+
+static double ksum_value(const ksum_t *k)
+{
+    return k->sum + k->comp;
+}
+
+/*
  * F_i = sum over j in list(i) (list order) with s < rc^2 of f(s) d_ij.
  * Optionally per-atom scale[i] = sum_j |f(s) d_ij| (the conditioning scale of
  * the sum), total energy and virial (each pair counted once: 1/2 of the
@@ -316,15 +363,15 @@ void orc_forces(int n, const double *x, const double *y, const double *z, double
         ui[i] = u;
         wi[i] = w;
     }
-    double U = 0.0, W = 0.0;
+    ksum_t U = {0.0, 0.0}, W = {0.0, 0.0};
     for (int i = 0; i < n; ++i) {
-        U += ui[i];
-        W += wi[i];
+        ksum_add(&U, ui[i]);
+        ksum_add(&W, wi[i]);
     }
     if (energy)
-        *energy = 0.5 * U;
+        *energy = 0.5 * ksum_value(&U);
     if (virial)
-        *virial = 0.5 * W;
+        *virial = 0.5 * ksum_value(&W);
     free(ui);
     free(wi);
 }
@@ -370,10 +417,10 @@ static double wrap1(double p, double L)
 
 static double kinetic(int n, const double *vx, const double *vy, const double *vz, double mass)
 {
-    double s = 0.0;
+    ksum_t s = {0.0, 0.0};
     for (int i = 0; i < n; ++i)
-        s += vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
-    return 0.5 * mass * s;
+        ksum_add(&s, vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+    return 0.5 * mass * ksum_value(&s);
 }
 
 /* thermo row: KE, T (3N-3 degrees of freedom), U, W, E = KE + U */
@@ -397,14 +444,22 @@ static void thermo_row(double *row, int n, double ke, double u, double w)
  */
 long orc_run(int n, double *x, double *y, double *z, double *vx, double *vy, double *vz, double L, double eps,
              double sigma, double mass, double rc, double skin, double dt, int rebuild_every, int maxnb,
-             int nsteps, double *thermo, double *fx, double *fy, double *fz, uint64_t *hashes)
+             int nsteps, double *thermo, double *fx, double *fy, double *fz, uint64_t *hashes, double *times)
 {
+    /* times (nullable): seconds spent in the force sums, the list builds
+     * and everything else of the loop (the Force / Neigh / Other split of
+     * the paper's Sec. 6 figures) */
     int *count = (int *)malloc(sizeof(int) * (size_t)n);
     int *nbr = (int *)malloc(sizeof(int) * (size_t)n * (size_t)maxnb);
     double h = 0.5 * dt / mass;
     double U, W;
+    double t_force = 0.0, t_neigh = 0.0, t_all = wall(), t0;
+    t0 = wall();
     long maxc = orc_build_list(n, x, y, z, L, rc + skin, maxnb, count, nbr);
+    t_neigh += wall() - t0;
+    t0 = wall();
     orc_forces(n, x, y, z, L, count, nbr, maxnb, eps, sigma, rc, fx, fy, fz, NULL, &U, &W);
+    t_force += wall() - t0;
     if (thermo)
         thermo_row(thermo, n, kinetic(n, vx, vy, vz, mass), U, W);
     if (hashes)
@@ -420,11 +475,15 @@ long orc_run(int n, double *x, double *y, double *z, double *vx, double *vy, dou
             z[i] = wrap1(z[i] + dt * vz[i], L);
         }
         if (rebuild_every > 0 && step % rebuild_every == 0) {
+            t0 = wall();
             long m = orc_build_list(n, x, y, z, L, rc + skin, maxnb, count, nbr);
+            t_neigh += wall() - t0;
             if (m > maxc)
                 maxc = m;
         }
+        t0 = wall();
         orc_forces(n, x, y, z, L, count, nbr, maxnb, eps, sigma, rc, fx, fy, fz, NULL, &U, &W);
+        t_force += wall() - t0;
 #pragma omp parallel for schedule(static)
         for (int i = 0; i < n; ++i) {
             vx[i] = vx[i] + h * fx[i];
@@ -435,6 +494,11 @@ long orc_run(int n, double *x, double *y, double *z, double *vx, double *vy, dou
             thermo_row(thermo + 5 * (size_t)step, n, kinetic(n, vx, vy, vz, mass), U, W);
         if (hashes)
             hashes[step] = pair_hash(x, y, z, L, count, nbr, maxnb, rc, n);
+    }
+    if (times) {
+        times[0] = t_force;
+        times[1] = t_neigh;
+        times[2] = wall() - t_all - t_force - t_neigh;
     }
     free(count);
     free(nbr);

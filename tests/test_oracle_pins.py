@@ -136,6 +136,20 @@ def test_fcc_energy_virial_closed_form():
     assert np.abs(F).max() < 1e-12 * sc.max()
 
 
+@pytest.mark.slow
+def test_fcc_energy_virial_closed_form_at_131k_atoms():
+    """The same lattice sums over 32^3 unit cells: 131,072 equal per-atom
+    terms, whose plain left-to-right total drifts by 2e-12 from the exact
+    sum; the oracle's totals stay within 1e-14 of it."""
+    rho = 0.8442
+    pos, L = fcc_positions(32, rho)
+    c, nb, _ = oracle.build_list(pos[:, 0], pos[:, 1], pos[:, 2], L, 2.8, maxnb=128)
+    _, _, U, W = oracle.forces(pos[:, 0], pos[:, 1], pos[:, 2], L, c, nb)
+    n = pos.shape[0]
+    assert U / n == pytest.approx(-6.773368053252957, rel=1e-14)
+    assert W / n == pytest.approx(-22.158199254035498, rel=1e-14)
+
+
 def _liquid(ncell=6, steps=30, seed=1000, T=1.44, rho=0.8442):
     s = md_system(ncell, rho, T, seed=seed)
     r = oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.L, steps, thermo=False)
