@@ -71,24 +71,50 @@ def _schedule(g) -> dict:
 REBUILD_EVERY = 20  # list rebuild interval of every workload here
 
 
-def _warm_and_tune(g, warmup: int, schedule=None):
-    """Run the warmup steps and fix the schedule, both outside the timed
-    region.  Without a given schedule the autotuner runs after the largest
-    multiple of the rebuild interval within the warmup (a rebuild step, so the
-    fixed rebuild schedule is kept): on the initial lattice every list has the
-    same length, while a few steps later lengths spread as they do in the
-    timed steps, and every wavefront runs to the longest list among its
-    atoms, which changes which schedule is fastest."""
+def _warm_and_tune(g, warmup: int, schedule=None) -> int:
+    """Fix the schedule and run the warmup steps, all outside the timed
+    region; returns the untimed steps run before the warmup.  Without a
+    given schedule, one whole rebuild interval runs first and the autotuner
+    picks the schedule at its end (a rebuild step, so the fixed rebuild
+    schedule is kept), whatever the warmup: on the initial lattice every list
+    has the same length, while a few steps later lengths spread as they do
+    in the timed steps, and every wavefront runs to the longest list among
+    its atoms, which changes which schedule is fastest."""
     if schedule:  # fixed schedule, e.g. for profiling runs
         g.set_schedule(**schedule)
         g.integrate(warmup)
-        return
-    k = warmup // REBUILD_EVERY * REBUILD_EVERY
-    if k:
-        g.integrate(k)
+        return 0
+    g.integrate(REBUILD_EVERY)
     g.autotune(repeats=5)
-    if warmup > k:
-        g.integrate(warmup - k)
+    g.integrate(warmup)
+    return REBUILD_EVERY
+
+
+# Issue rate of unfused FP64 vector instructions (add, mul, compare): 256
+# CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz.  The 78.6 TFLOP/s FP64
+# vector peak counts a fused multiply-add as two operations of this rate.
+FP64_ISSUE_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def _force_roofline(n: int, mean_list: float, avg_s: float, traffic=None, kernel="") -> dict:
+    """Force kernel against the HBM roofline at the algorithmic bytes per
+    atom of the force sum: count 4 + list 4 n_list + x_i 24 + F_i 24 (each
+    neighbor position counted once, gathered from LDS or cache).  The kernel
+    fuses the kicks and the drift, so its own traffic replaces the force
+    write by the velocity read and write and the drifted position write
+    (100 + 4 n_list); that figure is reported beside it."""
+    alg = (52.0 + 4.0 * mean_list) * n
+    fused = (100.0 + 4.0 * mean_list) * n
+    out = {"bound": "hbm", "kernel": kernel, "achieved": alg / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": alg / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+           "alg_bytes_per_atom": 52.0 + 4.0 * mean_list, "alg_bytes_per_launch": alg,
+           "avg_launch_us": avg_s * 1e6,
+           "fused_kernel": {"bytes_per_atom": 100.0 + 4.0 * mean_list, "achieved": fused / avg_s / 1e9,
+                            "frac": fused / avg_s / 1e9 / HBM_PEAK_GBS}}
+    if traffic:
+        out["traffic_frac"] = traffic / avg_s / 1e9 / HBM_PEAK_GBS
+    out.update(_force_flops(n, mean_list, avg_s))
+    return out
 
 
 def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int) -> dict:
@@ -99,9 +125,11 @@ def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int) -> dict:
     28; the permutation reads x, v and id and writes them, 52 + 52).  The
     list build reads x (24) and writes the count (4) and the list (4 bytes
     per entry at the method's index width) and tests 27 cells' worth of
-    candidates per atom, 8 FP64 operations each (3 differences, 3 squares,
-    2 sums): it is bound by FP64 issue, so its fraction is taken against the
-    FP64 vector peak, with the HBM fraction beside it."""
+    candidates per atom, 8 unfused FP64 instructions each (3 differences, 3
+    squares, 2 sums, no fused multiply-add so that its decisions match any
+    IEEE evaluation): it is bound by FP64 instruction issue, so its fraction
+    is taken against the issue rate of unfused FP64 instructions, with the
+    HBM fraction beside it."""
     out = {}
     if tm.get("binning", (0, 0))[1]:
         ms, calls = tm["binning"]
@@ -114,11 +142,11 @@ def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int) -> dict:
         t = ms / calls * 1e-3
         b = (28.0 + 4.0 * mean_list) * n
         cand = 27.0 * n / n_cells
-        fl = 8.0 * cand * n
-        out["neighbor"] = {"bound": "alu", "achieved": fl / t / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": fl / t / 1e12 / FP64_PEAK_TFLOPS, "candidates_per_atom": cand,
-                           "hbm_achieved_gbs": b / t / 1e9, "hbm_frac": b / t / 1e9 / HBM_PEAK_GBS,
-                           "alg_bytes_per_call": b, "avg_call_us": t * 1e6}
+        ops = 8.0 * cand * n
+        out["neighbor"] = {"bound": "alu", "achieved": ops / t / 1e12, "peak": FP64_ISSUE_PEAK_T,
+                           "unit": "T FP64 instr/s", "frac": ops / t / 1e12 / FP64_ISSUE_PEAK_T,
+                           "candidates_per_atom": cand, "hbm_achieved_gbs": b / t / 1e9,
+                           "hbm_frac": b / t / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_call": b, "avg_call_us": t * 1e6}
     return out
 
 
@@ -143,7 +171,7 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     s = md_system(w["ncell"], w["rho"], w["T"], seed=w["seed"], jitter=w["jitter"])
     g = System(s.n, s.L, max_neighbors=128)
     g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
-    _warm_and_tune(g, warmup, schedule)
+    tuning_steps = _warm_and_tune(g, warmup, schedule)
     g.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -165,34 +193,19 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     g.sync()
     ms, launches = tm["force"]
     avg_s = ms / max(launches, 1) * 1e-3
-    # algorithmic bytes of the fused force + kick + drift kernel per atom:
-    # count 4 + list 4*n_list + x_i 24 + v read 24 + v write 24 + x_new 24
-    bytes_per_atom = 100.0 + 4.0 * mean_list
-    alg_bytes = bytes_per_atom * s.n
-    achieved = alg_bytes / avg_s / 1e9
-    traffic = _traffic(workload)
     res = {
         "n": s.n,
         "steps": steps,
         "warmup": warmup,
+        "tuning_steps": tuning_steps,
         "elapsed_s": elapsed,
         "value": s.n * steps / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
         "mean_list_length": mean_list,
         "schedule": _schedule(g),
         "kernel_ms": {k: (v[0] / max(v[1], 1), v[1]) for k, v in tm.items() if v[1]},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_force<2,false>: LDS-staged block force + kick + kick + drift",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "alg_bytes_per_launch": alg_bytes,
-            "avg_launch_us": avg_s * 1e6,
-            **_force_flops(s.n, mean_list, avg_s),
-        },
+        "roofline": _force_roofline(s.n, mean_list, avg_s, _traffic(workload),
+                                    "k_force<2,false>: LDS-staged block force + kick + kick + drift"),
         "build_rooflines": _build_rooflines(tm, s.n, mean_list, n_cells),
     }
     g.close()
@@ -229,7 +242,19 @@ def run_batched(steps: int = 200, warmup: int = 20, n_boxes: int = 512):
     t_batch = time.perf_counter() - t0
     g.sync()
     info = g.info()
+    # kernel timing pass (eager: timing keeps graph mode off)
+    g.set_timing(True)
+    g.integrate(steps)
+    g.sync()
+    tm = g.get_timing()
+    g.set_timing(False)
+    mean_list = float(g.neighbor_counts().double().mean().item())
+    g.sync()
     g.close()
+    ms, launches = tm["force"]
+    roof = _force_roofline(total, mean_list, ms / max(launches, 1) * 1e-3,
+                           kernel="k_force<2,false>: one launch over every box's blocks")
+    brf = _build_rooflines(tm, total, mean_list, int(info["n_cells"]))
     seq = []
     for b in boxes:
         s = System(b.n, b.L, max_neighbors=128)
@@ -252,7 +277,8 @@ def run_batched(steps: int = 200, warmup: int = 20, n_boxes: int = 512):
             "sequential_ms_per_step": t_seq / steps * 1e3, "speedup_vs_sequential": t_seq / t_batch,
             "schedule": sched, "n_blocks": info["n_blocks"], "lds_atoms": info["lds_atoms"],
             "graph_captures_in_warmup": captured, "graph_launches": info["graph_launches"],
-            "graph_captures": info["graph_captures"]}
+            "graph_captures": info["graph_captures"], "mean_list_length": mean_list, "roofline": roof,
+            "build_rooflines": brf, "kernel_avg_ms": {k: (v[0] / max(v[1], 1), v[1]) for k, v in tm.items() if v[1]}}
 
 
 def run_adjoint(steps: int = 200, replicas: int = 64):
@@ -293,28 +319,71 @@ def run_adjoint(steps: int = 200, replicas: int = 64):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         g.sync()
+    # reverse-kernel timing: one more forward + backward with HIP events
+    g.set_state(x0, v0)
+    g.adjoint_forward(steps)
+    g.set_timing(True)
+    g.adjoint_backward(lam)
+    g.sync()
+    tm = g.get_timing()
+    g.set_timing(False)
+    mean_list = float(g.neighbor_counts().double().mean().item())
+    g.sync()
     g.close()
+    ms, launches = tm["adjoint"]
+    avg_s = ms / max(launches, 1) * 1e-3
+    # algorithmic bytes per atom of the Hessian-vector product: count 4 + list
+    # 4 n_list + x_i and w_i 48 + output 24 (neighbor x_j, w_j from LDS/cache)
+    hvp_b = (76.0 + 4.0 * mean_list) * total
+    hvp = {"bound": "hbm", "kernel": "k_hvp: Hessian-vector product + parameter partials + drift adjoint",
+           "achieved": hvp_b / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": hvp_b / avg_s / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_atom": 76.0 + 4.0 * mean_list,
+           "avg_launch_us": avg_s * 1e6, "launches": launches}
     return {"workload": f"{replicas} x LJ FCC 10^3 = {total:,} atoms, rho 0.8442, T 1.0, {steps} steps, "
                         "checkpoints at every rebuild (20)",
             "value": total * steps / (t2 - t0), "unit": "atom-steps/s (forward + reverse per step)",
             "plain_value": total * steps / t_plain, "adjoint_over_plain_time": (t2 - t0) / t_plain,
             "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3, "plain_ms": t_plain * 1e3,
-            "schedule": sched}
+            "schedule": sched, "hvp_roofline": hvp}
 
 
-def run_cpu_baseline(workload: str, sample_steps: int):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(workload: str, sample_steps: int, single_steps: int):
+    """The oracle on a bounded sample of the workload: OpenMP over atoms on
+    the host's threads, then on one thread (the paper's single-core
+    protocol), with its time split into force sums, list builds and the rest
+    (the Force / Neigh / Other split of the paper's Sec. 6 figures)."""
     import oracle
     from workloads import md_system
 
     w = WORKLOADS[workload]
     s = md_system(w["ncell"], w["rho"], w["T"], seed=w["seed"], jitter=w["jitter"])
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
-    oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.L, sample_steps, thermo=False)
+    r = oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.L, sample_steps, thermo=False, maxnb=128)
     dt = time.perf_counter() - t0
-    return {"value": s.n * sample_steps / dt, "unit": "atom-steps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    r1 = oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.L, single_steps, thermo=False, maxnb=128)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    return {"value": s.n * sample_steps / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": _cpu_model(),
             "sample": f"{w['name']}: first {sample_steps} steps (initial list build + {sample_steps // 20} "
-                      f"rebuilds), OpenMP over atoms, {dt:.1f} s"}
+                      f"rebuilds), OpenMP over atoms on {threads} threads, {dt:.1f} s",
+            "split_s": r["times"],
+            "single_thread": {"value": s.n * single_steps / dt1, "unit": "atom-steps/s", "cores": 1,
+                              "sample": f"first {single_steps} steps on one thread, {dt1:.1f} s",
+                              "split_s": r1["times"]}}
 
 
 def main():
@@ -326,6 +395,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3.5M-atom secondary workload")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-single-steps", type=int, default=40)
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule for the primary workload: block edge, workgroups per block, lanes per "
                          "atom, force threads[, build threads[, build lanes]], e.g. 3,1,1,640 (default: autotune)")
@@ -368,6 +438,7 @@ def main():
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
+        "tuning_steps": prim["tuning_steps"],
         "ms_per_step": prim["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -399,7 +470,7 @@ def main():
               "time", file=sys.stderr, flush=True)
         out["secondary"]["adjoint"] = adj
     if not args.no_cpu:
-        out["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_steps)
+        out["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_steps, args.cpu_single_steps)
     print(json.dumps(out), flush=True)
 
 

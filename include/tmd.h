@@ -98,6 +98,7 @@ enum {
     TMD_T_DRIFT,     /* stand-alone kick + drift (first step of an integrate call) */
     TMD_T_THERMO,    /* deterministic reductions of energy, virial and kinetic energy */
     TMD_T_COPY,      /* state load/unload between original and internal order */
+    TMD_T_ADJOINT,   /* reverse kernel of the adjoint (Hessian-vector product, drift adjoint) */
     TMD_T_COUNT
 };
 

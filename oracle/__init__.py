@@ -38,6 +38,8 @@ def _load():
         lib.orc_cells_per_axis.restype = _I
         lib.orc_cells_per_axis.argtypes = [_D, _D]
         lib.orc_num_threads.restype = _I
+        lib.orc_set_threads.restype = None
+        lib.orc_set_threads.argtypes = [_I]
         for name in ("orc_build_list", "orc_build_list_brute"):
             f = getattr(lib, name)
             f.restype = _L
@@ -49,7 +51,8 @@ def _load():
         lib.orc_atom_force.restype = None
         lib.orc_atom_force.argtypes = [_I, _P, _P, _P, _D, _I, _D, _D, _D, _P, _P]
         lib.orc_run.restype = _L
-        lib.orc_run.argtypes = [_I, _P, _P, _P, _P, _P, _P, _D, _D, _D, _D, _D, _D, _D, _I, _I, _I, _P, _P, _P, _P, _P]
+        lib.orc_run.argtypes = [_I, _P, _P, _P, _P, _P, _P, _D, _D, _D, _D, _D, _D, _D, _I, _I, _I, _P, _P, _P, _P, _P,
+                                _P]
         lib.orc_jvp.restype = None
         lib.orc_jvp.argtypes = [_I, _P, _P, _P, _D, _P, _P, _I, _D, _D, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
         lib.orc_adjoint.restype = _L
@@ -72,6 +75,11 @@ def _ptr(a):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (for timing runs)."""
+    _load().orc_set_threads(int(n))
 
 
 def pair_force(s: float, eps: float = 1.0, sigma: float = 1.0) -> float:
@@ -138,21 +146,23 @@ def atom_force(x, y, z, L, i, eps=1.0, sigma=1.0, rc=2.5):
 
 def run(x, y, z, vx, vy, vz, L, nsteps, eps=1.0, sigma=1.0, mass=1.0, rc=2.5, skin=0.3, dt=0.005,
         rebuild_every=20, maxnb=160, thermo=True, hashes=False):
-    """Velocity Verlet; returns dict(x, v, f, thermo[nsteps+1, 5], maxc, hashes).
+    """Velocity Verlet; returns dict(x, v, f, thermo[nsteps+1, 5], maxc, hashes, times).
 
-    hashes[k] identifies the set of interacting pairs (s < rc^2) at step k."""
+    hashes[k] identifies the set of interacting pairs (s < rc^2) at step k;
+    times = seconds in the force sums, the list builds and the rest."""
     st = [_f64(a).copy() for a in (x, y, z, vx, vy, vz)]
     n = st[0].shape[0]
     f = np.zeros((3, n))
     th = np.zeros((nsteps + 1, 5)) if thermo else None
     hs = np.zeros(nsteps + 1, dtype=np.uint64) if hashes else None
+    tm = np.zeros(3)
     m = _load().orc_run(n, *[_ptr(a) for a in st], L, eps, sigma, mass, rc, skin, dt, rebuild_every, maxnb,
                         nsteps, _ptr(th) if thermo else None, _ptr(f[0]), _ptr(f[1]), _ptr(f[2]),
-                        _ptr(hs) if hashes else None)
+                        _ptr(hs) if hashes else None, _ptr(tm))
     if m > maxnb:
         raise ValueError(f"neighbor list overflow: {m} > {maxnb}")
     return {"x": np.stack(st[:3], 1), "v": np.stack(st[3:], 1), "f": f.T.copy(), "thermo": th, "maxc": int(m),
-            "hashes": hs}
+            "hashes": hs, "times": {"force": float(tm[0]), "neigh": float(tm[1]), "other": float(tm[2])}}
 
 
 def jvp(x, y, z, L, count, nbr, w, eps=1.0, sigma=1.0, rc=2.5, a=None):

@@ -23,7 +23,7 @@ TMD_ENONFINITE = -5
 TMD_EWORKSPACE = -6
 TMD_EHIP = -7
 
-TIMING_CLASSES = ("force", "neighbor", "binning", "drift", "thermo", "copy")
+TIMING_CLASSES = ("force", "neighbor", "binning", "drift", "thermo", "copy", "adjoint")
 
 
 class TmdParams(C.Structure):

@@ -9,8 +9,8 @@
 #include <string.h>
 
 #include <algorithm>
-#include <new>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -77,7 +77,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kMaxCap = 4096;       // atoms staged per block neighborhood (96 KB of LDS at most)
 constexpr int kLdsPerCu = 163840;   // gfx950: 160 KB of LDS per compute unit
-constexpr int kStaticLds = 1536;    // static LDS of a block kernel (neighborhood tables, reductions), rounded up
+constexpr int kStaticLds = kBlockStaticLds;  // static LDS of a block kernel (neighborhood tables, reductions)
 static_assert(kForceLdsTail <= kStaticLds, "the force kernel's table and scratch fit the static LDS allowance");
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -289,11 +289,14 @@ double expected_hood_atoms(const Box &B, int E) {
 // still holds at least 15% more atoms than the largest mean neighborhood
 // population (liquid density fluctuations over ~1000 atoms are a few
 // percent; rarer blocks fall back to global gathers), threads the mean block
-// population rounded up to whole wavefronts.  Returns false when the cell slots overflow int32.
-bool layout_blocks(tmd_system *s, int E) {
+// population rounded up to whole wavefronts.  Fills the block fields of the
+// `nbox` descriptors and the Dims fields that follow from them.  Returns
+// false when the cell slots overflow int32.
+bool layout_dims(Box *boxes, int32_t nbox, int E, Dims &d) {
     int64_t blocks = 0;
     double worst = 0.0;
-    for (Box &B : s->boxes) {
+    for (int32_t k = 0; k < nbox; ++k) {
+        Box &B = boxes[k];
         B.edge = E;
         B.nbx = (B.nc + E - 1) / E;
         B.nblocks = B.nbx * B.nbx * B.nbx;
@@ -304,7 +307,6 @@ bool layout_blocks(tmd_system *s, int E) {
         if (blocks * E * E * E > INT32_MAX / 2)
             return false;
     }
-    Dims &d = s->d;
     d.edge = E;
     d.cpb = E * E * E;
     d.nblk = int32_t(blocks);
@@ -329,7 +331,14 @@ bool layout_blocks(tmd_system *s, int E) {
         d.blanes = 1;
     d.threads = default_threads(d, d.lpa);
     d.bthreads = default_threads(d, d.blanes);
-    s->blk_box.assign(size_t(blocks), 0);
+    return true;
+}
+
+bool layout_blocks(tmd_system *s, int E) {
+    Dims &d = s->d;
+    if (!layout_dims(s->boxes.data(), d.nbox, E, d))
+        return false;
+    s->blk_box.assign(size_t(d.nblk), 0);
     for (int32_t k = 0; k < d.nbox; ++k) {
         const Box &B = s->boxes[size_t(k)];
         std::fill(s->blk_box.begin() + B.block_off, s->blk_box.begin() + B.block_off + B.nblocks, k);
@@ -341,13 +350,47 @@ bool layout_blocks(tmd_system *s, int E) {
 }
 
 // Default block edge: 3 when that still gives every CU several blocks.
-int default_edge(tmd_system *s) {
+int default_edge(const Box *boxes, int32_t nbox) {
     int64_t b3 = 0;
-    for (const Box &B : s->boxes) {
-        const int64_t n = (B.nc + 2) / 3;
+    for (int32_t k = 0; k < nbox; ++k) {
+        const int64_t n = (boxes[k].nc + 2) / 3;
         b3 += n * n * n;
     }
     return b3 >= 4 * 256 ? 3 : 2;
+}
+
+// Check one box's parameters (the argument rules of tmd_create) and fill
+// its descriptor; its atoms start at slot atom_off of the concatenated arrays.
+tmd_status make_box(const tmd_params &p, int64_t n, double L, int64_t atom_off, Box &B) {
+    if (n <= 0 || n > INT32_MAX)
+        return TMD_EINVAL;
+    if (!positive(p.epsilon) || !positive(p.sigma) || !positive(p.mass) || !positive(p.cutoff) ||
+        !positive(p.dt) || !positive(L) || !isfinite(p.skin) || p.skin < 0.0)
+        return TMD_EINVAL;
+    if (p.rebuild_every < 1 || p.max_neighbors < 1 || p.max_neighbors > 4096)
+        return TMD_EINVAL;
+    const double r = p.cutoff + p.skin;
+    if (!(r < 0.5 * L))
+        return TMD_EBOX;
+    const double ncd = floor(L / r);
+    if (ncd > 1290.0)
+        return TMD_EINVAL;
+    B = Box{};
+    B.atom_off = int32_t(atom_off);
+    B.n = int32_t(n);
+    B.nc = int32_t(ncd);  // >= 2 because r < L/2
+    B.L = L;
+    B.halfL = 0.5 * L;
+    B.halfL2 = B.halfL * B.halfL;
+    B.invL = 1.0 / L;
+    B.side = L / B.nc;
+    B.rc2 = p.cutoff * p.cutoff;
+    B.rl2 = r * r;
+    set_lj(B, p.epsilon, p.sigma);
+    B.h = 0.5 * p.dt / p.mass;
+    B.dt = p.dt;
+    B.mass = p.mass;
+    return TMD_OK;
 }
 
 tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengths, const tmd_params *params,
@@ -366,39 +409,12 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
     }
     for (int32_t k = 0; k < nbox; ++k) {
         const tmd_params &p = params[k];
-        const double L = lengths[k];
-        const int64_t n = n_atoms[k];
-        if (n <= 0 || n > INT32_MAX)
-            return TMD_EINVAL;
-        if (!positive(p.epsilon) || !positive(p.sigma) || !positive(p.mass) || !positive(p.cutoff) ||
-            !positive(p.dt) || !positive(L) || !isfinite(p.skin) || p.skin < 0.0)
-            return TMD_EINVAL;
-        if (p.rebuild_every < 1 || p.max_neighbors < 1 || p.max_neighbors > 4096)
-            return TMD_EINVAL;
         if (p.rebuild_every != params[0].rebuild_every || p.max_neighbors != params[0].max_neighbors)
             return TMD_EINVAL;
-        const double r = p.cutoff + p.skin;
-        if (!(r < 0.5 * L))
-            return TMD_EBOX;
-        const double ncd = floor(L / r);
-        if (ncd > 1290.0)
-            return TMD_EINVAL;
-        Box &B = boxes[size_t(k)];
-        B.atom_off = int32_t(total);
-        B.n = int32_t(n);
-        B.nc = int32_t(ncd);  // >= 2 because r < L/2
-        B.L = L;
-        B.halfL = 0.5 * L;
-        B.halfL2 = B.halfL * B.halfL;
-        B.invL = 1.0 / L;
-        B.side = L / B.nc;
-        B.rc2 = p.cutoff * p.cutoff;
-        B.rl2 = r * r;
-        set_lj(B, p.epsilon, p.sigma);
-        B.h = 0.5 * p.dt / p.mass;
-        B.dt = p.dt;
-        B.mass = p.mass;
-        total += n;
+        const tmd_status st = make_box(p, n_atoms[k], lengths[k], total, boxes[size_t(k)]);
+        if (st != TMD_OK)
+            return st;
+        total += n_atoms[k];
         if (total > INT32_MAX - 256)
             return TMD_EINVAL;
     }
@@ -436,7 +452,7 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
         big.nblk = std::max(big.nblk, d.nblk);
         big.ncs = std::max(big.ncs, d.ncs);
         s->dmax = big;
-        const int E = default_edge(s);
+        const int E = default_edge(s->boxes.data(), nbox);
         if (E != 2)
             layout_blocks(s, E);
         s->ws_need = carve(s->dmax, nullptr, nullptr);
@@ -487,6 +503,26 @@ size_t carve_adj(const Dims &d, int32_t R, int32_t nsteps, char *base, AdjBuf *o
     return off;
 }
 
+// Per-workgroup LDS limit of the current device.
+hipError_t device_lds_limit(int &max_lds) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    return e;
+}
+
+// The adjoint kernel stages 48 bytes per atom (twice the 24 of the other
+// block kernels): lower the capacity until its copy plus the static LDS of
+// a block kernel fit the device's per-workgroup limit.  True if lowered.
+bool fit_cap(Dims &d, int max_lds) {
+    if (2 * hood_lds_bytes(d.cap) + size_t(kStaticLds) <= size_t(max_lds))
+        return false;
+    const int fit = int((size_t(max_lds) - size_t(kStaticLds)) / 48) - 2 - kHoodPad;
+    d.cap = std::max(64, fit / 64 * 64);
+    return true;
+}
+
 tmd_status upload_tables(tmd_system *s, hipStream_t hs) {
     hipError_t e = hipMemcpyAsync(s->b.boxes, s->boxes.data(), s->boxes.size() * sizeof(Box), hipMemcpyHostToDevice,
                                   hs);
@@ -497,19 +533,12 @@ tmd_status upload_tables(tmd_system *s, hipStream_t hs) {
     if (e == hipSuccess)
         s->tables_dirty = false;
     if (e == hipSuccess && !s->prepared) {
-        // the adjoint kernel stages 48 bytes per atom: keep within the
-        // device's per-workgroup LDS limit (static LDS needs < 1 KB)
-        int dev = 0, max_lds = 0;
-        e = hipGetDevice(&dev);
-        if (e == hipSuccess)
-            e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        if (e == hipSuccess && 2 * hood_lds_bytes(s->d.cap) + 1024 > size_t(max_lds)) {
-            const int fit = int((size_t(max_lds) - 1024) / 48) - 1;
-            s->d.cap = std::max(64, fit / 64 * 64);
+        int max_lds = 0;
+        e = device_lds_limit(max_lds);
+        if (e == hipSuccess && fit_cap(s->d, max_lds))
             s->list_valid = s->force_valid = false;
-        }
         if (e == hipSuccess)
-            e = prepare_kernels(s->d);
+            e = prepare_kernels(max_lds - kStaticLds);
         s->prepared = (e == hipSuccess);
     }
     return e == hipSuccess ? TMD_OK : hip_fail(s, e, "table upload");
@@ -1164,8 +1193,10 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
     double *const lo_v[3] = {a.lo + 3 * nt, a.lo + 4 * nt, a.lo + 5 * nt};
     Pos wa = a.wa, wb = a.wb;
     auto hvp = [&](const Pos &x, double mult, bool drift_adj) {
-        if (e == hipSuccess)
+        if (e == hipSuccess) {
+            Timed t(s, TMD_T_ADJOINT, hs);
             e = launch_hvp(s->d, b, x, wa, a.lx, wb, mult, drift_adj, a.partials, hs);
+        }
         if (e == hipSuccess)
             e = launch_grad_reduce(s->d, b, a.partials, mult, a.acc, hs);
         if (drift_adj)

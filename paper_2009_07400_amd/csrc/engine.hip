@@ -1645,8 +1645,12 @@ __global__ void k_split_pairs(const double *__restrict__ acc, int n, double *a, 
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t prepare_kernels(const Dims &d) {
-    const int bytes = int(hood_lds_bytes(d.cap));
+// Static LDS of the block kernels: the build and the export keep a Hood
+// table, the reverse kernel a Hood table and block_sum3's scratch.
+static_assert(sizeof(Hood) + 3 * (kMaxThreads / 64) * sizeof(double) <= kBlockStaticLds,
+              "static LDS of the block kernels");
+
+hipError_t prepare_kernels(int dyn_bytes) {
     const void *fns[] = {
         reinterpret_cast<const void *>(&k_build<1>),
         reinterpret_cast<const void *>(&k_build<2>),
@@ -1668,19 +1672,12 @@ hipError_t prepare_kernels(const Dims &d) {
         reinterpret_cast<const void *>(&k_force<1, true, 4>),
         reinterpret_cast<const void *>(&k_force<2, false, 4>),
         reinterpret_cast<const void *>(&k_force<2, true, 4>),
+        reinterpret_cast<const void *>(&k_hvp<1>),
+        reinterpret_cast<const void *>(&k_hvp<2>),
+        reinterpret_cast<const void *>(&k_hvp<4>),
     };
     for (const void *f : fns) {
-        // the force kernels add their table and scratch to the dynamic LDS
-        const bool build = f == reinterpret_cast<const void *>(&k_build<1>) ||
-                           f == reinterpret_cast<const void *>(&k_build<2>);
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           build ? bytes : int(force_lds_bytes(d.cap)));
-        if (e != hipSuccess)
-            return e;
-    }
-    for (const void *f : {reinterpret_cast<const void *>(&k_hvp<1>), reinterpret_cast<const void *>(&k_hvp<2>),
-                          reinterpret_cast<const void *>(&k_hvp<4>)}) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * bytes);
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_bytes);
         if (e != hipSuccess)
             return e;
     }

@@ -141,8 +141,14 @@ inline size_t hood_lds_bytes(int cap) { return size_t(cap + 2 + kHoodPad) * 3 * 
 constexpr int kForceLdsTail = 1536;
 inline size_t force_lds_bytes(int cap) { return hood_lds_bytes(cap) + kForceLdsTail; }
 
+// Upper bound of the static LDS any block kernel declares (neighborhood
+// table, reduction scratch); engine.hip checks its kernels against it.
+constexpr int kBlockStaticLds = 1536;
+
 // Launchers (engine.hip).  All enqueue on `s` and return the launch status.
-hipError_t prepare_kernels(const Dims &d);
+// Allow every block kernel up to dyn_bytes of dynamic LDS on the current
+// device (the device's per-workgroup limit less kBlockStaticLds).
+hipError_t prepare_kernels(int dyn_bytes);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_load_state(const Dims &d, const double *const pos[3], const double *const vel[3], Buffers &b,
                              Cursor c, hipStream_t s);

@@ -30,10 +30,12 @@ def test_build_rooflines_arithmetic():
     assert r["binning"]["achieved"] == pytest.approx(132.0 * n / 80e-6 / 1e9)
     assert r["binning"]["frac"] == pytest.approx(r["binning"]["achieved"] / 8000.0)
     nb = r["neighbor"]
-    assert nb["bound"] == "alu" and nb["unit"] == "TFLOP/s"
+    assert nb["bound"] == "alu" and nb["unit"] == "T FP64 instr/s"
     assert nb["candidates_per_atom"] == pytest.approx(27.0 * n / n_cells)
     assert nb["achieved"] == pytest.approx(8.0 * 27.0 * n / n_cells * n / 2e-3 / 1e12)
-    assert nb["frac"] == pytest.approx(nb["achieved"] / 78.6)
+    # unfused FP64 instructions issue at 256 CUs x 64 lanes x 2.4 GHz = 39.32 T/s
+    assert nb["peak"] == pytest.approx(39.3216)
+    assert nb["frac"] == pytest.approx(nb["achieved"] / 39.3216)
     assert nb["alg_bytes_per_call"] == pytest.approx((28.0 + 4.0 * mean_list) * n)
     assert nb["hbm_frac"] == pytest.approx(nb["hbm_achieved_gbs"] / 8000.0)
 
@@ -45,6 +47,18 @@ def test_force_flops_arithmetic():
     assert r["fp64_flops_per_launch"] == pytest.approx((8 * 75.0 + 15 * n_int) * 1000)
     assert r["fp64_tflops"] == pytest.approx(r["fp64_flops_per_launch"] / 1e-3 / 1e12)
     assert r["fp64_frac"] == pytest.approx(r["fp64_tflops"] / 78.6)
+
+
+def test_force_roofline_counts_the_force_sum_bytes():
+    b = _bench()
+    r = b._force_roofline(1000, 75.0, 1e-3, traffic=4.0e5)
+    # count 4 + list 4 n + x_i 24 + F_i 24 per atom; the fused kernel's own
+    # 100 + 4 n beside it
+    assert r["alg_bytes_per_atom"] == pytest.approx(352.0)
+    assert r["achieved"] == pytest.approx(352.0 * 1000 / 1e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    assert r["fused_kernel"]["bytes_per_atom"] == pytest.approx(400.0)
+    assert r["traffic_frac"] == pytest.approx(4.0e5 / 1e-3 / 1e9 / 8000.0)
 
 
 def test_build_rooflines_skip_kernels_not_run():

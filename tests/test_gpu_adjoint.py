@@ -250,8 +250,7 @@ def test_gpu_gradients_against_central_differences():
             kp, km = ({"eps": 1 + h}, {"eps": 1 - h}) if what == "eps" else ({"sigma": 1 + h}, {"sigma": 1 - h})
             if np.any(_flips(s, steps, **kp) != _flips(s, steps, **km)):
                 continue
-            fd = (_gpu_loss(s, steps, tgt, **{("epsilon" if what == "eps" else "sigma"): 1 + h})
-                  - _gpu_loss(s, steps, tgt, **{("epsilon" if what == "eps" else "sigma"): 1 - h})) / (2 * h)
+            fd = (_gpu_loss(s, steps, tgt, **kp) - _gpu_loss(s, steps, tgt, **km)) / (2 * h)
             g = ge if what == "eps" else gs
             assert g == pytest.approx(fd, rel=1e-7), what
             checked.append((what, abs(g - fd) / abs(fd)))
