@@ -322,13 +322,14 @@ def run_adjoint(steps: int = 200, replicas: int = 64):
     # reverse-kernel timing: one more forward + backward with HIP events
     g.set_state(x0, v0)
     g.adjoint_forward(steps)
+    # list of the recorded run's last interval (the backward pass leaves the
+    # state but not a valid list)
+    mean_list = float(g.neighbor_counts().double().mean().item())
     g.set_timing(True)
     g.adjoint_backward(lam)
     g.sync()
     tm = g.get_timing()
     g.set_timing(False)
-    mean_list = float(g.neighbor_counts().double().mean().item())
-    g.sync()
     g.close()
     ms, launches = tm["adjoint"]
     avg_s = ms / max(launches, 1) * 1e-3
@@ -394,8 +395,9 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c1")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3.5M-atom secondary workload")
-    ap.add_argument("--cpu-steps", type=int, default=100)
-    ap.add_argument("--cpu-single-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=1000,
+                    help="oracle steps on all host threads (default: the whole 1000-step workload)")
+    ap.add_argument("--cpu-single-steps", type=int, default=100, help="oracle steps on one thread")
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule for the primary workload: block edge, workgroups per block, lanes per "
                          "atom, force threads[, build threads[, build lanes]], e.g. 3,1,1,640 (default: autotune)")
