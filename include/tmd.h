@@ -310,6 +310,37 @@ tmd_status tmd_get_timing(tmd_system *sys, double *ms, int64_t *launches);
  * memsets and no host work. */
 tmd_status tmd_set_graphs(tmd_system *sys, int32_t enable);
 
+/* --- One call that allocates nothing ------------------------------------
+ * For callers that cannot allocate device memory or bind a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Equivalent to tmd_create + tmd_bind_workspace +
+ * tmd_set_state (zero velocities) + tmd_build_neighbors +
+ * tmd_compute_forces + tmd_sync's status, at the default schedule, with
+ * bitwise the same forces, energy and virial, but every intermediate
+ * (cells, sorted state, neighbor list, block partials, error word) lives in
+ * one library-owned device array of TMD_STATIC_SCRATCH_BYTES per GPU.
+ * params, n_atoms, box_length: as tmd_create (same synchronous errors).
+ * pos[3]: device arrays of n_atoms doubles (original order), read on stream.
+ * f[3] (nullable, any component nullable): device arrays receiving F.
+ * energy_virial (nullable, device, 2 doubles): U and W as tmd_compute_forces.
+ * device_status (nullable, device, 2 int32): [0] the status tmd_sync would
+ * return for the device-detected conditions (TMD_OK, TMD_ENBR_OVERFLOW,
+ * TMD_ENONFINITE, TMD_EINVAL for a coordinate outside [-L, 2L)), [1] the
+ * largest list length requested on overflow; written on stream.
+ * Returns TMD_EWORKSPACE, before touching the GPU, when the system's
+ * workspace (tmd_workspace_size of the same system at one block edge)
+ * exceeds TMD_STATIC_SCRATCH_BYTES: about 90,000 atoms at max_neighbors =
+ * 128 and liquid density.  The first call on a device looks up that
+ * device's copy of the array and sets kernel attributes (no allocation);
+ * make it outside any stream capture.  Calls on the same GPU share its one
+ * array: calls that overlap (other streams, other threads) race and must be
+ * serialised by the caller; a later call overwrites the earlier one's
+ * intermediates (outputs are the caller's and are not touched again). */
+#define TMD_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+tmd_status tmd_compute_forces_static(const tmd_params *params, int64_t n_atoms, double box_length,
+                                     const double *const pos[3], double *const f[3], double *energy_virial,
+                                     int32_t *device_status, tmd_stream stream);
+
 /* Static description of a status code. */
 const char *tmd_status_string(tmd_status status);
 

@@ -11,6 +11,6 @@ the built library.
 from . import _abi  # noqa: F401
 from ._abi import TmdError, TmdParams, load_library  # noqa: F401
 from .autograd import LJMDFunction, lj_md  # noqa: F401
-from .system import System, make_params  # noqa: F401
+from .system import System, compute_forces_static, make_params  # noqa: F401
 
-__all__ = ["System", "make_params", "TmdError", "TmdParams", "load_library", "LJMDFunction", "lj_md"]
+__all__ = ["System", "compute_forces_static", "make_params", "TmdError", "TmdParams", "load_library", "LJMDFunction", "lj_md"]

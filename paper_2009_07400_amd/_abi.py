@@ -105,6 +105,7 @@ def load_library():
         "tmd_set_timing": (_S, [_P, C.c_int32]),
         "tmd_set_graphs": (_S, [_P, C.c_int32]),
         "tmd_get_timing": (_S, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "tmd_compute_forces_static": (_S, [C.POINTER(TmdParams), C.c_int64, C.c_double, _P, _P, _P, _P, _P]),
         "tmd_status_string": (C.c_char_p, [_S]),
         "tmd_last_error": (C.c_char_p, [_P]),
         "tmd_destroy": (None, [_P]),
@@ -184,6 +185,15 @@ def tmd_compute_forces(handle, f_ptrs, energy_virial_ptr, stream: int) -> None:
     f = _p3(f_ptrs)
     _check(load_library().tmd_compute_forces(handle, C.cast(f, _P) if f is not None else None,
                                               energy_virial_ptr, stream), handle)
+
+
+def tmd_compute_forces_static(params: TmdParams, n_atoms: int, box_length: float, pos_ptrs, f_ptrs,
+                              energy_virial_ptr, status_ptr, stream: int) -> None:
+    p, f = _p3(pos_ptrs), _p3(f_ptrs)
+    _check(load_library().tmd_compute_forces_static(C.byref(params), n_atoms, box_length,
+                                                     C.cast(p, _P) if p is not None else None,
+                                                     C.cast(f, _P) if f is not None else None,
+                                                     energy_virial_ptr, status_ptr, stream))
 
 
 def tmd_integrate(handle, n_steps: int, thermo_every: int, thermo_ptr, stream: int) -> None:

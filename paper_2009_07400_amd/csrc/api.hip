@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -646,6 +647,48 @@ tmd_status run_interval(tmd_system *s, hipStream_t hs) {
     if (e == hipSuccess)
         s->graph_launches++;
     return e == hipSuccess ? TMD_OK : hip_fail(s, e, "graph launch");
+}
+
+// Device memory of tmd_compute_forces_static: every GPU the library runs
+// on holds its own copy of this array until the process ends.  Host code
+// never uses the symbol's own address (a host-side stand-in): each device's
+// address comes from hipGetSymbolAddress with that device current.
+static __device__ __align__(256) unsigned char scratch[TMD_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+struct StaticDevice {
+    bool ready = false;
+    void *ptr = nullptr;  // this device's copy of `scratch`
+    int max_lds = 0;      // per-workgroup LDS limit
+};
+
+std::mutex g_static_mu;
+StaticDevice g_static[kMaxDevices];
+
+// Once per device, with it current: the array's device address and the
+// block kernels' dynamic-LDS attribute.
+tmd_status static_device(StaticDevice &out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return TMD_EHIP;
+    if (dev < 0 || dev >= kMaxDevices)
+        return TMD_EINVAL;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticDevice &sd = g_static[dev];
+    if (!sd.ready) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return TMD_EHIP;
+        int max_lds = 0;
+        if (device_lds_limit(max_lds) != hipSuccess || prepare_kernels(max_lds - kStaticLds) != hipSuccess)
+            return TMD_EHIP;
+        sd.ptr = p;
+        sd.max_lds = max_lds;
+        sd.ready = true;
+    }
+    out = sd;
+    return TMD_OK;
 }
 
 }  // namespace
@@ -1313,6 +1356,59 @@ tmd_status tmd_get_timing(tmd_system *s, double *ms, int64_t *launches) {
         s->t_n[k] = 0;
     }
     return TMD_OK;
+}
+
+tmd_status tmd_compute_forces_static(const tmd_params *p, int64_t n_atoms, double L, const double *const pos[3],
+                                     double *const f[3], double *ev, int32_t *device_status, tmd_stream stream) {
+    if (!p || !pos || !pos[0] || !pos[1] || !pos[2])
+        return TMD_EINVAL;
+    // the schedule tmd_create picks, on the stack
+    Box B;
+    tmd_status st = make_box(*p, n_atoms, L, 0, B);
+    if (st != TMD_OK)
+        return st;
+    Dims d{};
+    d.nt = int32_t(n_atoms);
+    d.ntp = round_up(d.nt + 1, 256);
+    d.nbox = 1;
+    d.maxnb = p->max_neighbors;
+    d.nchunk = (d.maxnb + 3) / 4 + 1;
+    if (!layout_dims(&B, 1, default_edge(&B, 1), d))
+        return TMD_EINVAL;
+    if (carve(d, nullptr, nullptr) > size_t(TMD_STATIC_SCRATCH_BYTES))
+        return TMD_EWORKSPACE;
+    StaticDevice sd;
+    if ((st = static_device(sd)) != TMD_OK)
+        return st;
+    fit_cap(d, sd.max_lds);
+    Buffers b{};
+    carve(d, static_cast<char *>(sd.ptr), &b);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    Cursor cur;
+    hipError_t e = launch_store_box(b.boxes, B, hs);
+    if (e == hipSuccess)
+        e = launch_fill_i32(b.blk_box, 0, d.nblk, hs);
+    if (e == hipSuccess)
+        e = launch_fill_i32(b.atom_box, 0, d.ntp, hs);
+    if (e == hipSuccess)
+        e = launch_fill_i32(b.err, 0, 16, hs);
+    if (e == hipSuccess)
+        e = launch_load_state(d, pos, nullptr, b, cur, hs);
+    if (e == hipSuccess)
+        e = launch_bin(d, b, cur, false, hs);
+    cur.x = 1 - cur.x;
+    cur.o = 1 - cur.o;
+    if (e == hipSuccess)
+        e = launch_build(d, b, cur, hs);
+    if (e == hipSuccess)
+        e = launch_force(d, b, cur, 0, ev != nullptr, hs);
+    if (e == hipSuccess && ev)
+        e = launch_reduce(d, b, ev, 2, hs);
+    if (e == hipSuccess && f && (f[0] || f[1] || f[2]))
+        e = launch_unload(d, b.fx, b.fy, b.fz, b.orig[cur.o], f, hs);
+    if (e == hipSuccess && device_status)
+        e = launch_status_out(b.err, device_status, hs);
+    return e == hipSuccess ? TMD_OK : TMD_EHIP;
 }
 
 void tmd_destroy(tmd_system *s) {

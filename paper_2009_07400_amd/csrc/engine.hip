@@ -428,7 +428,7 @@ __global__ __launch_bounds__(kAtomThreads) void k_load_state(Dims d, const Box *
         return;
     const double L = boxes[atom_box[i]].L;
     const double px = wrap(ix[i], L), py = wrap(iy[i], L), pz = wrap(iz[i], L);
-    const double a = ivx[i], b = ivy[i], c = ivz[i];
+    const double a = ivx ? ivx[i] : 0.0, b = ivy ? ivy[i] : 0.0, c = ivz ? ivz[i] : 0.0;
     if (!(isfinite(a) && isfinite(b) && isfinite(c)))
         atomicOr(err, kErrNonFinite);
     if (!(px >= 0.0 && px < L && py >= 0.0 && py < L && pz >= 0.0 && pz < L))
@@ -1631,6 +1631,31 @@ __global__ void k_fill_f64(double *p, double v, int64_t n) {
         p[i] = v;
 }
 
+// One box descriptor written from a kernel argument (no host staging copy).
+__global__ void k_store_box(Box *dst, Box B) {
+    if (threadIdx.x == 0)
+        *dst = B;
+}
+
+// The device error word as a status code (the codes tmd_sync returns):
+// out[0] = status, out[1] = largest list length requested on overflow.
+__global__ void k_status_out(const int32_t *__restrict__ err, int32_t *out) {
+    if (threadIdx.x != 0)
+        return;
+    const int w = err[0];
+    int st = 0;
+    if (w & kErrNonFinite)
+        st = -5;
+    else if (w & kErrOverflow)
+        st = -4;
+    else if (w & kErrOutOfBox)
+        st = -1;
+    else if (w & kErrLdsLayout)
+        st = -7;
+    out[0] = st;
+    out[1] = err[1];
+}
+
 __global__ void k_split_pairs(const double *__restrict__ acc, int n, double *a, double *b) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -1745,6 +1770,16 @@ hipError_t launch_split_pairs(const double *acc, int n, double *a, double *b, hi
     return hipGetLastError();
 }
 
+hipError_t launch_store_box(Box *dst, const Box &B, hipStream_t s) {
+    k_store_box<<<1, 64, 0, s>>>(dst, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_out(const int32_t *err, int32_t *out, hipStream_t s) {
+    k_status_out<<<1, 64, 0, s>>>(err, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
     if (n <= 0)
         return hipSuccess;
@@ -1754,8 +1789,9 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
 
 hipError_t launch_load_state(const Dims &d, const double *const pos[3], const double *const vel[3], Buffers &b,
                              Cursor c, hipStream_t s) {
-    k_load_state<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, pos[0], pos[1], pos[2], vel[0],
-                                                             vel[1], vel[2], b.x[c.x], b.y[c.x], b.z[c.x],
+    const double *v0 = vel ? vel[0] : nullptr, *v1 = vel ? vel[1] : nullptr, *v2 = vel ? vel[2] : nullptr;
+    k_load_state<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, pos[0], pos[1], pos[2], v0,
+                                                             v1, v2, b.x[c.x], b.y[c.x], b.z[c.x],
                                                              b.vx[c.o], b.vy[c.o], b.vz[c.o], b.orig[c.o],
                                                              b.x[1 - c.x], b.y[1 - c.x], b.z[1 - c.x], b.err);
     return hipGetLastError();

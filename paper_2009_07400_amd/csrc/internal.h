@@ -150,6 +150,12 @@ constexpr int kBlockStaticLds = 1536;
 // device (the device's per-workgroup limit less kBlockStaticLds).
 hipError_t prepare_kernels(int dyn_bytes);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+// Write one box descriptor (passed by value) to dst.
+hipError_t launch_store_box(Box *dst, const Box &B, hipStream_t s);
+// out[0] = the status code tmd_sync() would return for the error word err
+// (0 when clear), out[1] = largest list length requested on overflow.
+hipError_t launch_status_out(const int32_t *err, int32_t *out, hipStream_t s);
+// vel == nullptr loads zero velocities.
 hipError_t launch_load_state(const Dims &d, const double *const pos[3], const double *const vel[3], Buffers &b,
                              Cursor c, hipStream_t s);
 hipError_t launch_unload(const Dims &d, const double *ax, const double *ay, const double *az, const int32_t *orig,

@@ -43,6 +43,23 @@ def make_params(epsilon=1.0, sigma=1.0, mass=1.0, cutoff=2.5, skin=0.3, dt=0.005
     return abi.TmdParams(epsilon, sigma, mass, cutoff, skin, dt, rebuild_every, max_neighbors)
 
 
+def compute_forces_static(pos, box_length: float, device="cuda", **params):
+    """One-shot forces of one periodic box through tmd_compute_forces_static,
+    whose intermediates live in the library's own device array (no
+    workspace).  pos: [N, 3].  Returns (F [N, 3], [U, W], status [2] int32),
+    all device tensors written on torch's current stream."""
+    abi.load_library()
+    _require_cuda()
+    n = int(torch.as_tensor(pos).shape[0])
+    p = _soa(pos, n, device)
+    f = torch.empty(3, n, dtype=torch.float64, device=device)
+    ev = torch.empty(2, dtype=torch.float64, device=device)
+    st = torch.empty(2, dtype=torch.int32, device=device)
+    abi.tmd_compute_forces_static(make_params(**params), n, float(box_length), _ptrs(p), _ptrs(f),
+                                  int(ev.data_ptr()), int(st.data_ptr()), _stream())
+    return f.t(), ev, st
+
+
 class System:
     """Periodic cubic LJ box(es) advanced by the HIP library.
 

@@ -191,3 +191,24 @@ def test_null_arguments():
     assert lib.tmd_set_timing(out, 1) == abi.TMD_OK
     assert lib.tmd_set_graphs(None, 1) == abi.TMD_EINVAL
     lib.tmd_destroy(out)
+
+
+def test_static_forces_validates_before_the_gpu():
+    """tmd_compute_forces_static checks its arguments and the size of its
+    intermediates against the library's fixed device array before it touches
+    a GPU (these calls return without one)."""
+    lib = abi.load_library()
+    p = make_params()
+    fake = (C.c_void_p * 3)(16, 32, 48)  # never dereferenced: every call below fails its checks first
+    args = (C.cast(fake, C.c_void_p), None, None, None, None)
+    assert lib.tmd_compute_forces_static(None, 2048, 13.43677, *args) == abi.TMD_EINVAL
+    assert lib.tmd_compute_forces_static(C.byref(p), 2048, 13.43677, None, None, None, None, None) == abi.TMD_EINVAL
+    assert lib.tmd_compute_forces_static(C.byref(p), 0, 13.43677, *args) == abi.TMD_EINVAL
+    assert lib.tmd_compute_forces_static(C.byref(p), 2048, 5.0, *args) == abi.TMD_EBOX
+    # 32^3 unit cells (131,072 atoms) need more than the 64 MiB array
+    h = abi.tmd_create(p, 131072, 53.74708)
+    try:
+        assert abi.tmd_workspace_size(h) > 64 * 1024 * 1024
+    finally:
+        abi.tmd_destroy(h)
+    assert lib.tmd_compute_forces_static(C.byref(p), 131072, 53.74708, *args) == abi.TMD_EWORKSPACE
