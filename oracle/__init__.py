@@ -61,6 +61,15 @@ def _load():
         lib.orc_tangent.restype = _L
         lib.orc_tangent.argtypes = [_I, _P, _P, _P, _P, _P, _P, _D, _D, _D, _D, _D, _D, _D, _I, _I, _I,
                                     _P, _P, _P, _P, _P, _P, _D, _D]
+        lib.orc_sd_pair.restype = _D
+        lib.orc_sd_pair.argtypes = [_D, _D, _D, _D, _D, _D, _D, _D, _D, _P]
+        lib.orc_sd_forces.restype = None
+        lib.orc_sd_forces.argtypes = [_I, _P, _P, _P, _P, _P, _P, _D, _P, _P, _I, _D, _D, _D, _P, _P, _P, _P, _P, _P]
+        lib.orc_sd_atom_force.restype = None
+        lib.orc_sd_atom_force.argtypes = [_I, _P, _P, _P, _P, _P, _P, _D, _I, _D, _D, _D, _P]
+        lib.orc_sd_run.restype = _L
+        lib.orc_sd_run.argtypes = [_I, _P, _P, _P, _P, _P, _P, _D, _D, _D, _D, _D, _D, _D, _D, _I, _I, _I, _P, _P, _P,
+                                   _P]
         _lib = lib
     return _lib
 
@@ -216,3 +225,59 @@ def tangent(x0, v0, L, nsteps, dx, dv, d_eps, d_sigma, eps=1.0, sigma=1.0, mass=
     if m > maxnb:
         raise ValueError("neighbor list overflow")
     return tx.T.copy(), tv.T.copy()
+
+
+# ---------------------------------------------------------------- Spring-Dashpot (Eq. 3)
+
+def sd_pair(d, dv, k, gamma, sigma):
+    """Force on i of one pair (separation d = x_i - x_j, relative velocity
+    dv = v_i - v_j); returns (F[3], magnitude along the unit vector)."""
+    out = np.zeros(3)
+    fm = _load().orc_sd_pair(float(d[0]), float(d[1]), float(d[2]), float(dv[0]), float(dv[1]), float(dv[2]),
+                             k, gamma, sigma, _ptr(out))
+    return out, float(fm)
+
+
+def sd_forces(x, v, L, count, nbr, k, gamma, sigma):
+    """Spring-Dashpot forces for the given list; x, v [N, 3].  Returns
+    (F[N, 3], scale[N] = sum_j |F_ij|, U elastic, W virial)."""
+    xT = _f64(np.asarray(x).T)
+    vT = _f64(np.asarray(v).T)
+    n = xT.shape[1]
+    count = np.ascontiguousarray(count, dtype=np.int32)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    f = np.zeros((3, n))
+    scale = np.zeros(n)
+    U = C.c_double()
+    W = C.c_double()
+    _load().orc_sd_forces(n, _ptr(xT[0]), _ptr(xT[1]), _ptr(xT[2]), _ptr(vT[0]), _ptr(vT[1]), _ptr(vT[2]), L,
+                          _ptr(count), _ptr(nbr), nbr.shape[1], k, gamma, sigma, _ptr(f[0]), _ptr(f[1]), _ptr(f[2]),
+                          _ptr(scale), C.byref(U), C.byref(W))
+    return f.T.copy(), scale, U.value, W.value
+
+
+def sd_atom_force(x, v, L, i, k, gamma, sigma):
+    """All-pairs Spring-Dashpot force on one sphere (no list)."""
+    xT = _f64(np.asarray(x).T)
+    vT = _f64(np.asarray(v).T)
+    out = np.zeros(3)
+    _load().orc_sd_atom_force(xT.shape[1], _ptr(xT[0]), _ptr(xT[1]), _ptr(xT[2]), _ptr(vT[0]), _ptr(vT[1]),
+                              _ptr(vT[2]), L, int(i), k, gamma, sigma, _ptr(out))
+    return out
+
+
+def sd_run(x, v, L, nsteps, k, gamma, sigma=1.0, mass=1.0, cutoff=1.0, skin=0.3, dt=0.001, rebuild_every=20,
+           maxnb=64, thermo=True):
+    """Velocity Verlet of Spring-Dashpot spheres; x, v [N, 3].  Returns
+    dict(x, v, f, thermo[nsteps+1, 5] = (KE, T, U elastic, W, KE + U), maxc)."""
+    xT = _f64(np.asarray(x).T).copy()
+    vT = _f64(np.asarray(v).T).copy()
+    n = xT.shape[1]
+    f = np.zeros((3, n))
+    th = np.zeros((nsteps + 1, 5)) if thermo else None
+    m = _load().orc_sd_run(n, _ptr(xT[0]), _ptr(xT[1]), _ptr(xT[2]), _ptr(vT[0]), _ptr(vT[1]), _ptr(vT[2]), L, k,
+                           gamma, sigma, mass, cutoff, skin, dt, rebuild_every, maxnb, nsteps,
+                           _ptr(th) if thermo else None, _ptr(f[0]), _ptr(f[1]), _ptr(f[2]))
+    if m > maxnb:
+        raise ValueError(f"neighbor list overflow: {m} > {maxnb}")
+    return {"x": xT.T.copy(), "v": vT.T.copy(), "f": f.T.copy(), "thermo": th, "maxc": int(m)}

@@ -22,6 +22,9 @@
  *   - The exact derivative of that discrete map with lists and cutoff
  *     indicators held fixed (adjoint and tangent-linear), for gradients with
  *     respect to epsilon, sigma and the initial state.
+ *   - The Spring-Dashpot contact force between spheres (Sec. 3.2, Eq. 3)
+ *     with the same lists and integrator (the damping takes the half-step
+ *     velocities).
  *
  * Readings where the paper is silent: strict '<' for both the cutoff and the
  * list radius; canonical minimum image `d = a - b; if d > L/2: d -= L; else if
@@ -781,5 +784,163 @@ long orc_tangent(int n, const double *x0, const double *y0, const double *z0, co
     free(g);
     free(vT);
     free_traj(&t);
+    return maxc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Spring-Dashpot contact model (Sec. 3.2, Eq. 3)                      */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Spheres of diameter sigma.  For a pair with separation vector x_ij =
+ * x_i - x_j (minimum image), distance r = |x_ij|, unit vector u = x_ij / r and
+ * relative velocity v_ij = v_i - v_j, Eq. 3 gives the force on i
+ *     F_ij = K xi + gamma xi_dot,
+ *     xi     = u (sigma - r) Theta(sigma - r),
+ *     xi_dot = -u (u . v_ij) Theta(sigma - r),
+ * i.e. F_ij = [K (sigma - r) - gamma (u . v_ij)] u while the spheres overlap
+ * (r < sigma: Theta(0) read as 0, the contact starts at strict overlap) and
+ * zero otherwise.  K is the spring constant, gamma the dissipation constant.
+ *
+ * Only overlapping pairs interact, so the Verlet list is built at
+ * cutoff + skin with cutoff >= sigma and the contact test is r < sigma.
+ * The force depends on velocities: in velocity Verlet the force at step
+ * k + 1 takes the half-step velocities v_{k+1/2} (the full-step ones need
+ * that very force); the first force takes the initial velocities.
+ */
+
+/* Force on i from one pair, added to out3; returns the pair force magnitude
+ * K (sigma - r) - gamma (u . v_ij) (0 without contact). */
+double orc_sd_pair(double dx, double dy, double dz, double dvx, double dvy, double dvz, double k, double gamma,
+                   double sigma, double *out3)
+{
+    double s = dx * dx + dy * dy + dz * dz;
+    if (!(s < sigma * sigma))
+        return 0.0;
+    double r = sqrt(s);
+    double ux = dx / r, uy = dy / r, uz = dz / r;
+    double un = ux * dvx + uy * dvy + uz * dvz;
+    double fm = k * (sigma - r) - gamma * un;
+    out3[0] += fm * ux;
+    out3[1] += fm * uy;
+    out3[2] += fm * uz;
+    return fm;
+}
+
+/*
+ * F_i = sum over j in list(i) (list order) of F_ij.  scale[i] (nullable) =
+ * sum_j |F_ij| (the conditioning scale).  energy = the springs' elastic
+ * energy 1/2 K (sigma - r)^2 per overlapping pair; virial = sum over pairs
+ * of x_ij . F_ij (each pair once: 1/2 of the double sums).
+ */
+void orc_sd_forces(int n, const double *x, const double *y, const double *z, const double *vx, const double *vy,
+                   const double *vz, double L, const int *count, const int *nbr, int maxnb, double k, double gamma,
+                   double sigma, double *fx, double *fy, double *fz, double *scale, double *energy, double *virial)
+{
+    double *ui = (double *)calloc((size_t)n, sizeof(double));
+    double *wi = (double *)calloc((size_t)n, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        double a[3] = {0.0, 0.0, 0.0}, sc = 0.0, u = 0.0, w = 0.0;
+        for (int q = 0; q < count[i]; ++q) {
+            int j = nbr[(size_t)i * maxnb + q];
+            double dx, dy, dz;
+            double s = dist2(x, y, z, i, j, L, &dx, &dy, &dz);
+            if (s < sigma * sigma) {
+                double fm = orc_sd_pair(dx, dy, dz, vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j], k, gamma, sigma, a);
+                double r = sqrt(s);
+                sc += fabs(fm);
+                u += 0.5 * k * (sigma - r) * (sigma - r);
+                w += fm * r;
+            }
+        }
+        fx[i] = a[0];
+        fy[i] = a[1];
+        fz[i] = a[2];
+        if (scale)
+            scale[i] = sc;
+        ui[i] = u;
+        wi[i] = w;
+    }
+    ksum_t U = {0.0, 0.0}, W = {0.0, 0.0};
+    for (int i = 0; i < n; ++i) {
+        ksum_add(&U, ui[i]);
+        ksum_add(&W, wi[i]);
+    }
+    if (energy)
+        *energy = 0.5 * ksum_value(&U);
+    if (virial)
+        *virial = 0.5 * ksum_value(&W);
+    free(ui);
+    free(wi);
+}
+
+/* Force on atom i from every atom j (no list), ascending j: the all-pairs
+ * definition of Eq. 3. */
+void orc_sd_atom_force(int n, const double *x, const double *y, const double *z, const double *vx,
+                       const double *vy, const double *vz, double L, int i, double k, double gamma, double sigma,
+                       double *out3)
+{
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < n; ++j) {
+        double dx, dy, dz;
+        if (j == i)
+            continue;
+        dist2(x, y, z, i, j, L, &dx, &dy, &dz);
+        orc_sd_pair(dx, dy, dz, vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j], k, gamma, sigma, a);
+    }
+    out3[0] = a[0];
+    out3[1] = a[1];
+    out3[2] = a[2];
+}
+
+/*
+ * Velocity Verlet of Spring-Dashpot spheres, in place:
+ *   v += (dt/2m) F;  x += dt v;  wrap;  [rebuild list if step % rebuild_every == 0];
+ *   F = F(x, v);  v += (dt/2m) F
+ * where the force takes the half-step velocities of the line before it; the
+ * initial list and forces come from the input state.  thermo (nullable):
+ * nsteps+1 rows (KE, T, U elastic, W, E = KE + U).  Returns the largest list
+ * length seen.
+ */
+long orc_sd_run(int n, double *x, double *y, double *z, double *vx, double *vy, double *vz, double L, double k,
+                double gamma, double sigma, double mass, double cutoff, double skin, double dt, int rebuild_every,
+                int maxnb, int nsteps, double *thermo, double *fx, double *fy, double *fz)
+{
+    int *count = (int *)malloc(sizeof(int) * (size_t)n);
+    int *nbr = (int *)malloc(sizeof(int) * (size_t)n * (size_t)maxnb);
+    double h = 0.5 * dt / mass;
+    double U, W;
+    long maxc = orc_build_list(n, x, y, z, L, cutoff + skin, maxnb, count, nbr);
+    orc_sd_forces(n, x, y, z, vx, vy, vz, L, count, nbr, maxnb, k, gamma, sigma, fx, fy, fz, NULL, &U, &W);
+    if (thermo)
+        thermo_row(thermo, n, kinetic(n, vx, vy, vz, mass), U, W);
+    for (int step = 1; step <= nsteps; ++step) {
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; ++i) {
+            vx[i] = vx[i] + h * fx[i];
+            vy[i] = vy[i] + h * fy[i];
+            vz[i] = vz[i] + h * fz[i];
+            x[i] = wrap1(x[i] + dt * vx[i], L);
+            y[i] = wrap1(y[i] + dt * vy[i], L);
+            z[i] = wrap1(z[i] + dt * vz[i], L);
+        }
+        if (rebuild_every > 0 && step % rebuild_every == 0) {
+            long m = orc_build_list(n, x, y, z, L, cutoff + skin, maxnb, count, nbr);
+            if (m > maxc)
+                maxc = m;
+        }
+        orc_sd_forces(n, x, y, z, vx, vy, vz, L, count, nbr, maxnb, k, gamma, sigma, fx, fy, fz, NULL, &U, &W);
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; ++i) {
+            vx[i] = vx[i] + h * fx[i];
+            vy[i] = vy[i] + h * fy[i];
+            vz[i] = vz[i] + h * fz[i];
+        }
+        if (thermo)
+            thermo_row(thermo + 5 * (size_t)step, n, kinetic(n, vx, vy, vz, mass), U, W);
+    }
+    free(count);
+    free(nbr);
     return maxc;
 }

@@ -14,4 +14,7 @@ from .lattice import (  # noqa: F401
     md_system,
     batched_box_specs,
     MDInput,
+    SDInput,
+    sd_system,
+    sd_half_domain,
 )

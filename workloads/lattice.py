@@ -143,3 +143,45 @@ def batched_box_specs(n_boxes: int = 512, master_seed: int = 2000):
         specs.append((4 + int(np.floor(9.0 * u[b, 0])), 0.75 + 0.15 * float(u[b, 1]),
                       0.7 + 0.8 * float(u[b, 2]), int(raw[b, 3])))
     return specs
+
+
+@dataclass
+class SDInput(MDInput):
+    """Spheres for the Spring-Dashpot contact model (Sec. 3.2, Eq. 3) with
+    the parameters the run uses: spring constant k, dissipation gamma,
+    diameter sigma, list radius cutoff + skin, time step dt."""
+
+    k: float = 1000.0
+    gamma: float = 5.0
+    sigma: float = 1.0
+    cutoff: float = 1.0
+    skin: float = 0.3
+    dt: float = 1e-3
+
+
+def sd_system(ncell: int, seed: int = 4000, overlap: float = 0.02, jitter: float = 0.05, T: float = 0.5,
+              k: float = 1000.0, gamma: float = 5.0, sigma: float = 1.0, dt: float = 1e-3) -> SDInput:
+    """A dense packing of spheres of diameter sigma: an FCC lattice of
+    ncell^3 unit cells whose nearest neighbours sit (1 - overlap) sigma
+    apart, so every sphere presses on its twelve neighbours, then seeded
+    jitter and velocities as in md_system (draw order jitter, velocities)."""
+    a = np.sqrt(2.0) * (1.0 - overlap) * sigma
+    rho = 4.0 / a ** 3
+    b = md_system(ncell, rho=rho, T=T, seed=seed, jitter=jitter)
+    return SDInput(b.x, b.y, b.z, b.vx, b.vy, b.vz, b.L, ncell, rho, T, seed, k=k, gamma=gamma, sigma=sigma,
+                   cutoff=sigma, skin=0.3, dt=dt)
+
+
+def sd_half_domain(ncell: int, sigma: float = 1.0):
+    """The load-balancing geometry of Sec. 6: a periodic cube of ncell^3
+    unit cells of side sigma, with one sphere at the corner of every unit
+    cell on one side of the diagonal plane x + y + z = 3 L / 2 - half of the
+    domain filled, half empty (ncell^3 / 2 spheres for even ncell).  The
+    paper runs it with zero stiffness and damping (spheres at rest).
+    Returns (pos[N, 3], L)."""
+    idx = np.arange(ncell, dtype=np.float64)
+    iz, iy, ix = np.meshgrid(idx, idx, idx, indexing="ij")
+    p = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1) * sigma
+    L = ncell * sigma
+    keep = (p[:, 0] + p[:, 1] + p[:, 2]) + 1.5 * sigma < 1.5 * L
+    return np.ascontiguousarray(p[keep]), float(L)
