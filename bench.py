@@ -124,8 +124,9 @@ def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int) -> dict:
     Binning moves 132 algorithmic bytes per atom (read x and the atom id,
     28; the permutation reads x, v and id and writes them, 52 + 52).  The
     list build reads x (24) and writes the count (4) and the list (4 bytes
-    per entry at the method's index width) and tests 27 cells' worth of
-    candidates per atom, 8 unfused FP64 instructions each (3 differences, 3
+    per entry at the method's index width) and tests the atoms of 125
+    half-size subcells per atom (125 / 8 cells' worth; 27 whole cells hold
+    1.73x as many), 8 unfused FP64 instructions each (3 differences, 3
     squares, 2 sums, no fused multiply-add so that its decisions match any
     IEEE evaluation): it is bound by FP64 instruction issue, so its fraction
     is taken against the issue rate of unfused FP64 instructions, with the
@@ -141,11 +142,12 @@ def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int) -> dict:
         ms, calls = tm["neighbor"]
         t = ms / calls * 1e-3
         b = (28.0 + 4.0 * mean_list) * n
-        cand = 27.0 * n / n_cells
+        cand = 125.0 / 8.0 * n / n_cells
         ops = 8.0 * cand * n
         out["neighbor"] = {"bound": "alu", "achieved": ops / t / 1e12, "peak": FP64_ISSUE_PEAK_T,
                            "unit": "T FP64 instr/s", "frac": ops / t / 1e12 / FP64_ISSUE_PEAK_T,
-                           "candidates_per_atom": cand, "hbm_achieved_gbs": b / t / 1e9,
+                           "candidates_per_atom": cand, "cell_stencil_candidates_per_atom": 27.0 * n / n_cells,
+                           "hbm_achieved_gbs": b / t / 1e9,
                            "hbm_frac": b / t / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_call": b, "avg_call_us": t * 1e6}
     return out
 
@@ -348,6 +350,66 @@ def run_adjoint(steps: int = 200, replicas: int = 64):
             "schedule": sched, "hvp_roofline": hvp}
 
 
+def run_spring_dashpot(steps: int = 200, warmup: int = 20):
+    """Spring-Dashpot spheres (Sec. 3.2, Eq. 3): the paper's load-balancing
+    geometry - a periodic cube of 96^3 unit cells, one sphere per cell corner
+    on one side of a diagonal plane (442,368 spheres, half the domain empty),
+    stiffness and damping zero as in the paper (spheres at rest) - and a
+    dense packing of 1,048,576 spheres pressing on their twelve neighbours
+    (K 1000, gamma 5) in motion.  Diameter 1, list radius 1.3, dt 0.001,
+    rebuild every 20 steps."""
+    import torch
+
+    from paper_2009_07400_amd import System
+    from workloads import sd_half_domain, sd_system
+
+    out = {}
+    pos, L = sd_half_domain(96)
+    dense = sd_system(64)
+    cases = {
+        "half_domain": (pos, np.zeros_like(pos), L, 0.0, 0.0,
+                        "96^3 unit cells, spheres on one side of the diagonal plane (442,368), K = gamma = 0 "
+                        "(the paper's load-balancing setup)"),
+        "dense": (dense.pos(), dense.vel(), dense.L, dense.k, dense.gamma,
+                  "FCC 64^3 = 1,048,576 spheres at 0.98 sigma spacing (12 contacts each), K 1000, gamma 5, T 0.5"),
+    }
+    for name, (p, v, Lb, k, gamma, desc) in cases.items():
+        g = System(p.shape[0], Lb, model="spring_dashpot", stiffness=k, damping=gamma, sigma=1.0, cutoff=1.0,
+                   skin=0.3, dt=1e-3, max_neighbors=32)
+        g.set_state(torch.from_numpy(p), torch.from_numpy(v))
+        _warm_and_tune(g, warmup)
+        g.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.integrate(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g.sync()
+        g.set_timing(True)
+        g.integrate(steps)
+        g.sync()
+        tm = g.get_timing()
+        g.set_timing(False)
+        mean_list = float(g.neighbor_counts().double().mean().item())
+        g.sync()
+        sched = _schedule(g)
+        g.close()
+        ms, launches = tm["force"]
+        avg_s = ms / max(launches, 1) * 1e-3
+        n = p.shape[0]
+        # algorithmic bytes per sphere of the force sum: count 4 + list
+        # 4 n_list + x_i 24 + v_i 24 + F_i 24 (neighbours' x, v from LDS/cache)
+        alg = (76.0 + 4.0 * mean_list) * n
+        out[name] = {"workload": desc, "value": n * steps / el, "unit": "atom-steps/s", "steps": steps,
+                     "ms_per_step": el / steps * 1e3, "mean_list_length": mean_list, "schedule": sched,
+                     "roofline": {"bound": "hbm", "kernel": "k_force_sd<2,false>: contact force + kicks + drift",
+                                  "achieved": alg / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": alg / avg_s / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_atom": 76.0 + 4.0 * mean_list,
+                                  "avg_launch_us": avg_s * 1e6},
+                     "kernel_avg_ms": {k2: (v2[0] / max(v2[1], 1), v2[1]) for k2, v2 in tm.items() if v2[1]}}
+    return out
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -471,6 +533,10 @@ def main():
         print(f"# secondary adjoint: {adj['value']:.4g} atom-steps/s, {adj['adjoint_over_plain_time']:.2f}x plain "
               "time", file=sys.stderr, flush=True)
         out["secondary"]["adjoint"] = adj
+        sd = run_spring_dashpot()
+        print("# secondary spring-dashpot: " + ", ".join(f"{k} {v['value']:.4g} atom-steps/s" for k, v in sd.items()),
+              file=sys.stderr, flush=True)
+        out["secondary"]["spring_dashpot"] = sd
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_steps, args.cpu_single_steps)
     print(json.dumps(out), flush=True)

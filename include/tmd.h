@@ -49,11 +49,25 @@ typedef enum {
     TMD_EHIP = -7           /* a HIP runtime call failed; tmd_last_error() has the HIP message */
 } tmd_status;
 
+/* Force models (Sec. 3.2). */
+enum {
+    TMD_MODEL_LJ = 0,             /* Lennard-Jones 12-6 pair force, Eq. 2 */
+    TMD_MODEL_SPRING_DASHPOT = 1  /* Spring-Dashpot contact of spheres, Eq. 3 */
+};
+
 /* Physical and algorithmic parameters.  epsilon is the depth of the LJ well,
  * sigma the distance at which the pair potential is zero (Sec. 3.2, Eq. 2);
  * cutoff and skin give the force cutoff and the list radius cutoff + skin
  * (Fig. 1 caption; 2.5 and 0.3 in Sec. 6); rebuild_every is the reneighboring
- * interval (20 in Sec. 6); max_neighbors the list capacity per atom. */
+ * interval (20 in Sec. 6); max_neighbors the list capacity per atom.
+ * model selects the force: TMD_MODEL_LJ (default), or
+ * TMD_MODEL_SPRING_DASHPOT (Sec. 3.2, Eq. 3) for spheres of diameter sigma
+ * with spring constant `stiffness` (K) and dissipation constant `damping`
+ * (gamma): F_ij = [K (sigma - r) - gamma (u . v_ij)] u while r < sigma, u =
+ * x_ij / r, v_ij = v_i - v_j; it needs cutoff >= sigma (the list radius is
+ * cutoff + skin) and ignores epsilon.  In velocity Verlet its damping takes
+ * the half-step velocities v_{k+1/2} at the force of step k + 1 (the
+ * initial force takes the initial velocities). */
 typedef struct {
     double epsilon;
     double sigma;
@@ -63,6 +77,10 @@ typedef struct {
     double dt;
     int32_t rebuild_every;
     int32_t max_neighbors;
+    double stiffness;  /* Spring-Dashpot K >= 0 */
+    double damping;    /* Spring-Dashpot gamma >= 0 */
+    int32_t model;     /* TMD_MODEL_* */
+    int32_t reserved;  /* 0 */
 } tmd_params;
 
 typedef struct tmd_system tmd_system; /* opaque, library-owned host object */
@@ -106,8 +124,10 @@ enum {
  * Host only; touches no GPU.  Returns TMD_EINVAL for a NULL pointer, n_atoms
  * <= 0 or > 2^31-1, a non-finite or non-positive epsilon, sigma, mass, cutoff,
  * dt, box_length, a negative skin, rebuild_every < 1 or max_neighbors outside
- * [1, 4096]; TMD_EBOX when cutoff + skin >= box_length / 2.  On success *out
- * owns a handle to release with tmd_destroy(). */
+ * [1, 4096], an unknown model, and for the Spring-Dashpot model a negative or
+ * non-finite stiffness or damping or cutoff < sigma; TMD_EBOX when cutoff +
+ * skin >= box_length / 2.  On success *out owns a handle to release with
+ * tmd_destroy(). */
 tmd_status tmd_create(const tmd_params *params, int64_t n_atoms, double box_length, tmd_system **out);
 
 /* Create one system holding n_boxes independent periodic cubes (replicas)
@@ -248,7 +268,8 @@ tmd_status tmd_autotune(tmd_system *sys, int32_t repeats, tmd_stream stream);
 
 /* Replace epsilon and sigma of every box (host arrays of n_boxes values, each
  * finite and positive); the copy to the device is enqueued on `stream`.  The
- * list is kept; forces are recomputed at the next step. */
+ * list is kept; forces are recomputed at the next step.  Lennard-Jones
+ * systems only (TMD_EINVAL otherwise). */
 tmd_status tmd_set_lj_params(tmd_system *sys, const double *epsilon, const double *sigma, tmd_stream stream);
 
 /* --- Gradients through the discrete trajectory (reverse mode) ------------
@@ -263,14 +284,17 @@ tmd_status tmd_set_lj_params(tmd_system *sys, const double *epsilon, const doubl
  * Hessian-vector product, and each drift adds lam_v += dt lam_x. */
 
 /* Bytes of adjoint workspace for an n_steps run: (x, v) checkpoints at each
- * rebuild, one rebuild interval of recomputed positions, cotangents. */
+ * rebuild, the positions of every step (24 bytes per atom and step),
+ * cotangents. */
 tmd_status tmd_adjoint_workspace_size(const tmd_system *sys, int32_t n_steps, size_t *bytes);
 
-/* Integrate n_steps like tmd_integrate() while recording checkpoints in `ws`
+/* Integrate n_steps like tmd_integrate() (bit-identical trajectory) while
+ * recording checkpoints and every step's positions in `ws`
  * (device, 256-byte aligned, at least tmd_adjoint_workspace_size bytes,
  * borrowed until the backward pass).  The step counter must be a multiple of
  * rebuild_every (TMD_ESTATE otherwise); the run starts from a list built at
- * the current positions. */
+ * the current positions.  Lennard-Jones systems only (TMD_EINVAL for the
+ * Spring-Dashpot model). */
 tmd_status tmd_adjoint_forward(tmd_system *sys, int32_t n_steps, void *ws, size_t bytes, tmd_stream stream);
 
 /* Given the cotangents of the final state lam_x[3] (required) and lam_v[3]
@@ -278,9 +302,10 @@ tmd_status tmd_adjoint_forward(tmd_system *sys, int32_t n_steps, void *ws, size_
  * grad_x0[3] = dL/dx_0, grad_v0[3] = dL/dv_0 (nullable), and per box
  * grad_eps[n_boxes], grad_sigma[n_boxes] (device, nullable).  Needs the run
  * recorded by tmd_adjoint_forward() in the same workspace with no
- * state-changing call in between (TMD_ESTATE otherwise).  Recomputes each
- * rebuild interval from its checkpoint (bit-identical to the recorded run)
- * and leaves the system in the run's final state. */
+ * state-changing call in between (TMD_ESTATE otherwise).  Rebuilds each
+ * interval's list from its checkpoint (the list and atom order of the
+ * recorded run) and takes the positions from the store, and leaves the
+ * system in the run's final state. */
 tmd_status tmd_adjoint_backward(tmd_system *sys, void *ws, size_t bytes, const double *const lam_x[3],
                                 const double *const lam_v[3], double *const grad_x0[3], double *const grad_v0[3],
                                 double *grad_eps, double *grad_sigma, tmd_stream stream);

@@ -25,6 +25,9 @@ TMD_EHIP = -7
 
 TIMING_CLASSES = ("force", "neighbor", "binning", "drift", "thermo", "copy", "adjoint")
 
+TMD_MODEL_LJ = 0
+TMD_MODEL_SPRING_DASHPOT = 1
+
 
 class TmdParams(C.Structure):
     _fields_ = [
@@ -36,6 +39,10 @@ class TmdParams(C.Structure):
         ("dt", C.c_double),
         ("rebuild_every", C.c_int32),
         ("max_neighbors", C.c_int32),
+        ("stiffness", C.c_double),
+        ("damping", C.c_double),
+        ("model", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

@@ -111,9 +111,10 @@ size_t carve(const Dims &d, char *base, Buffers *out) {
     b.cell_of = (int32_t *)take(np * 4);
     b.slot = (int32_t *)take(np * 4);
     b.tmp_idx = (int32_t *)take(np * 4);
-    b.cell_count = (int32_t *)take(size_t(d.ncs) * 4);
-    b.cell_start = (int32_t *)take((size_t(d.ncs) + 1) * 4);
-    b.scan_sums = (int32_t *)take((size_t(scan_blocks(d.ncs)) + 1) * 4);
+    const size_t nbin = size_t(d.ncs) * kSub;
+    b.cell_count = (int32_t *)take(nbin * 4);
+    b.cell_start = (int32_t *)take((nbin + 1) * 4);
+    b.scan_sums = (int32_t *)take((size_t(scan_blocks(int(nbin))) + 1) * 4);
     b.nbr_count = (int32_t *)take(np * 4);
     b.nbr = (int32_t *)take(np * size_t(d.nchunk) * 4 * 4);
     b.hood_tab = (int32_t *)take(size_t(d.nblk) * kHoodWords * 4);
@@ -229,12 +230,13 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
     {
         Timed t(s, TMD_T_BINNING, st);
         e = launch_bin(s->d, s->b, s->cur, s->counts_clear, st);
-        s->counts_clear = e == hipSuccess && s->d.ncs <= kScanOne;
+        s->counts_clear = e == hipSuccess && int64_t(s->d.ncs) * kSub <= kScanOne;
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "binning");
     s->cur.x = 1 - s->cur.x;
     s->cur.o = 1 - s->cur.o;
+    s->cur.v = 1 - s->cur.v;
     {
         Timed t(s, TMD_T_NEIGHBOR, st);
         e = launch_build(s->d, s->b, s->cur, st);
@@ -305,7 +307,7 @@ bool layout_dims(Box *boxes, int32_t nbox, int E, Dims &d) {
         B.cell_off = int32_t(blocks * E * E * E);
         blocks += B.nblocks;
         worst = std::max(worst, expected_hood_atoms(B, E));
-        if (blocks * E * E * E > INT32_MAX / 2)
+        if (blocks * E * E * E * kSub > INT32_MAX / 2)
             return false;
     }
     d.edge = E;
@@ -316,9 +318,11 @@ bool layout_dims(Box *boxes, int32_t nbox, int E, Dims &d) {
     // LDS still stages at least 15% more atoms than the largest mean
     // neighborhood; the capacity then takes that whole share.
     const int need = int(1.15 * worst) + 32;
+    // the Spring-Dashpot force kernel stages velocities too: 48 bytes a slot
+    const int slot = d.model == 1 ? 48 : 24;
     d.cap = std::min(kMaxCap, round_up(int(1.3 * worst) + 64, 64));
     for (int wg = 8; wg >= 1; --wg) {
-        const int c = ((kLdsPerCu / wg - kStaticLds) / 24 - 2 - kHoodPad) / 64 * 64;  // + slots past the capacity
+        const int c = ((kLdsPerCu / wg - kStaticLds) / slot - 2 - kHoodPad) / 64 * 64;  // + slots past the capacity
         if (c >= need) {
             d.cap = std::min(kMaxCap, c);
             break;
@@ -370,6 +374,12 @@ tmd_status make_box(const tmd_params &p, int64_t n, double L, int64_t atom_off, 
         return TMD_EINVAL;
     if (p.rebuild_every < 1 || p.max_neighbors < 1 || p.max_neighbors > 4096)
         return TMD_EINVAL;
+    if (p.model != TMD_MODEL_LJ && p.model != TMD_MODEL_SPRING_DASHPOT)
+        return TMD_EINVAL;
+    if (p.model == TMD_MODEL_SPRING_DASHPOT &&
+        (!isfinite(p.stiffness) || p.stiffness < 0.0 || !isfinite(p.damping) || p.damping < 0.0 ||
+         !(p.cutoff >= p.sigma)))
+        return TMD_EINVAL;
     const double r = p.cutoff + p.skin;
     if (!(r < 0.5 * L))
         return TMD_EBOX;
@@ -385,12 +395,17 @@ tmd_status make_box(const tmd_params &p, int64_t n, double L, int64_t atom_off, 
     B.halfL2 = B.halfL * B.halfL;
     B.invL = 1.0 / L;
     B.side = L / B.nc;
+    B.hside = 0.5 * B.side;
     B.rc2 = p.cutoff * p.cutoff;
     B.rl2 = r * r;
     set_lj(B, p.epsilon, p.sigma);
     B.h = 0.5 * p.dt / p.mass;
     B.dt = p.dt;
     B.mass = p.mass;
+    B.sd_k = p.stiffness;
+    B.sd_g = p.damping;
+    B.sd_sig = p.sigma;
+    B.sd_sig2 = p.sigma * p.sigma;
     return TMD_OK;
 }
 
@@ -410,7 +425,8 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
     }
     for (int32_t k = 0; k < nbox; ++k) {
         const tmd_params &p = params[k];
-        if (p.rebuild_every != params[0].rebuild_every || p.max_neighbors != params[0].max_neighbors)
+        if (p.rebuild_every != params[0].rebuild_every || p.max_neighbors != params[0].max_neighbors ||
+            p.model != params[0].model)
             return TMD_EINVAL;
         const tmd_status st = make_box(p, n_atoms[k], lengths[k], total, boxes[size_t(k)]);
         if (st != TMD_OK)
@@ -431,6 +447,7 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
         d.nbox = nbox;
         d.maxnb = params[0].max_neighbors;
         d.nchunk = (d.maxnb + 3) / 4 + 1;  // one spare chunk of sentinel padding
+        d.model = params[0].model;
         if (int64_t(d.ntp) * d.maxnb > (int64_t(1) << 40)) {
             delete s;
             return TMD_EINVAL;
@@ -466,12 +483,12 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
 }
 
 // Adjoint workspace: checkpoints of (x, v) in original order at every
-// rebuild step of the recorded run plus its final state, one segment of
-// recomputed positions in sorted order, the cotangents and the parameter
-// gradient accumulators.
+// rebuild step of the recorded run plus its final state, the positions of
+// every step in the sorted order of its rebuild interval, the cotangents and
+// the parameter gradient accumulators.
 struct AdjBuf {
     double *ckpt;   // [(nseg + 1) * 6 * nt]
-    double *traj;   // [(R + 1) * 3 * ntp]
+    double *traj;   // [(nsteps + 1) * 3 * ntp]: slot k holds x_k (slot 0 unused)
     Pos lx, wa, wb; // sorted order, ntp each
     double *lo;     // [6 * nt] cotangents in original order
     double *partials;
@@ -489,7 +506,7 @@ size_t carve_adj(const Dims &d, int32_t R, int32_t nsteps, char *base, AdjBuf *o
     const int32_t nseg = (nsteps + R - 1) / R;
     AdjBuf a{};
     a.ckpt = (double *)take(size_t(nseg + 1) * 6 * nt * 8);
-    a.traj = (double *)take(size_t(R + 1) * 3 * np * 8);
+    a.traj = (double *)take(size_t(nsteps + 1) * 3 * np * 8);
     Pos *ps[3] = {&a.lx, &a.wa, &a.wb};
     for (Pos *p : ps) {
         p->x = (double *)take(np * 8);
@@ -567,6 +584,13 @@ void drop_segs(tmd_system *s) {
     s->segs.clear();
 }
 
+// After a force launch that kicked velocities: the Spring-Dashpot model
+// wrote them to the other half.
+void kicked(tmd_system *s) {
+    if (s->d.model == TMD_MODEL_SPRING_DASHPOT)
+        s->cur.v = 1 - s->cur.v;
+}
+
 // One rebuild interval of tmd_integrate's loop, starting right after a step
 // whose number is a multiple of the interval: interval - 1 fused steps, the
 // rebuild, and the fused step after it.
@@ -581,6 +605,7 @@ tmd_status enqueue_interval(tmd_system *s, hipStream_t hs) {
         if (e != hipSuccess)
             return hip_fail(s, e, "force");
         s->cur.x = 1 - s->cur.x;
+        kicked(s);
     }
     return TMD_OK;
 }
@@ -859,6 +884,7 @@ tmd_status tmd_integrate(tmd_system *s, int32_t n_steps, int32_t thermo_every, d
             return hip_fail(s, e, "force");
         if (mode == 2)
             s->cur.x = 1 - s->cur.x;
+        kicked(s);
         if (th) {
             run.close();
             Timed t(s, TMD_T_THERMO, hs);
@@ -888,7 +914,8 @@ tmd_status tmd_get_state(const tmd_system *cs, double *const pos[3], double *con
             return hip_fail(s, e, "get_state");
     }
     if (vel) {
-        hipError_t e = launch_unload(s->d, s->b.vx[o], s->b.vy[o], s->b.vz[o], s->b.orig[o], vel, hs);
+        const int v = s->cur.v;
+        hipError_t e = launch_unload(s->d, s->b.vx[v], s->b.vy[v], s->b.vz[v], s->b.orig[o], vel, hs);
         if (e != hipSuccess)
             return hip_fail(s, e, "get_state");
     }
@@ -972,7 +999,8 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
         build_threads > kMaxThreads || build_threads % 64 != 0 || lds_atoms < 0 || lds_atoms > kMaxCap ||
         lds_atoms % 64 != 0 || (block_edge != 0 && block_edge != 2 && block_edge != 3) ||
         (block_parts != 0 && block_parts != 1 && block_parts != 2 && block_parts != 4) ||
-        (lanes_per_atom != 0 && lanes_per_atom != 1 && lanes_per_atom != 2 && lanes_per_atom != 4))
+        (lanes_per_atom != 0 && lanes_per_atom != 1 && lanes_per_atom != 2 && lanes_per_atom != 4) ||
+        (lanes_per_atom > 1 && s->d.model == 1))
         return TMD_EINVAL;
     if (block_edge != 0 && block_edge != s->d.edge) {
         layout_blocks(s, block_edge);  // resets threads and capacity to that edge's defaults
@@ -1013,7 +1041,10 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
 // buffer, and write the spare position buffer: the state is not changed.
 static hipError_t time_force(tmd_system *s, int32_t repeats, hipStream_t hs, hipEvent_t a, hipEvent_t b, float &ms) {
     Buffers &bf = s->b;
-    const int c = s->cur.x, o = s->cur.o;
+    const int c = s->cur.x, o = s->cur.v;
+    // the Spring-Dashpot kernel would kick into the state's own velocity
+    // half: time its force-only launch (the same pair work)
+    const int mode = s->d.model == TMD_MODEL_SPRING_DASHPOT ? 0 : 2;
     const size_t bytes = size_t(s->d.nt) * sizeof(double);
     hipError_t e = hipMemcpyAsync(bf.vx[1 - o], bf.vx[o], bytes, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess)
@@ -1021,11 +1052,11 @@ static hipError_t time_force(tmd_system *s, int32_t repeats, hipStream_t hs, hip
     if (e == hipSuccess)
         e = hipMemcpyAsync(bf.vz[1 - o], bf.vz[o], bytes, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess)  // warm-up
-        e = launch_force_at(s->d, bf, bf.pos(c), bf.pos(1 - c), 1 - o, 2, false, hs);
+        e = launch_force_at(s->d, bf, bf.pos(c), bf.pos(1 - c), 1 - o, mode, false, hs);
     if (e == hipSuccess)
         e = hipEventRecord(a, hs);
     for (int32_t r = 0; r < repeats && e == hipSuccess; ++r)
-        e = launch_force_at(s->d, bf, bf.pos(c), bf.pos(1 - c), 1 - o, 2, false, hs);
+        e = launch_force_at(s->d, bf, bf.pos(c), bf.pos(1 - c), 1 - o, mode, false, hs);
     if (e == hipSuccess)
         e = hipEventRecord(b, hs);
     if (e == hipSuccess)
@@ -1100,7 +1131,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
             }
             s->d.bthreads = bt_best;
             s->d.blanes = bl_best;
-            for (int32_t Lp = 1; Lp <= 4 && e == hipSuccess; Lp *= 2) {
+            for (int32_t Lp = 1; Lp <= (s->d.model == 1 ? 1 : 4) && e == hipSuccess; Lp *= 2) {
                 s->d.lpa = Lp;
                 // from one lane group per mean block atom (in whole
                 // wavefronts) up to two wavefronts more: fewer threads put
@@ -1149,6 +1180,8 @@ tmd_status tmd_set_lj_params(tmd_system *s, const double *epsilon, const double 
         return st;
     if (!epsilon || !sigma)
         return fail(s, TMD_EINVAL, "set_lj_params: NULL array");
+    if (s->d.model != TMD_MODEL_LJ)
+        return fail(s, TMD_EINVAL, "set_lj_params: the system uses the Spring-Dashpot model");
     for (int32_t k = 0; k < s->d.nbox; ++k)
         if (!positive(epsilon[k]) || !positive(sigma[k]))
             return fail(s, TMD_EINVAL, "set_lj_params: epsilon and sigma must be finite and positive");
@@ -1177,6 +1210,8 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
     if (n_steps < 1 || !ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 ||
         bytes < carve_adj(s->dmax,s->rebuild_every, n_steps, nullptr, nullptr))
         return fail(s, TMD_EINVAL, "adjoint_forward: n_steps < 1 or workspace missing, misaligned or too small");
+    if (s->d.model != TMD_MODEL_LJ)
+        return fail(s, TMD_EINVAL, "adjoint_forward: gradients are implemented for the Lennard-Jones model only");
     const int32_t R = s->rebuild_every;
     if (s->step % R != 0)
         return fail(s, TMD_ESTATE, "adjoint_forward: the step counter must be a multiple of rebuild_every");
@@ -1184,22 +1219,68 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
     AdjBuf a{};
     carve_adj(s->dmax,R, n_steps, static_cast<char *>(ws), &a);
     const int32_t nseg = (n_steps + R - 1) / R;
-    const size_t nt = size_t(s->d.nt);
-    s->list_valid = s->force_valid = false;  // the run starts from a list built at its first positions
+    const size_t nt = size_t(s->d.nt), np = size_t(s->d.ntp);
     const int64_t step0 = s->step;
-    for (int32_t m = 0; m <= nseg; ++m) {
+    Buffers &b = s->b;
+    // every stored position buffer carries the NaN sentinel atom (slot nt)
+    // that padding of 32-bit lists points at
+    hipError_t e = launch_traj_sentinels(a.traj, np, s->d.nt, n_steps, hs);
+    auto slot = [&](int32_t k) {
+        double *t = a.traj + size_t(k) * 3 * np;
+        return Pos{t, t + np, t + 2 * np};
+    };
+    // Each interval starts from its checkpoint, reloaded and binned as the
+    // backward pass will bin it (the same list and atom order), and runs the
+    // velocity-Verlet steps of tmd_integrate with explicit output buffers:
+    // x_{k+1} of every step goes to store slot k + 1, in the interval's
+    // sorted order.  The interval's last step then finishes as tmd_integrate
+    // finishes it (rebuild at a rebuild step, force and closing kick).
+    for (int32_t m = 0; m < nseg && e == hipSuccess; ++m) {
+        const int32_t k_lo = m * R, len = std::min(R, n_steps - k_lo);
         double *c = a.ckpt + size_t(m) * 6 * nt;
         double *const po[3] = {c, c + nt, c + 2 * nt};
         double *const vo[3] = {c + 3 * nt, c + 4 * nt, c + 5 * nt};
         if ((st = tmd_get_state(s, po, vo, nullptr, stream)) != TMD_OK)
             return st;
-        if (m < nseg) {
-            const int32_t k = std::min(R, n_steps - m * R);
-            if ((st = tmd_integrate(s, k, 0, nullptr, stream)) != TMD_OK)
-                return st;
+        const double *const pi[3] = {po[0], po[1], po[2]};
+        const double *const vi[3] = {vo[0], vo[1], vo[2]};
+        e = launch_load_state(s->d, pi, vi, b, Cursor{}, hs);
+        s->cur = Cursor{};
+        if (e == hipSuccess && (st = rebuild(s, hs)) != TMD_OK)
+            return st;
+        const int o = s->cur.v;
+        const Pos x0 = b.pos(s->cur.x);
+        auto traj = [&](int32_t j) { return j == 0 ? x0 : slot(k_lo + j); };
+        if (e == hipSuccess)
+            e = launch_force_at(s->d, b, x0, x0, o, 0, false, hs);
+        if (e == hipSuccess)
+            e = launch_drift_at(s->d, b, x0, traj(1), o, hs);
+        for (int32_t j = 1; j < len && e == hipSuccess; ++j)
+            e = launch_force_at(s->d, b, traj(j), traj(j + 1), o, 2, false, hs);
+        // step k_lo + len: its positions become the system's
+        const Pos xe = traj(len), xs = b.pos(s->cur.x);
+        for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+            const double *src = q == 0 ? xe.x : (q == 1 ? xe.y : xe.z);
+            double *dst = q == 0 ? xs.x : (q == 1 ? xs.y : xs.z);
+            e = hipMemcpyAsync(dst, src, nt * sizeof(double), hipMemcpyDeviceToDevice, hs);
         }
+        if (e == hipSuccess && (step0 + k_lo + len) % R == 0 && (st = rebuild(s, hs)) != TMD_OK)
+            return st;
+        if (e == hipSuccess)
+            e = launch_force(s->d, b, s->cur, 1, false, hs);
+        s->force_valid = true;
+        s->step = step0 + k_lo + len;
     }
-    (void)hs;
+    if (e != hipSuccess)
+        return hip_fail(s, e, "adjoint_forward");
+    {
+        double *c = a.ckpt + size_t(nseg) * 6 * nt;
+        double *const po[3] = {c, c + nt, c + 2 * nt};
+        double *const vo[3] = {c + 3 * nt, c + 4 * nt, c + 5 * nt};
+        if ((st = tmd_get_state(s, po, vo, nullptr, stream)) != TMD_OK)
+            return st;
+    }
+    s->gen++;
     s->adj.recorded = true;
     s->adj.step0 = step0;
     s->adj.nsteps = n_steps;
@@ -1228,10 +1309,6 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
     carve_adj(s->dmax,R, T, static_cast<char *>(ws), &a);
     Buffers &b = s->b;
     hipError_t e = launch_fill_f64(a.acc, 0.0, 2 * s->d.nbox, hs);
-    // the recomputed positions of a segment go to the trajectory store, whose
-    // buffers need the NaN sentinel atom that list padding points at
-    if (e == hipSuccess)
-        e = launch_traj_sentinels(a.traj, s->d.ntp, s->d.nt, R, hs);
     double *const lo_x[3] = {a.lo, a.lo + nt, a.lo + 2 * nt};
     double *const lo_v[3] = {a.lo + 3 * nt, a.lo + 4 * nt, a.lo + 5 * nt};
     Pos wa = a.wa, wb = a.wb;
@@ -1258,7 +1335,8 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
         e = launch_unload(s->d, wa.x, wa.y, wa.z, b.orig[s->cur.o], lo_v, hs);
     for (int32_t m = nseg - 1; m >= 0 && e == hipSuccess; --m) {
         const int32_t k_lo = m * R, k_hi = std::min((m + 1) * R, T) - 1;
-        // restore the checkpoint, rebuild the same list, recompute positions
+        // restore the checkpoint and rebuild the interval's list (and atom
+        // order); its positions are in the store
         const double *c = a.ckpt + size_t(m) * 6 * nt;
         const double *const po[3] = {c, c + nt, c + 2 * nt};
         const double *const vo[3] = {c + 3 * nt, c + 4 * nt, c + 5 * nt};
@@ -1270,18 +1348,10 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
         auto traj = [&](int32_t j) {
             if (j == 0)
                 return b.pos(s->cur.x);
-            double *t = a.traj + size_t(j) * 3 * np;
+            double *t = a.traj + size_t(k_lo + j) * 3 * np;
             return Pos{t, t + np, t + 2 * np};
         };
         const int o = s->cur.o;
-        if (k_hi > k_lo) {
-            if (e == hipSuccess)
-                e = launch_force_at(s->d, b, traj(0), traj(0), o, 0, false, hs);
-            if (e == hipSuccess)
-                e = launch_drift_at(s->d, b, traj(0), traj(1), o, hs);
-            for (int32_t j = 1; j < k_hi - k_lo && e == hipSuccess; ++j)
-                e = launch_force_at(s->d, b, traj(j), traj(j + 1), o, 2, false, hs);
-        }
         if (e == hipSuccess)
             e = launch_gather(s->d, lo_x, b.orig[o], a.lx, hs);
         if (e == hipSuccess)
@@ -1373,6 +1443,7 @@ tmd_status tmd_compute_forces_static(const tmd_params *p, int64_t n_atoms, doubl
     d.nbox = 1;
     d.maxnb = p->max_neighbors;
     d.nchunk = (d.maxnb + 3) / 4 + 1;
+    d.model = p->model;
     if (!layout_dims(&B, 1, default_edge(&B, 1), d))
         return TMD_EINVAL;
     if (carve(d, nullptr, nullptr) > size_t(TMD_STATIC_SCRATCH_BYTES))
@@ -1398,6 +1469,7 @@ tmd_status tmd_compute_forces_static(const tmd_params *p, int64_t n_atoms, doubl
         e = launch_bin(d, b, cur, false, hs);
     cur.x = 1 - cur.x;
     cur.o = 1 - cur.o;
+    cur.v = 1 - cur.v;
     if (e == hipSuccess)
         e = launch_build(d, b, cur, hs);
     if (e == hipSuccess)

@@ -140,6 +140,19 @@ __device__ __forceinline__ int cell_coord(double p, double side, int nc) {
     return int(q);
 }
 
+// Subcell index along one axis (cells cut in halves of side hs = side / 2),
+// clamped to [0, 2 nc).  hs is side scaled by a power of two, so p / hs is
+// exactly 2 (p / side) and the subcell's cell, the index >> 1, is
+// cell_coord(p, side, nc).
+__device__ __forceinline__ int sub_coord(double p, double hs, int nc) {
+    double q = floor(p / hs);
+    if (!(q >= 0.0))
+        q = 0.0;
+    if (q > double(2 * nc - 1))
+        q = double(2 * nc - 1);
+    return int(q);
+}
+
 // Distinct cells c-1, c, c+1 (periodic) along one axis; fewer when the axis
 // has fewer than three cells, so no cell is visited twice.
 __device__ __forceinline__ int stencil_axis(int c, int nc, int out[3]) {

@@ -81,13 +81,6 @@ __device__ __forceinline__ int hood_axis(int c0, int e, int nc, int out[kAxis]) 
     return n;
 }
 
-__device__ __forceinline__ int axis_index(const int a[kAxis], int n, int v) {
-    int r = 0;
-    for (int q = 0; q < n; ++q)
-        r = (a[q] == v) ? q : r;
-    return r;
-}
-
 // Neighborhood axes of local block lb (uniform across the workgroup).
 __device__ __forceinline__ void hood_axes(const Box &B, int lb, int n[3], int co[3][kAxis]) {
     const int nbx = B.nbx;
@@ -137,8 +130,8 @@ __device__ __forceinline__ void hood_setup(const Box &B, int lb, const int32_t *
         const int first = B.cell_off + lb * cpb;
         int a01[2] = {0, 0};
         if (threadIdx.x == 0) {
-            a01[0] = cell_start[first];
-            a01[1] = cell_start[first + cpb];
+            a01[0] = cell_start[first * kSub];
+            a01[1] = cell_start[(first + cpb) * kSub];
         }
         int cs[2] = {0, 0}, cnt[2] = {0, 0};
 #pragma unroll
@@ -146,9 +139,9 @@ __device__ __forceinline__ void hood_setup(const Box &B, int lb, const int32_t *
             const int u = threadIdx.x + 64 * half;
             if (u < nh) {
                 const int ix = u % n[0], iy = (u / n[0]) % n[1], iz = u / (n[0] * n[1]);
-                const int sl = cell_slot(B, co[0][ix], co[1][iy], co[2][iz]);
+                const int sl = cell_slot(B, co[0][ix], co[1][iy], co[2][iz]) * kSub;
                 cs[half] = cell_start[sl];
-                cnt[half] = cell_start[sl + 1];
+                cnt[half] = cell_start[sl + kSub];
             }
         }
         int base = 0;
@@ -487,9 +480,10 @@ __global__ __launch_bounds__(kAtomThreads) void k_bin_count(Dims d, const Box *_
     const double px = wrap(x[i], B.L), py = wrap(y[i], B.L), pz = wrap(z[i], B.L);
     if (!(isfinite(px) && isfinite(py) && isfinite(pz)))
         atomicOr(err, kErrNonFinite);
-    const int c = cell_slot(B, cell_coord(px, B.side, B.nc), cell_coord(py, B.side, B.nc),
-                            cell_coord(pz, B.side, B.nc));
-    cell_of[i] = c;
+    const int sx = sub_coord(px, B.hside, B.nc), sy = sub_coord(py, B.hside, B.nc),
+              sz = sub_coord(pz, B.hside, B.nc);
+    const int c = cell_slot(B, sx >> 1, sy >> 1, sz >> 1) * kSub + ((sz & 1) * 2 + (sy & 1)) * 2 + (sx & 1);
+    cell_of[i] = c;  // bin slot: cell slot and subcell
     // One atomic per distinct cell of the wavefront (atoms arrive nearly
     // cell-sorted, so a wavefront spans a few cells): the first remaining
     // lane's cell is counted for every lane that shares it, and those lanes
@@ -576,21 +570,28 @@ __global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nt, int32
 }
 
 // The whole scan in one workgroup, for up to kScanOne counts: each thread
-// loads a contiguous run of at most kScanOne / 1024 of them at once, the
-// workgroup scans the run totals, and each thread writes its run's offsets
-// to cell_start[0..n] and clears its counts for the next binning (so that
-// binning needs no separate fill).
+// sums a contiguous run of at most kScanOne / 1024 of them, the workgroup
+// scans the run totals, and each thread reads its run again (from the
+// cache), writes its offsets to cell_start[0..n] and clears its counts for
+// the next binning (so that binning needs no separate fill).  The run is
+// read in batches of 32 whose loads are all in flight together (holding 64
+// counts a thread in registers at once would spill; a plain loop would wait
+// out one load after another).
 __global__ __launch_bounds__(1024) void k_scan_one(int32_t *counts, int32_t *out, int n) {
-    constexpr int M = kScanOne / 1024;
-    __shared__ int32_t sh[1024];
+    constexpr int M = 32;
+    __shared__ int32_t sh[32];
     const int t = threadIdx.x;
-    const int per = (n + 1023) / 1024;  // <= M
-    const int b0 = t * per;
-    int v[M], tot = 0;
+    const int per = (n + 1023) / 1024;  // <= kScanOne / 1024
+    const int b0 = t * per, b1 = min(b0 + per, n);
+    int tot = 0;
+    for (int base = b0; base < b1; base += M) {
+        int v[M];
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-        v[q] = (q < per && b0 + q < n) ? counts[b0 + q] : 0;
-        tot += v[q];
+        for (int q = 0; q < M; ++q)
+            v[q] = base + q < b1 ? counts[base + q] : 0;
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+            tot += v[q];
     }
     // run totals scanned within each wavefront, then across the 16 of them
     const int lane = t & 63, wv = t >> 6;
@@ -606,13 +607,18 @@ __global__ __launch_bounds__(1024) void k_scan_one(int32_t *counts, int32_t *out
     }
     __syncthreads();
     int run = sh[16 + wv] + incl - tot;
+    for (int base = b0; base < b1; base += M) {
+        int v[M];
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-        if (q < per && b0 + q < n) {
-            out[b0 + q] = run;
-            counts[b0 + q] = 0;
-        }
-        run += v[q];
+        for (int q = 0; q < M; ++q)
+            v[q] = base + q < b1 ? counts[base + q] : 0;
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+            if (base + q < b1) {
+                out[base + q] = run;
+                counts[base + q] = 0;
+                run += v[q];
+            }
     }
     if (t == 1023)
         out[n] = run;
@@ -632,9 +638,9 @@ __global__ __launch_bounds__(kAtomThreads) void k_scatter(int n, const int32_t *
         tmp_idx[cell_start[cell_of[i]] + slot[i]] = i;
 }
 
-// Atomic arrival order inside a cell is not reproducible: each atom's final
-// place is its cell start plus the number of cell members with a smaller
-// original id.  Then positions, velocities and ids move to that place.  The
+// Atomic arrival order inside a bin (a cell's subcell) is not reproducible:
+// each atom's final place is its bin start plus the number of bin members
+// with a smaller original id.  Then positions, velocities and ids move to that place.  The
 // ids of the workgroup's own arrival slots are staged in LDS first, so only
 // cells that straddle a workgroup boundary read members from global memory.
 __global__ __launch_bounds__(kAtomThreads) void k_rank_permute(
@@ -681,57 +687,345 @@ __device__ __forceinline__ Box block_box(const Dims &d, const Box *__restrict__ 
     return boxes[d.nbox == 1 ? 0 : blk_box[b]];
 }
 
-// One workgroup per block, BL lanes per atom (1 or 2): every j != i in the
-// distinct cells of i's 27-cell stencil with s < (cutoff + skin)^2 enters
-// i's list.  Candidates come from the LDS copy of the neighborhood (lanes of
-// one cell read the same candidate, a broadcast); list entries are 16-bit
-// LDS slots, or 32-bit global indices when the neighborhood did not fit.
-// Both lane counts write the same list: entries in the order of the
-// stencil's runs and, within a run, of the LDS slots.
-// One run of consecutive LDS slots [beg, end) of atom i's stencil, one lane
-// per atom: four candidates per round, their LDS reads issued together and
-// unconditional (up to three slots past the run's end: other atoms, the
-// sentinel, pad or unused slots, all failing the t < end test).  Accepted
-// slots go to the 16-bit list at wp, entry c.  MIC: the neighborhood may
-// wrap the box, so the difference takes the minimum image; without it no
-// raw difference along an axis exceeds L/2 and the image test is dropped
-// (it could only recompute the same value).
-template <bool MIC>
-__device__ __forceinline__ void build_run1(lds_double *S, int beg, int end, int self, double xi, double yi,
-                                           double zi, const Box &B, int maxnb, uint16_t *&wp, int &c) {
-    for (int t0 = beg; t0 < end; t0 += 4) {
-        const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t0), 24u);
-        double px[4], py[4], pz[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const lds_double *q = (const lds_double *)(pb + r * 24);
-            px[r] = q[0];
-            py[r] = q[1];
-            pz[r] = q[2];
+// Neighbor-list build.  Every j != i within (cutoff + skin) of i enters i's
+// list (Sec. 3.2, Fig. 1).  The cells are cut in 2 x 2 x 2 subcells of side
+// >= (cutoff + skin) / 2 - smaller cells with a larger stencil, as the
+// footnote to Fig. 1 allows - so every partner lies within +-2 subcells
+// along each axis: 125 subcells, about 0.56 of the volume of the 27 cells
+// (boxes of two cells per axis have four distinct subcells per axis, all
+// of them).  Candidates are visited in one canonical order, the same on
+// every path and schedule: for dz, then dy, then dx in -2 .. 2 (distinct
+// subcells only, in that order), the subcell's atoms in memory order (bins
+// are sorted by original id).  So lists, and the force sums that follow
+// them, do not depend on the schedule.
+//
+// Subcell rows (the common path): the workgroup copies its neighborhood
+// into LDS ordered by subcell rows (z, then y, then x fastest), so the x
+// subcells of each of i's (y, z) rows are one run of consecutive slots (two
+// where a small box's row wraps).  Each lane walks its own runs back to
+// back, four candidates per round, so short runs cost no wait for the
+// wavefront's longest run.  Next to each position the copy keeps the
+// atom's slot in the force kernel's neighborhood copy (cells in table
+// order), which is what the list stores.
+//
+// Global gathers: neighborhoods too crowded for the row copy (26 bytes a
+// slot and the subcell offsets, within the area sized for the force
+// kernel's 24) read candidates from memory in the same order; they store
+// force-kernel slots when the force kernel stages the neighborhood, else
+// 32-bit global indices.
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+
+// Exclusive prefix sum of n 16-bit counts in LDS, in place, with a[n] = the
+// total; wsum is LDS scratch of kMaxThreads / 64 ints.  Ends with a barrier.
+__device__ __forceinline__ void scan_excl_u16(lds_u16 *a, int n, int *wsum) {
+    const int T = blockDim.x, K = (n + T - 1) / T, b0 = threadIdx.x * K;
+    int tot = 0;
+    for (int q = 0; q < K; ++q)
+        tot += (b0 + q < n) ? int(a[b0 + q]) : 0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int incl = wave_prefix_incl(tot);
+    if (lane == 63)
+        wsum[wv] = incl;
+    __syncthreads();
+    int run = incl - tot;
+    for (int w = 0; w < wv; ++w)
+        run += wsum[w];
+    for (int q = 0; q < K; ++q)
+        if (b0 + q < n) {
+            const int v = a[b0 + q];
+            a[b0 + q] = uint16_t(run);
+            run += v;
         }
+    if (threadIdx.x == T - 1)
+        a[n] = uint16_t(run);
+    __syncthreads();
+}
+
+// Subcell grid of a block neighborhood.  Along each axis the neighborhood
+// holds the distinct cells c0 - 1, c0, ... (periodic), n = min(e + 2, nc)
+// of them (hood_axes() lists them in this order), two subcells each: grid
+// index g along an axis is the box subcell (2 c0 - 2 + g) mod 2 nc.
+struct SubGrid {
+    int c0[3];  // first own cell per axis
+    int n[3];   // neighborhood cells per axis
+    int nx, ny, nz, ng;
+    int nsub;   // subcells per box axis, 2 nc
+    int m;      // distinct stencil subcells per axis: min(5, nsub)
+};
+
+__device__ __forceinline__ SubGrid sub_grid(const Box &B, int lb) {
+    SubGrid G;
+    const int nbx = B.nbx;
+    const int bc[3] = {lb % nbx, (lb / nbx) % nbx, lb / (nbx * nbx)};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double dx, dy, dz;
-            double s;
-            if (MIC) {
-                s = pair_delta(xi, yi, zi, px[r], py[r], pz[r], B.L, B.halfL, B.halfL2, dx, dy, dz);
-            } else {
-                dx = xi - px[r];
-                dy = yi - py[r];
-                dz = zi - pz[r];
-                s = dist2(dx, dy, dz);
+    for (int a = 0; a < 3; ++a) {
+        G.c0[a] = B.edge * bc[a];
+        G.n[a] = min(min(B.edge, B.nc - G.c0[a]) + 2, B.nc);
+    }
+    G.nx = 2 * G.n[0];
+    G.ny = 2 * G.n[1];
+    G.nz = 2 * G.n[2];
+    G.ng = G.nx * G.ny * G.nz;
+    G.nsub = 2 * B.nc;
+    G.m = min(5, G.nsub);
+    return G;
+}
+
+__device__ __forceinline__ int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Bin slot of grid subcell g, and the neighborhood cell (table index) it
+// lies in.
+__device__ __forceinline__ int sub_bin(const Box &B, const SubGrid &G, int g, int &u) {
+    const int gx = g % G.nx, r = g / G.nx, gy = r % G.ny, gz = r / G.ny;
+    const int kx = gx >> 1, ky = gy >> 1, kz = gz >> 1;
+    const int cx = wrap_index(G.c0[0] - 1 + kx, B.nc), cy = wrap_index(G.c0[1] - 1 + ky, B.nc),
+              cz = wrap_index(G.c0[2] - 1 + kz, B.nc);
+    u = (kz * G.n[1] + ky) * G.n[0] + kx;
+    return cell_slot(B, cx, cy, cz) * kSub + ((gz & 1) * 2 + (gy & 1)) * 2 + (gx & 1);
+}
+
+// Copy the neighborhood into LDS in subcell-row order: positions at S (24
+// bytes a slot) and each atom's slot in the force kernel's copy at F;
+// soff[g] = first slot of grid subcell g, soff[ng] = atoms staged.  Ends
+// with a barrier.
+__device__ __forceinline__ void sub_stage(const Box &B, const SubGrid &G, const Hood &h,
+                                          const int32_t *__restrict__ cell_start, const double *__restrict__ x,
+                                          const double *__restrict__ y, const double *__restrict__ z,
+                                          lds_double *S, lds_u16 *F, lds_u16 *soff, int *wsum) {
+    const int T = blockDim.x;
+    for (int g = threadIdx.x; g < G.ng; g += T) {
+        int u;
+        const int bs = sub_bin(B, G, g, u);
+        soff[g] = uint16_t(cell_start[bs + 1] - cell_start[bs]);
+    }
+    __syncthreads();
+    scan_excl_u16(soff, G.ng, wsum);
+    for (int g = threadIdx.x; g < G.ng; g += T) {
+        int u;
+        const int bs = sub_bin(B, G, g, u);
+        const int st = cell_start[bs], n = cell_start[bs + 1] - st;
+        const int dst = soff[g], fb = h.off[u] + (st - h.cs[u]);
+        for (int k = 0; k < n; ++k) {
+            lds_double *a = lds_slot(S, dst + k);
+            a[0] = x[st + k];
+            a[1] = y[st + k];
+            a[2] = z[st + k];
+            F[dst + k] = uint16_t(fb + k);
+        }
+    }
+    __syncthreads();
+}
+
+// Distance test of a candidate: MIC takes the minimum image of the raw
+// difference; without it no raw difference along an axis exceeds L/2.
+template <bool MIC>
+__device__ __forceinline__ double cand_dist2(double xi, double yi, double zi, double xj, double yj, double zj,
+                                             const Box &B) {
+    double dx, dy, dz;
+    if (MIC)
+        return pair_delta(xi, yi, zi, xj, yj, zj, B.L, B.halfL, B.halfL2, dx, dy, dz);
+    return dist2(xi - xj, yi - yj, zi - zj);
+}
+
+// Entry c of the 16-bit list at wp (the next element, or the first element
+// of the next 16-byte row of the tile), if it is within capacity.
+__device__ __forceinline__ void put16(uint16_t *&wp, int &c, int maxnb, int v) {
+    if (c < maxnb)
+        *wp = uint16_t(v);
+    wp += ((c & 7) == 7) ? 505 : 1;
+    ++c;
+}
+
+// Where atom i's runs lie in the subcell-row copy: grid coordinates of the
+// current row, the first subcell of its x-run, the stencil offsets walked so
+// far, and the run's split where a small box's row wraps.
+struct RowWalk {
+    int gz, gy, xs;  // grid z, y of the current row; grid x of the run's first subcell
+    int kz, ky;      // stencil offsets walked so far along z, y
+    int xa, xb;      // run lengths in subcells: [xs, xs + xa), then [0, xb) where the row wraps
+    int piece;       // 0: first part of the row, 1: the wrapped part
+};
+
+// Slots [t, e) of the run w points at.
+__device__ __forceinline__ void row_run(const SubGrid &G, const lds_u16 *soff, const RowWalk &w, int &t, int &e) {
+    const int rb = (w.gz * G.ny + w.gy) * G.nx;
+    const int a = rb + (w.piece ? 0 : w.xs), len = w.piece ? w.xb : w.xa;
+    t = soff[a];
+    e = soff[a + len];
+}
+
+// The run after w's (selects only); false after the last.
+__device__ __forceinline__ bool row_next(const SubGrid &G, int gy0, RowWalk &w) {
+    const bool second = w.piece == 0 && w.xb > 0;  // the wrapped part of this row
+    const bool newz = !second && w.ky + 1 == G.m;
+    const bool last = newz && w.kz + 1 == G.m;
+    const int gy1 = w.gy + 1 == G.ny ? 0 : w.gy + 1, gz1 = w.gz + 1 == G.nz ? 0 : w.gz + 1;
+    w.gy = second ? w.gy : (newz ? gy0 : gy1);
+    w.ky = second ? w.ky : (newz ? 0 : w.ky + 1);
+    w.gz = newz && !last ? gz1 : w.gz;
+    w.kz = newz && !last ? w.kz + 1 : w.kz;
+    w.piece = second ? 1 : 0;
+    return !last;
+}
+
+// Atom i's runs in the subcell-row copy, one lane per atom (BL = 1) or two
+// lanes testing alternate candidates (BL = 2, lane p).  A round reads four
+// (eight) consecutive slots unconditionally, up to three (seven) past the
+// run's end, which the t < e test rejects; the self test compares the
+// force-kernel slot.  Every round also looks up where the next run lies and
+// takes it if this one is done: one straight loop, so a lane whose run
+// ended moves on while the others finish theirs (branching to the next run
+// instead lets the compiler nest a loop over each run's rounds, which the
+// whole wavefront then waits out).  WRAP: the neighborhood grid covers the
+// whole box along some axis (rows and runs wrap); else each of the 25 runs
+// is the five subcells x - 2 .. x + 2 of row (y + dy, z + dz).  Returns the
+// number of neighbors found.
+template <int BL, bool MIC, bool WRAP>
+__device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const lds_u16 *soff, const SubGrid &G,
+                                          int gx, int gy, int gz, int fself, double xi, double yi, double zi,
+                                          const Box &B, int maxnb, int p, uint16_t *nbr16, int i, int nchunk) {
+    RowWalk w;
+    w.gz = wrap_index(gz - 2, G.nz);
+    w.gy = wrap_index(gy - 2, G.ny);
+    w.xs = wrap_index(gx - 2, G.nx);
+    w.xa = min(G.m, G.nx - w.xs);
+    w.xb = G.m - w.xa;
+    w.kz = w.ky = w.piece = 0;
+    const int gy0 = w.gy;
+    // without wrapping: run r starts at table index idx, the next at idx + nx
+    // (+ nx (ny - 5) after every fifth)
+    int idx = (w.gz * G.ny + w.gy) * G.nx + w.xs, ky = 0, row = 0;
+    const int zskip = G.nx * (G.ny - 5), idx_max = G.ng - 5;
+    int t, e;
+    if (WRAP) {
+        row_run(G, soff, w, t, e);
+    } else {
+        t = soff[idx];
+        e = soff[idx + 5];
+    }
+    int c = 0;
+    uint16_t *wp = nbr16 + nbr_index16(i, 0, nchunk);
+    for (;;) {
+        if (BL == 1) {
+            const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t), 24u);
+            double px[4], py[4], pz[4];
+            int tr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const lds_double *q = (const lds_double *)(pb + r * 24);
+                px[r] = q[0];
+                py[r] = q[1];
+                pz[r] = q[2];
+                tr[r] = F[t + r];
             }
-            const int t = t0 + r;
-            if (s < B.rl2 && t < end && t != self) {
-                // entry c of the 16-bit list: the next element, or the
-                // first element of the next 16-byte row of the tile
-                if (c < maxnb)
-                    *wp = uint16_t(t);
-                wp += ((c & 7) == 7) ? 505 : 1;
-                ++c;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double s = cand_dist2<MIC>(xi, yi, zi, px[r], py[r], pz[r], B);
+                if (s < B.rl2 && t + r < e && tr[r] != fself)
+                    put16(wp, c, maxnb, tr[r]);
+            }
+            t += 4;
+        } else {
+            const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t + p), 24u);
+            double px[4], py[4], pz[4];
+            int tr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const lds_double *q = (const lds_double *)(pb + r * 48);
+                px[r] = q[0];
+                py[r] = q[1];
+                pz[r] = q[2];
+                tr[r] = F[t + p + 2 * r];
+            }
+            unsigned mine = 0;  // bit 2r + p: slot t + 2r + p accepted
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double s = cand_dist2<MIC>(xi, yi, zi, px[r], py[r], pz[r], B);
+                mine |= (s < B.rl2 && t + 2 * r + p < e && tr[r] != fself) ? (1u << (2 * r + p)) : 0u;
+            }
+            const unsigned m8 = mine | unsigned(__shfl_xor(int(mine), 1, 64));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = 2 * r + p;
+                if (mine & (1u << j)) {
+                    const int pos = c + __popc(m8 & ((1u << j) - 1u));
+                    if (pos < maxnb)
+                        nbr16[nbr_index16(i, pos, nchunk)] = uint16_t(tr[r]);
+                }
+            }
+            c += __popc(m8);
+            t += 8;
+        }
+        const bool adv = t >= e;
+        int nt, ne;
+        bool more;
+        if (WRAP) {
+            RowWalk w2 = w;
+            more = row_next(G, gy0, w2);
+            row_run(G, soff, w2, nt, ne);
+            w.gz = adv ? w2.gz : w.gz;
+            w.gy = adv ? w2.gy : w.gy;
+            w.kz = adv ? w2.kz : w.kz;
+            w.ky = adv ? w2.ky : w.ky;
+            w.piece = adv ? w2.piece : w.piece;
+        } else {
+            const int nidx = min(idx + G.nx + (ky == 4 ? zskip : 0), idx_max);
+            nt = soff[nidx];
+            ne = soff[nidx + 5];
+            more = row + 1 < 25;
+            idx = adv ? nidx : idx;
+            ky = adv ? (ky == 4 ? 0 : ky + 1) : ky;
+            row += adv ? 1 : 0;
+        }
+        if (adv && !more)
+            break;
+        t = adv ? nt : t;
+        e = adv ? ne : e;
+    }
+    return c;
+}
+
+// Atom i's candidates from memory, in the canonical order (the atom's
+// first lane alone).  fits: store force-kernel slots (16-bit), else global
+// indices (32-bit).  Returns the number of neighbors found.
+__device__ __forceinline__ int build_global(const Box &B, const SubGrid &G, const Hood &h, bool fits,
+                                            const int32_t *__restrict__ cell_start, const double *__restrict__ x,
+                                            const double *__restrict__ y, const double *__restrict__ z, int i,
+                                            double xi, double yi, double zi, int X, int Y, int Z, int maxnb,
+                                            int32_t *__restrict__ nbr, int nchunk) {
+    uint16_t *nbr16 = reinterpret_cast<uint16_t *>(nbr);
+    int c = 0;
+    for (int kz = 0; kz < G.m; ++kz) {
+        const int sz = wrap_index(Z - 2 + kz, G.nsub);
+        for (int ky = 0; ky < G.m; ++ky) {
+            const int sy = wrap_index(Y - 2 + ky, G.nsub);
+            for (int kx = 0; kx < G.m; ++kx) {
+                const int sx = wrap_index(X - 2 + kx, G.nsub);
+                const int cx = sx >> 1, cy = sy >> 1, cz = sz >> 1;
+                const int bs = cell_slot(B, cx, cy, cz) * kSub + ((sz & 1) * 2 + (sy & 1)) * 2 + (sx & 1);
+                const int st = cell_start[bs], en = cell_start[bs + 1];
+                // table index of the cell: its place along each neighborhood axis
+                const int u = (wrap_index(cz - G.c0[2] + 1, B.nc) * G.n[1] + wrap_index(cy - G.c0[1] + 1, B.nc)) *
+                                  G.n[0] +
+                              wrap_index(cx - G.c0[0] + 1, B.nc);
+                const int fb = h.off[u] - h.cs[u];
+                for (int g = st; g < en; ++g) {
+                    double dx, dy, dz;
+                    const double s = pair_delta(xi, yi, zi, x[g], y[g], z[g], B.L, B.halfL, B.halfL2, dx, dy, dz);
+                    if (s < B.rl2 && g != i) {
+                        if (c < maxnb) {
+                            if (fits)
+                                nbr16[nbr_index16(i, c, nchunk)] = uint16_t(fb + g);
+                            else
+                                nbr[nbr_index(i, c, nchunk)] = g;
+                        }
+                        ++c;
+                    }
+                }
             }
         }
     }
+    return c;
 }
 
 template <int BL>
@@ -743,6 +1037,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                                                        int32_t *__restrict__ hood_tab, int32_t *__restrict__ cnt,
                                                        int32_t *__restrict__ nbr, int32_t *err) {
     __shared__ Hood h;
+    __shared__ int wsum[kMaxThreads / 64];
     extern __shared__ double lds[];
     int b, part;
     if (!block_part(d, b, part))
@@ -756,131 +1051,51 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     h.share(part, d.parts, lo, hi);
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
+    const SubGrid G = sub_grid(B, lb);
+    // the row copy takes 26 bytes a slot (position, force-kernel slot) and
+    // the subcell offsets, within the area sized for the force kernel
+    const int nslot = total + 2 + kHoodPad;
+    const bool rows = fits && 26 * nslot + 2 * (G.ng + 1) <= 24 * (d.cap + 2 + kHoodPad);
     lds_double *S = (lds_double *)lds;
-    if (fits)
-        hood_stage(h, total, d.cap, x, y, z, S, hood_image(B, lb, false));
-    // list padding points at the NaN sentinel: LDS slot cap, or global slot nt
+    lds_u16 *F = (lds_u16 *)((lds_char *)lds + 24 * nslot);
+    lds_u16 *soff = F + nslot;
+    if (rows)
+        sub_stage(B, G, h, cell_start, x, y, z, S, F, soff, wsum);
+    // list padding points at the NaN sentinel: force-kernel LDS slot cap, or
+    // global slot nt
     const int sentinel = fits ? d.cap : d.nt;
     uint16_t *nbr16 = reinterpret_cast<uint16_t *>(nbr);
-    int n[3], co[3][kAxis];
-    hood_axes(B, lb, n, co);
     // no neighborhood cell range wraps the box and each spans at most half
     // of it: no raw difference along an axis exceeds L/2
-    bool interior = true;
-    {
-        const int nbx = B.nbx;
-        const int bc[3] = {lb % nbx, (lb / nbx) % nbx, lb / (nbx * nbx)};
-        for (int a = 0; a < 3; ++a) {
-            const int c0 = B.edge * bc[a];
-            const int e = min(B.edge, B.nc - c0);
-            interior &= c0 >= 1 && c0 + e <= B.nc - 1 && 2 * (e + 2) <= B.nc;
-        }
+    bool interior = true, wraps = false;
+    for (int a = 0; a < 3; ++a) {
+        const int c0 = G.c0[a], e = min(B.edge, B.nc - c0);
+        interior &= c0 >= 1 && c0 + e <= B.nc - 1 && 2 * (e + 2) <= B.nc;
+        wraps |= G.n[a] < e + 2;  // the neighborhood holds every cell of the axis
     }
     const int p = threadIdx.x & (BL - 1);  // lane of the atom's pair (BL = 2)
     for (int i = lo + threadIdx.x / BL; i < hi; i += blockDim.x / BL) {
         const double xi = x[i], yi = y[i], zi = z[i];
-        const int cx = cell_coord(xi, B.side, B.nc), cy = cell_coord(yi, B.side, B.nc),
-                  cz = cell_coord(zi, B.side, B.nc);
-        int st[3][3], ns[3];
-        {
-            int v[3];
-            ns[0] = stencil_axis(cx, B.nc, v);
-            for (int k = 0; k < ns[0]; ++k)
-                st[0][k] = axis_index(co[0], n[0], v[k]);
-            ns[1] = stencil_axis(cy, B.nc, v);
-            for (int k = 0; k < ns[1]; ++k)
-                st[1][k] = axis_index(co[1], n[1], v[k]);
-            ns[2] = stencil_axis(cz, B.nc, v);
-            for (int k = 0; k < ns[2]; ++k)
-                st[2][k] = axis_index(co[2], n[2], v[k]);
-        }
+        const int X = sub_coord(xi, B.hside, B.nc), Y = sub_coord(yi, B.hside, B.nc),
+                  Z = sub_coord(zi, B.hside, B.nc);
         int c = 0;
-        if (fits) {
-            const int hx = axis_index(co[0], n[0], cx);
-            const int us = (axis_index(co[2], n[2], cz) * n[1] + axis_index(co[1], n[1], cy)) * n[0] + hx;
-            const int self = h.off[us] + (i - h.cs[us]);
-            // The x-stencil cells of a row: one run of consecutive neighborhood
-            // cells (contiguous LDS slots) whenever their positions along the
-            // neighborhood axis are consecutive, else one run per cell.
-            int lo = st[0][0], hi = st[0][0];
-            for (int k = 1; k < ns[0]; ++k) {
-                lo = min(lo, st[0][k]);
-                hi = max(hi, st[0][k]);
-            }
-            const bool run = hi - lo + 1 == ns[0];
-            const int nrun = run ? 1 : ns[0];
-            uint16_t *wp = nbr16 + nbr_index16(i, 0, d.nchunk);
-            for (int kz = 0; kz < ns[2]; ++kz)
-                for (int ky = 0; ky < ns[1]; ++ky) {
-                    const int row = (st[2][kz] * n[1] + st[1][ky]) * n[0];
-                    for (int q = 0; q < nrun; ++q) {
-                        const int u0 = row + (run ? lo : st[0][q]), u1 = row + (run ? hi : st[0][q]);
-                        const int beg = h.off[u0], end = h.off[u1 + 1];
-                        if (BL == 2) {
-                            // the atom's two lanes test alternate slots, four each
-                            // per round of eight (reads up to seven slots past the
-                            // run's end: other atoms, the sentinel or the pad slots
-                            // after it, all failing the slot test); the accepted
-                            // slots of both, exchanged as bit masks, take their
-                            // places in slot order
-                            for (int t0 = beg; t0 < end; t0 += 8) {
-                                const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t0 + p), 24u);
-                                double px[4], py[4], pz[4];
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) {
-                                    const lds_double *q = (const lds_double *)(pb + r * 48);
-                                    px[r] = q[0];
-                                    py[r] = q[1];
-                                    pz[r] = q[2];
-                                }
-                                unsigned mine = 0;  // bit 2r + p: slot t0 + 2r + p accepted
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) {
-                                    double dx, dy, dz;
-                                    const double s = pair_delta(xi, yi, zi, px[r], py[r], pz[r], B.L, B.halfL,
-                                                                B.halfL2, dx, dy, dz);
-                                    const int t = t0 + 2 * r + p;
-                                    mine |= (s < B.rl2 && t < end && t != self) ? (1u << (2 * r + p)) : 0u;
-                                }
-                                const unsigned m8 = mine | unsigned(__shfl_xor(int(mine), 1, 64));
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) {
-                                    const int j = 2 * r + p;
-                                    if (mine & (1u << j)) {
-                                        const int pos = c + __popc(m8 & ((1u << j) - 1u));
-                                        if (pos < d.maxnb)
-                                            nbr16[nbr_index16(i, pos, d.nchunk)] = uint16_t(t0 + j);
-                                    }
-                                }
-                                c += __popc(m8);
-                            }
-                            continue;
-                        }
-                        if (interior)
-                            build_run1<false>(S, beg, end, self, xi, yi, zi, B, d.maxnb, wp, c);
-                        else
-                            build_run1<true>(S, beg, end, self, xi, yi, zi, B, d.maxnb, wp, c);
-                    }
-                }
-        } else if (p == 0) {  // (global gathers: the atom's first lane alone)
-            for (int kz = 0; kz < ns[2]; ++kz)
-                for (int ky = 0; ky < ns[1]; ++ky)
-                    for (int kx = 0; kx < ns[0]; ++kx) {
-                        const int u = (st[2][kz] * n[1] + st[1][ky]) * n[0] + st[0][kx];
-                        const int beg = h.off[u], end = h.off[u + 1];
-                        const int g0 = h.cs[u] - beg;
-                        for (int t = beg; t < end; ++t) {
-                            const int g = g0 + t;
-                            double dx, dy, dz;
-                            const double s =
-                                pair_delta(xi, yi, zi, x[g], y[g], z[g], B.L, B.halfL, B.halfL2, dx, dy, dz);
-                            if (s < B.rl2 && g != i) {
-                                if (c < d.maxnb)
-                                    nbr[nbr_index(i, c, d.nchunk)] = g;
-                                ++c;
-                            }
-                        }
-                    }
+        if (rows) {
+            // grid subcell of i
+            const int gx = wrap_index(X - 2 * G.c0[0] + 2, G.nx), gy = wrap_index(Y - 2 * G.c0[1] + 2, G.ny),
+                      gz = wrap_index(Z - 2 * G.c0[2] + 2, G.nz);
+            const int us = ((gz >> 1) * G.n[1] + (gy >> 1)) * G.n[0] + (gx >> 1);
+            const int fself = h.off[us] + (i - h.cs[us]);
+            if (wraps)
+                c = build_rows<BL, true, true>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16, i,
+                                               d.nchunk);
+            else if (interior)
+                c = build_rows<BL, false, false>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16,
+                                                 i, d.nchunk);
+            else
+                c = build_rows<BL, true, false>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16, i,
+                                                d.nchunk);
+        } else if (p == 0) {
+            c = build_global(B, G, h, fits, cell_start, x, y, z, i, xi, yi, zi, X, Y, Z, d.maxnb, nbr, d.nchunk);
         }
         if (p != 0)
             continue;  // the pair's first lane holds the same count and finishes the list
@@ -1592,6 +1807,131 @@ __global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restri
     }
 }
 
+// ------------------------------------------------------------------ Spring-Dashpot
+
+// One Spring-Dashpot pair term (Sec. 3.2, Eq. 3) on sphere i: while the
+// spheres overlap (r < sigma), F_ij = [K (sigma - r) - gamma (u . v_ij)] u
+// with u = x_ij / r and v_ij = v_i - v_j; with THERMO the elastic energy
+// K (sigma - r)^2 / 2 and x_ij . F_ij = r times the magnitude.  A NaN
+// sentinel entry fails the overlap test.  IMG as in eval2.
+template <bool THERMO, bool IMG>
+__device__ __forceinline__ void sd_term(double xj, double yj, double zj, double vxj, double vyj, double vzj,
+                                        double xi, double yi, double zi, double vxi, double vyi, double vzi,
+                                        const Box &B, double &ax, double &ay, double &az, double &u, double &w) {
+    double dx, dy, dz;
+    const double s = IMG ? pair_delta_img(xi, yi, zi, xj, yj, zj, dx, dy, dz)
+                         : pair_delta_fma(xi, yi, zi, xj, yj, zj, B.L, B.invL, dx, dy, dz);
+    if (s < B.sd_sig2) {
+        const double r = sqrt(s);
+        const double ir = 1.0 / r;
+        const double ux = dx * ir, uy = dy * ir, uz = dz * ir;
+        const double un = fma(uz, vzi - vzj, fma(uy, vyi - vyj, ux * (vxi - vxj)));
+        const double ov = B.sd_sig - r;
+        const double fm = fma(B.sd_k, ov, -(B.sd_g * un));
+        ax = fma(fm, ux, ax);
+        ay = fma(fm, uy, ay);
+        az = fma(fm, uz, az);
+        if (THERMO) {
+            u = fma(0.5 * B.sd_k * ov, ov, u);
+            w = fma(fm, r, w);
+        }
+    }
+}
+
+// Spring-Dashpot force on every sphere of a block, one lane per sphere, the
+// neighborhood staged with velocities (48 bytes a slot); MODE and the
+// epilogue as in k_force, except that kicked velocities go to vo, another
+// buffer than v.  The velocities read are those stored when the kernel runs
+// - the half-step velocities inside an integration, the initial ones at the
+// first force.
+template <int MODE, bool THERMO>
+__global__ __launch_bounds__(kMaxThreads) void k_force_sd(Dims d, const Box *__restrict__ boxes,
+                                                          const int32_t *__restrict__ blk_box, Pos x,
+                                                          const int32_t *__restrict__ hood_tab,
+                                                          const int32_t *__restrict__ cnt,
+                                                          const int32_t *__restrict__ nbr, Pos v, Pos vo, Pos f,
+                                                          Pos xo, double *__restrict__ partials, int32_t *err) {
+    __shared__ Hood h;
+    extern __shared__ double lds[];
+    int b, part;
+    if (!block_part(d, b, part))
+        return;
+    HoodWords hw;
+    hood_fetch(hood_tab, b, hw);
+    const Box B = block_box(d, boxes, blk_box, b);
+    hood_commit(hw, h);
+    const int total = h.off[h.ncell];
+    const bool fits = total <= d.cap;
+    lds_double *S = (lds_double *)lds;
+    const HoodImage im = hood_image(B, b - B.block_off, fits);
+    if (fits)
+        hood_stage6(h, total, d.cap, x, v, S, im);
+    double u = 0.0, w = 0.0, ke = 0.0;
+    int lo, hi;
+    h.share(part, d.parts, lo, hi);
+    const uint16_t *nbr16 = reinterpret_cast<const uint16_t *>(nbr);
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double xi = x.x[i], yi = x.y[i], zi = x.z[i];
+        const double vxi = v.x[i], vyi = v.y[i], vzi = v.z[i];
+        const int c = cnt[i];
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        if (fits) {
+            for (int k = 0; k < c; ++k) {
+                const lds_double *a = lds_slot6(S, nbr16[nbr_index16(i, k, d.nchunk)]);
+                if (im.on)
+                    sd_term<THERMO, true>(a[0], a[1], a[2], a[3], a[4], a[5], xi, yi, zi, vxi, vyi, vzi, B, ax, ay,
+                                          az, u, w);
+                else
+                    sd_term<THERMO, false>(a[0], a[1], a[2], a[3], a[4], a[5], xi, yi, zi, vxi, vyi, vzi, B, ax,
+                                           ay, az, u, w);
+            }
+        } else {
+            for (int k = 0; k < c; ++k) {
+                const int j = nbr[nbr_index(i, k, d.nchunk)];
+                sd_term<THERMO, false>(x.x[j], x.y[j], x.z[j], v.x[j], v.y[j], v.z[j], xi, yi, zi, vxi, vyi, vzi, B,
+                                       ax, ay, az, u, w);
+            }
+        }
+        if (MODE == 0 || MODE == 1) {
+            f.x[i] = ax;
+            f.y[i] = ay;
+            f.z[i] = az;
+            if (!(isfinite(ax) && isfinite(ay) && isfinite(az)))
+                atomicOr(err, kErrNonFinite);
+        }
+        if (MODE >= 1) {
+            double va = vxi + B.h * ax, vb = vyi + B.h * ay, vc = vzi + B.h * az;
+            if (THERMO)
+                ke += va * va + vb * vb + vc * vc;
+            if (MODE == 2) {
+                va = va + B.h * ax;
+                vb = vb + B.h * ay;
+                vc = vc + B.h * az;
+                const double nx = xi + B.dt * va, ny = yi + B.dt * vb, nz = zi + B.dt * vc;
+                xo.x[i] = nx;
+                xo.y[i] = ny;
+                xo.z[i] = nz;
+                if (!(isfinite(nx) && isfinite(ny) && isfinite(nz)))
+                    atomicOr(err, kErrNonFinite);
+            }
+            // (another half than v: other workgroups still read this
+            // sphere's velocity as a neighbour's)
+            vo.x[i] = va;
+            vo.y[i] = vb;
+            vo.z[i] = vc;
+        }
+    }
+    if (THERMO) {
+        block_sum3(u, w, ke);
+        if (threadIdx.x == 0) {
+            const int q = b * d.parts + part;
+            partials[q * kPartialStride + 0] = u;
+            partials[q * kPartialStride + 1] = w;
+            partials[q * kPartialStride + 2] = ke;
+        }
+    }
+}
+
 // acc[2 box + q] += mult * h * (sum over the box's blocks of partial q), one
 // wavefront per box, fixed order.
 __global__ __launch_bounds__(64) void k_grad_reduce(const Box *__restrict__ boxes,
@@ -1697,6 +2037,12 @@ hipError_t prepare_kernels(int dyn_bytes) {
         reinterpret_cast<const void *>(&k_force<1, true, 4>),
         reinterpret_cast<const void *>(&k_force<2, false, 4>),
         reinterpret_cast<const void *>(&k_force<2, true, 4>),
+        reinterpret_cast<const void *>(&k_force_sd<0, false>),
+        reinterpret_cast<const void *>(&k_force_sd<0, true>),
+        reinterpret_cast<const void *>(&k_force_sd<1, false>),
+        reinterpret_cast<const void *>(&k_force_sd<1, true>),
+        reinterpret_cast<const void *>(&k_force_sd<2, false>),
+        reinterpret_cast<const void *>(&k_force_sd<2, true>),
         reinterpret_cast<const void *>(&k_hvp<1>),
         reinterpret_cast<const void *>(&k_hvp<2>),
         reinterpret_cast<const void *>(&k_hvp<4>),
@@ -1792,7 +2138,7 @@ hipError_t launch_load_state(const Dims &d, const double *const pos[3], const do
     const double *v0 = vel ? vel[0] : nullptr, *v1 = vel ? vel[1] : nullptr, *v2 = vel ? vel[2] : nullptr;
     k_load_state<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, pos[0], pos[1], pos[2], v0,
                                                              v1, v2, b.x[c.x], b.y[c.x], b.z[c.x],
-                                                             b.vx[c.o], b.vy[c.o], b.vz[c.o], b.orig[c.o],
+                                                             b.vx[c.v], b.vy[c.v], b.vz[c.v], b.orig[c.o],
                                                              b.x[1 - c.x], b.y[1 - c.x], b.z[1 - c.x], b.err);
     return hipGetLastError();
 }
@@ -1812,28 +2158,29 @@ hipError_t launch_unload_pos(const Dims &d, const Buffers &b, const Pos &p, cons
 }
 
 hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, bool counts_clear, hipStream_t s) {
-    const int xc = c.x, xn = 1 - c.x, o = c.o, on = 1 - c.o;
+    const int xc = c.x, xn = 1 - c.x, o = c.o, on = 1 - c.o, v = c.v, vn = 1 - c.v;
+    const int nbin = d.ncs * kSub;
     if (!counts_clear) {
-        const hipError_t e = launch_fill_i32(b.cell_count, 0, d.ncs, s);
+        const hipError_t e = launch_fill_i32(b.cell_count, 0, nbin, s);
         if (e != hipSuccess)
             return e;
     }
     k_bin_count<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, b.x[xc], b.y[xc], b.z[xc],
                                                             b.cell_of, b.slot, b.cell_count, b.err);
-    if (d.ncs <= kScanOne) {
-        k_scan_one<<<1, 1024, 0, s>>>(b.cell_count, b.cell_start, d.ncs);
+    if (nbin <= kScanOne) {
+        k_scan_one<<<1, 1024, 0, s>>>(b.cell_count, b.cell_start, nbin);
     } else {
-        const int nt = scan_blocks(d.ncs);
-        k_scan_tiles<<<nt, 256, 0, s>>>(b.cell_count, b.cell_start, b.scan_sums, d.ncs);
-        k_scan_sums<<<1, 1024, 0, s>>>(b.scan_sums, nt, b.cell_start, d.ncs);
-        k_scan_add<<<(d.ncs + 255) / 256, 256, 0, s>>>(b.cell_start, b.scan_sums, d.ncs);
+        const int nt = scan_blocks(nbin);
+        k_scan_tiles<<<nt, 256, 0, s>>>(b.cell_count, b.cell_start, b.scan_sums, nbin);
+        k_scan_sums<<<1, 1024, 0, s>>>(b.scan_sums, nt, b.cell_start, nbin);
+        k_scan_add<<<(nbin + 255) / 256, 256, 0, s>>>(b.cell_start, b.scan_sums, nbin);
     }
     k_scatter<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.cell_of, b.slot, b.cell_start, b.tmp_idx);
     k_rank_permute<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, d.nbox, b.boxes, b.atom_box, b.tmp_idx, b.cell_of,
                                                                b.cell_start, b.x[xc],
-                                                               b.y[xc], b.z[xc], b.vx[o], b.vy[o], b.vz[o],
-                                                               b.orig[o], b.x[xn], b.y[xn], b.z[xn], b.vx[on],
-                                                               b.vy[on], b.vz[on], b.orig[on]);
+                                                               b.y[xc], b.z[xc], b.vx[v], b.vy[v], b.vz[v],
+                                                               b.orig[o], b.x[xn], b.y[xn], b.z[xn], b.vx[vn],
+                                                               b.vy[vn], b.vz[vn], b.orig[on]);
     return hipGetLastError();
 }
 
@@ -1856,8 +2203,28 @@ static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &o
         b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
 }
 
+template <int MODE, bool THERMO>
+static void force_sd_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
+    const int vo = MODE >= 1 ? 1 - o : o;  // kicked velocities go to the other half
+    k_force_sd<MODE, THERMO><<<block_grid(d.nblk * d.parts), d.threads, 2 * hood_lds_bytes(d.cap), s>>>(
+        d, b.boxes, b.blk_box, in, b.hood_tab, b.nbr_count, b.nbr, Pos{b.vx[o], b.vy[o], b.vz[o]},
+        Pos{b.vx[vo], b.vy[vo], b.vz[vo]}, Pos{b.fx, b.fy, b.fz}, out, b.partials, b.err);
+}
+
 hipError_t launch_force_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, int mode, bool thermo,
                            hipStream_t s) {
+    if (d.model == 1) {  // Spring-Dashpot: one lane per sphere
+        switch (mode * 2 + (thermo ? 1 : 0)) {
+        case 0: force_sd_variant<0, false>(d, b, in, out, o, s); break;
+        case 1: force_sd_variant<0, true>(d, b, in, out, o, s); break;
+        case 2: force_sd_variant<1, false>(d, b, in, out, o, s); break;
+        case 3: force_sd_variant<1, true>(d, b, in, out, o, s); break;
+        case 4: force_sd_variant<2, false>(d, b, in, out, o, s); break;
+        case 5: force_sd_variant<2, true>(d, b, in, out, o, s); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int l = d.lpa == 4 ? 2 : (d.lpa == 2 ? 1 : 0);
     switch ((mode * 2 + (thermo ? 1 : 0)) * 3 + l) {
     case 0: force_variant<0, false, 1>(d, b, in, out, o, s); break;
@@ -1884,7 +2251,7 @@ hipError_t launch_force_at(const Dims &d, Buffers &b, const Pos &in, const Pos &
 }
 
 hipError_t launch_force(const Dims &d, Buffers &b, Cursor c, int mode, bool thermo, hipStream_t s) {
-    return launch_force_at(d, b, b.pos(c.x), b.pos(1 - c.x), c.o, mode, thermo, s);
+    return launch_force_at(d, b, b.pos(c.x), b.pos(1 - c.x), c.v, mode, thermo, s);
 }
 
 hipError_t launch_drift_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
@@ -1894,7 +2261,7 @@ hipError_t launch_drift_at(const Dims &d, Buffers &b, const Pos &in, const Pos &
 }
 
 hipError_t launch_drift(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
-    return launch_drift_at(d, b, b.pos(c.x), b.pos(1 - c.x), c.o, s);
+    return launch_drift_at(d, b, b.pos(c.x), b.pos(1 - c.x), c.v, s);
 }
 
 hipError_t launch_reduce(const Dims &d, const Buffers &b, double *out, int row_len, hipStream_t s) {

@@ -8,7 +8,7 @@
 namespace tmd {
 
 constexpr int kScanTile = 1024;    // elements per workgroup in the cell-count scan
-constexpr int kScanOne = 32768;    // cell slots up to which one workgroup scans (and clears) the counts
+constexpr int kScanOne = 65536;    // bin slots up to which one workgroup scans (and clears) the counts
 constexpr int kPartialStride = 4;  // doubles per block partial: U, W, KE, pad
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kMaxEdge = 3;        // cells per block edge: 2 or 3
@@ -17,6 +17,11 @@ constexpr int kMaxThreads = 1024;  // threads per block workgroup (upper bound)
 constexpr int kAtomThreads = 256;  // threads per workgroup of per-atom kernels
 constexpr int kMaxParts = 4;       // workgroups per block, at most
 constexpr int kHoodWords = 256;    // int32 words of one block's stored neighborhood table
+// Binning sorts atoms by cell and, inside a cell, by subcell: the cell cut
+// in 2 x 2 x 2 (subcell index (sz * 2 + sy) * 2 + sx), then by original id.
+// Bin slot of subcell k of cell slot c: c * kSub + k.
+constexpr int kSub = 8;
+constexpr int kMaxSubGrid = kSub * kMaxHood;  // subcells of a block neighborhood, at most
 
 // Bits of the device error word err[0].
 constexpr int kErrOverflow = 1;
@@ -34,6 +39,7 @@ struct Box {
     int32_t nbx, block_off;  // blocks per axis (ceil(nc / E)); first block
     int32_t nblocks, edge;   // blocks of this box; E
     double L, halfL, side;   // box, half box, cell side L / nc
+    double hside;            // subcell side: side / 2
     double halfL2;           // (L/2)^2
     double invL;             // 1 / L
     double rc2, rl2;         // cutoff^2, (cutoff + skin)^2
@@ -50,6 +56,9 @@ struct Box {
     double e12, e6;          // f12 / eps, f6 / eps
     double h12, h6;          // 12 f12 / sigma, 6 f6 / sigma
     double h, dt, mass;      // half kick dt / (2 m), time step, mass
+    // Spring-Dashpot contact (model 1): spring constant K, dissipation
+    // gamma, diameter sigma and sigma^2
+    double sd_k, sd_g, sd_sig, sd_sig2;
 };
 
 // Sizes shared by all kernels of one system.
@@ -58,7 +67,7 @@ struct Dims {
     int32_t ntp;      // padded stride of the neighbor-major list
     int32_t nbox;     // boxes
     int32_t nblk;     // blocks in all boxes
-    int32_t ncs;      // cell slots in all boxes (E^3 per block)
+    int32_t ncs;      // cell slots in all boxes (E^3 per block); kSub bin slots each
     int32_t edge;     // E, cells per block edge
     int32_t cpb;      // E^3, cell slots per block
     int32_t maxnb;    // list capacity per atom
@@ -69,6 +78,7 @@ struct Dims {
     int32_t parts;    // workgroups per block (1, 2 or 4), each taking a share of the block's atoms
     int32_t lpa;      // lanes per atom in the force kernel (1, 2 or 4), each taking every lpa-th list chunk
     int32_t blanes;   // lanes per atom in the list build (1 or 2)
+    int32_t model;    // force model of every box: 0 Lennard-Jones, 1 Spring-Dashpot
 };
 
 // Neighbor list layout: neighbor-major within tiles of 64 atoms (one
@@ -105,7 +115,7 @@ struct Buffers {
     int32_t *blk_box;      // [nblk]  box of each block
     int32_t *atom_box;     // [nt]    box of each atom slot (boxes keep fixed slot ranges)
     int32_t *cell_of, *slot, *tmp_idx;
-    int32_t *cell_count, *cell_start, *scan_sums;
+    int32_t *cell_count, *cell_start, *scan_sums;  // per bin slot (kSub per cell slot)
     int32_t *nbr_count, *nbr;
     int32_t *hood_tab;     // [nblk][kHoodWords] neighborhood tables, written by every list build
     double *partials;      // [nblk * parts][kPartialStride]
@@ -113,11 +123,14 @@ struct Buffers {
 };
 
 // Which half of each double buffer is current: positions flip on every drift
-// and every binning; velocities and original ids flip only on binning (the
-// kicks update velocities in place).
+// and every binning; original ids flip only on binning.  Velocities flip on
+// binning, and for the Spring-Dashpot model also at every force launch that
+// kicks them: its force reads neighbours' velocities, so the kicked ones go
+// to the other half (Lennard-Jones kicks them in place).
 struct Cursor {
     int x = 0;
     int o = 0;
+    int v = 0;
 };
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -169,11 +182,14 @@ hipError_t launch_unload_pos(const Dims &d, const Buffers &b, const Pos &p, cons
 hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, bool counts_clear, hipStream_t s);
 hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s);
 // mode 0: F only (stored); 1: F + kick (stored, end of integrate);
-// 2: F + kick + kick + drift into positions 1 - c.x
+// 2: F + kick + kick + drift into positions 1 - c.x.  Velocities are read
+// from half c.v; the Spring-Dashpot model writes kicked ones to half 1 - c.v
+// (the caller then flips c.v), Lennard-Jones in place.
 hipError_t launch_force(const Dims &d, Buffers &b, Cursor c, int mode, bool thermo, hipStream_t s);
 hipError_t launch_drift(const Dims &d, Buffers &b, Cursor c, hipStream_t s);  // positions into 1 - c.x
 // The same with explicit position arrays (in: current, out: drifted) and
-// velocity half o; used to recompute a trajectory segment into storage.
+// velocity half o (kicked velocities as in launch_force); used to recompute
+// a trajectory segment into storage and to time the kernel.
 hipError_t launch_force_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, int mode, bool thermo,
                            hipStream_t s);
 hipError_t launch_drift_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s);

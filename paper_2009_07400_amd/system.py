@@ -38,9 +38,17 @@ def _ptrs(t3: torch.Tensor):
     return [int(t3[k].data_ptr()) for k in range(3)]
 
 
+_MODELS = {"lj": abi.TMD_MODEL_LJ, "spring_dashpot": abi.TMD_MODEL_SPRING_DASHPOT}
+
+
 def make_params(epsilon=1.0, sigma=1.0, mass=1.0, cutoff=2.5, skin=0.3, dt=0.005, rebuild_every=20,
-                max_neighbors=128) -> abi.TmdParams:
-    return abi.TmdParams(epsilon, sigma, mass, cutoff, skin, dt, rebuild_every, max_neighbors)
+                max_neighbors=128, model="lj", stiffness=0.0, damping=0.0) -> abi.TmdParams:
+    """model "lj" (Eq. 2) or "spring_dashpot" (Eq. 3: spheres of diameter
+    sigma, spring constant stiffness, dissipation damping)."""
+    if model not in _MODELS:
+        raise ValueError(f"model must be one of {sorted(_MODELS)}")
+    return abi.TmdParams(epsilon, sigma, mass, cutoff, skin, dt, rebuild_every, max_neighbors, stiffness, damping,
+                         _MODELS[model], 0)
 
 
 def compute_forces_static(pos, box_length: float, device="cuda", **params):

@@ -83,6 +83,11 @@ def test_graph_mode_switch_needs_no_gpu():
     ({}, 10, float("nan"), abi.TMD_EINVAL),
     ({}, 10, 5.6, abi.TMD_EBOX),      # cutoff + skin = 2.8 = L/2
     ({}, 10, 5.0, abi.TMD_EBOX),
+    # Spring-Dashpot (Eq. 3): non-negative finite K and gamma, list radius
+    # base cutoff >= the diameter sigma
+    (dict(model="spring_dashpot", stiffness=-1.0, cutoff=1.0), 10, 13.4, abi.TMD_EINVAL),
+    (dict(model="spring_dashpot", stiffness=100.0, damping=float("nan"), cutoff=1.0), 10, 13.4, abi.TMD_EINVAL),
+    (dict(model="spring_dashpot", stiffness=100.0, sigma=1.0, cutoff=0.9), 10, 13.4, abi.TMD_EINVAL),
 ])
 def test_create_rejects(kw, n, L, status):
     with pytest.raises(abi.TmdError) as e:
@@ -212,3 +217,19 @@ def test_static_forces_validates_before_the_gpu():
     finally:
         abi.tmd_destroy(h)
     assert lib.tmd_compute_forces_static(C.byref(p), 131072, 53.74708, *args) == abi.TMD_EWORKSPACE
+
+
+def test_unknown_model_and_mixed_batches_are_rejected():
+    p = make_params()
+    p.model = 7
+    with pytest.raises(abi.TmdError) as e:
+        abi.tmd_create(p, 10, 13.4)
+    assert e.value.status == abi.TMD_EINVAL
+    sd = make_params(model="spring_dashpot", stiffness=100.0, damping=1.0, cutoff=1.0)
+    with pytest.raises(abi.TmdError) as e:
+        abi.tmd_create_batch([make_params(), sd], [100, 100], [13.4, 13.4])
+    assert e.value.status == abi.TMD_EINVAL
+    h = abi.tmd_create(sd, 100, 13.4)
+    abi.tmd_destroy(h)
+    with pytest.raises(ValueError):
+        make_params(model="dem")

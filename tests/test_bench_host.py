@@ -31,8 +31,10 @@ def test_build_rooflines_arithmetic():
     assert r["binning"]["frac"] == pytest.approx(r["binning"]["achieved"] / 8000.0)
     nb = r["neighbor"]
     assert nb["bound"] == "alu" and nb["unit"] == "T FP64 instr/s"
-    assert nb["candidates_per_atom"] == pytest.approx(27.0 * n / n_cells)
-    assert nb["achieved"] == pytest.approx(8.0 * 27.0 * n / n_cells * n / 2e-3 / 1e12)
+    # 125 subcells of an eighth of a cell each
+    assert nb["candidates_per_atom"] == pytest.approx(125.0 / 8.0 * n / n_cells)
+    assert nb["cell_stencil_candidates_per_atom"] == pytest.approx(27.0 * n / n_cells)
+    assert nb["achieved"] == pytest.approx(8.0 * 125.0 / 8.0 * n / n_cells * n / 2e-3 / 1e12)
     # unfused FP64 instructions issue at 256 CUs x 64 lanes x 2.4 GHz = 39.32 T/s
     assert nb["peak"] == pytest.approx(39.3216)
     assert nb["frac"] == pytest.approx(nb["achieved"] / 39.3216)

@@ -127,11 +127,15 @@ def test_batch_equals_single_box_runs_bitwise():
     (128, 0, 2, 2, 2, 0), (0, 64, 2, 1, 2, 0), (0, 0, 3, 1, 2, 0), (256, 0, 3, 4, 2, 0), (0, 64, 3, 2, 2, 0),
     (0, 0, 2, 1, 4, 0), (0, 64, 2, 2, 4, 0), (512, 0, 3, 1, 4, 0), (0, 0, 2, 1, 1, 64), (0, 64, 3, 1, 2, 64),
     (0, 0, 3, 2, 1, 1024), (0, 64, 2, 1, 4, 1024), (0, 0, 2, 1, 1, -2), (0, 0, 3, 2, 2, -2), (0, 64, 2, 1, 1, -2),
-    (64, 0, 3, 4, 1, -2)])
+    (64, 0, 3, 4, 1, -2), (0, 1536, 2, 1, 1, 0), (0, 1536, 2, 1, 1, -2), (0, 3072, 3, 1, 2, 0)])
 def test_schedule_does_not_change_trajectory(threads, lds, edge, parts, lpa, bthreads):
     """Any schedule gives the trajectory of the default one bit for bit -
     against the default with the same lanes per atom (two lanes sum each
-    atom's force as two interleaved halves, a different rounding)."""
+    atom's force as two interleaved halves, a different rounding).  The list
+    build visits candidates in one order on every path: lds_atoms 64 sends
+    every neighborhood to global gathers, 1536 (E = 2) and 3072 (E = 3) leave
+    room for the force kernel's copy but not for the build's subcell-row copy
+    (global gathers writing LDS slots)."""
     s = md_system(9, seed=21)  # 5 cells per axis: edge blocks 1 (E = 2) or 2 (E = 3) cells thick
     ref = System(s.n, s.L)
     ref.set_schedule(lanes_per_atom=lpa)
