@@ -574,9 +574,11 @@ __global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nt, int32
 // scans the run totals, and each thread reads its run again (from the
 // cache), writes its offsets to cell_start[0..n] and clears its counts for
 // the next binning (so that binning needs no separate fill).  The run is
-// read in batches of 32 whose loads are all in flight together (holding 64
-// counts a thread in registers at once would spill; a plain loop would wait
-// out one load after another).
+// read in batches of 32 whose loads are all in flight together.  Each
+// thread's run is contiguous, so a wavefront's loads and stores touch one
+// cache line per lane: beyond a few tens of thousands of counts the
+// coalesced multi-workgroup scan is faster (measured: 64k counts took
+// 150 us here).
 __global__ __launch_bounds__(1024) void k_scan_one(int32_t *counts, int32_t *out, int n) {
     constexpr int M = 32;
     __shared__ int32_t sh[32];
@@ -868,6 +870,9 @@ __device__ __forceinline__ bool row_next(const SubGrid &G, int gy0, RowWalk &w) 
     return !last;
 }
 
+// Kinds of block for the list build's row walk.
+enum { kRowsInterior = 0, kRowsFace = 1, kRowsWrap = 2 };
+
 // Atom i's runs in the subcell-row copy, one lane per atom (BL = 1) or two
 // lanes testing alternate candidates (BL = 2, lane p).  A round reads four
 // (eight) consecutive slots unconditionally, up to three (seven) past the
@@ -876,14 +881,28 @@ __device__ __forceinline__ bool row_next(const SubGrid &G, int gy0, RowWalk &w) 
 // takes it if this one is done: one straight loop, so a lane whose run
 // ended moves on while the others finish theirs (branching to the next run
 // instead lets the compiler nest a loop over each run's rounds, which the
-// whole wavefront then waits out).  WRAP: the neighborhood grid covers the
-// whole box along some axis (rows and runs wrap); else each of the 25 runs
-// is the five subcells x - 2 .. x + 2 of row (y + dy, z + dz).  Returns the
-// number of neighbors found.
-template <int BL, bool MIC, bool WRAP>
+// whole wavefront then waits out).
+//
+// GEOM says how the differences get their periodic images:
+//   kRowsInterior: the neighborhood neither wraps the box nor spans half of
+//     it, so no raw difference exceeds L/2;
+//   kRowsFace: the neighborhood wraps a face but holds no cell twice.  A
+//     candidate's image is then fixed by where its subcell sits in the grid:
+//     subcells before grid index bl (past the low face) take d - (-L),
+//     subcells from bh on (past the high face) take d - L, the rest d - 0.
+//     For every candidate this is the oracle's shift (d > L/2: d -= L; d <
+//     -L/2: d += L), applied to the same raw difference, so decisions and
+//     roundings are the oracle's: along y and z the shift is the row's,
+//     along x it changes at most once inside a run, at slot tw;
+//   kRowsWrap: the neighborhood holds every cell of some axis (small
+//     boxes): rows and runs wrap, and each difference takes the minimum
+//     image of its value.
+// Returns the number of neighbors found.
+template <int BL, int GEOM>
 __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const lds_u16 *soff, const SubGrid &G,
                                           int gx, int gy, int gz, int fself, double xi, double yi, double zi,
                                           const Box &B, int maxnb, int p, uint16_t *nbr16, int i, int nchunk) {
+    constexpr bool WRAP = GEOM == kRowsWrap, SHIFT = GEOM == kRowsFace;
     RowWalk w;
     w.gz = wrap_index(gz - 2, G.nz);
     w.gy = wrap_index(gy - 2, G.ny);
@@ -894,15 +913,49 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
     const int gy0 = w.gy;
     // without wrapping: run r starts at table index idx, the next at idx + nx
     // (+ nx (ny - 5) after every fifth)
-    int idx = (w.gz * G.ny + w.gy) * G.nx + w.xs, ky = 0, row = 0;
+    int idx = (w.gz * G.ny + w.gy) * G.nx + w.xs, ky = 0, kz = 0, row = 0;
     const int zskip = G.nx * (G.ny - 5), idx_max = G.ng - 5;
+    // face shifts: grid indices below bl lie past the low face, from bh on
+    // past the high face (per axis)
+    const int blx = 2 - 2 * G.c0[0], bhx = G.nsub - 2 * G.c0[0] + 2;
+    const int bly = 2 - 2 * G.c0[1], bhy = G.nsub - 2 * G.c0[1] + 2;
+    const int blz = 2 - 2 * G.c0[2], bhz = G.nsub - 2 * G.c0[2] + 2;
+    // along x: slots before tw take sxa, the others sxb; tw sits at grid
+    // index gx - 2 + dgb of each row
+    double sxa = 0.0, sxb = 0.0;
+    int dgb = 0, tw = -1;
+    if (SHIFT) {
+        if (blx > gx - 2) {
+            sxa = -B.L;
+            dgb = blx - (gx - 2);
+        } else if (bhx <= gx + 2) {
+            sxb = B.L;
+            dgb = bhx - (gx - 2);
+        }
+    }
+    auto shift_of = [&](int g, int bl, int bh) { return g < bl ? -B.L : (g >= bh ? B.L : 0.0); };
+    double sy = SHIFT ? shift_of(gy - 2, bly, bhy) : 0.0, sz = SHIFT ? shift_of(gz - 2, blz, bhz) : 0.0;
+    const bool xshift = SHIFT && (sxa != 0.0 || sxb != 0.0);
     int t, e;
     if (WRAP) {
         row_run(G, soff, w, t, e);
     } else {
         t = soff[idx];
         e = soff[idx + 5];
+        tw = xshift ? int(soff[idx + dgb]) : -1;
     }
+    // difference of one candidate along the three axes, with its image
+    auto dist = [&](double xj, double yj, double zj, int tj) {
+        if (WRAP)
+            return cand_dist2<true>(xi, yi, zi, xj, yj, zj, B);
+        if (SHIFT) {
+            const double dx = (xi - xj) - (tj < tw ? sxa : sxb);
+            const double dy = (yi - yj) - sy;
+            const double dz = (zi - zj) - sz;
+            return dist2(dx, dy, dz);
+        }
+        return dist2(xi - xj, yi - yj, zi - zj);
+    };
     int c = 0;
     uint16_t *wp = nbr16 + nbr_index16(i, 0, nchunk);
     for (;;) {
@@ -920,7 +973,7 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const double s = cand_dist2<MIC>(xi, yi, zi, px[r], py[r], pz[r], B);
+                const double s = dist(px[r], py[r], pz[r], t + r);
                 if (s < B.rl2 && t + r < e && tr[r] != fself)
                     put16(wp, c, maxnb, tr[r]);
             }
@@ -940,7 +993,7 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
             unsigned mine = 0;  // bit 2r + p: slot t + 2r + p accepted
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const double s = cand_dist2<MIC>(xi, yi, zi, px[r], py[r], pz[r], B);
+                const double s = dist(px[r], py[r], pz[r], t + 2 * r + p);
                 mine |= (s < B.rl2 && t + 2 * r + p < e && tr[r] != fself) ? (1u << (2 * r + p)) : 0u;
             }
             const unsigned m8 = mine | unsigned(__shfl_xor(int(mine), 1, 64));
@@ -969,12 +1022,22 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
             w.ky = adv ? w2.ky : w.ky;
             w.piece = adv ? w2.piece : w.piece;
         } else {
-            const int nidx = min(idx + G.nx + (ky == 4 ? zskip : 0), idx_max);
+            const bool zstep = ky == 4;
+            const int nidx = min(idx + G.nx + (zstep ? zskip : 0), idx_max);
             nt = soff[nidx];
             ne = soff[nidx + 5];
             more = row + 1 < 25;
+            if (SHIFT) {
+                const int ky2 = zstep ? 0 : ky + 1, kz2 = zstep ? kz + 1 : kz;
+                const int ntw = xshift ? int(soff[min(nidx + dgb, G.ng)]) : -1;
+                const double nsy = shift_of(gy - 2 + ky2, bly, bhy), nsz = shift_of(gz - 2 + kz2, blz, bhz);
+                sy = adv ? nsy : sy;
+                sz = adv ? nsz : sz;
+                tw = adv ? ntw : tw;
+                kz = adv ? kz2 : kz;
+            }
             idx = adv ? nidx : idx;
-            ky = adv ? (ky == 4 ? 0 : ky + 1) : ky;
+            ky = adv ? (zstep ? 0 : ky + 1) : ky;
             row += adv ? 1 : 0;
         }
         if (adv && !more)
@@ -1065,12 +1128,15 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     // global slot nt
     const int sentinel = fits ? d.cap : d.nt;
     uint16_t *nbr16 = reinterpret_cast<uint16_t *>(nbr);
-    // no neighborhood cell range wraps the box and each spans at most half
-    // of it: no raw difference along an axis exceeds L/2
+    // interior: no neighborhood cell range crosses a face of the box.  A
+    // candidate lies within two subcells of its atom's subcell, less than
+    // 1.5 cells away along each axis, and a neighborhood that holds no cell
+    // twice needs at least four cells per axis (L/2 >= 2 cells): no raw
+    // difference exceeds L/2
     bool interior = true, wraps = false;
     for (int a = 0; a < 3; ++a) {
         const int c0 = G.c0[a], e = min(B.edge, B.nc - c0);
-        interior &= c0 >= 1 && c0 + e <= B.nc - 1 && 2 * (e + 2) <= B.nc;
+        interior &= c0 >= 1 && c0 + e <= B.nc - 1;
         wraps |= G.n[a] < e + 2;  // the neighborhood holds every cell of the axis
     }
     const int p = threadIdx.x & (BL - 1);  // lane of the atom's pair (BL = 2)
@@ -1086,14 +1152,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
             const int us = ((gz >> 1) * G.n[1] + (gy >> 1)) * G.n[0] + (gx >> 1);
             const int fself = h.off[us] + (i - h.cs[us]);
             if (wraps)
-                c = build_rows<BL, true, true>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16, i,
-                                               d.nchunk);
+                c = build_rows<BL, kRowsWrap>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16, i,
+                                              d.nchunk);
             else if (interior)
-                c = build_rows<BL, false, false>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16,
-                                                 i, d.nchunk);
+                c = build_rows<BL, kRowsInterior>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16,
+                                                  i, d.nchunk);
             else
-                c = build_rows<BL, true, false>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16, i,
-                                                d.nchunk);
+                c = build_rows<BL, kRowsFace>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16, i,
+                                              d.nchunk);
         } else if (p == 0) {
             c = build_global(B, G, h, fits, cell_start, x, y, z, i, xi, yi, zi, X, Y, Z, d.maxnb, nbr, d.nchunk);
         }
@@ -1725,8 +1791,14 @@ __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0
 // kernel's lanes do (groups of eight entries dealt in turn, on the 32-bit
 // path too, so both paths give the same sums) and combine their sums by a
 // butterfly; the atom's first lane writes.
+// (at most kHvpThreads threads: its 48-byte LDS slots leave room for one
+// workgroup per CU at the usual capacities, so the bound costs no occupancy
+// and lets the compiler keep the 2- and 4-lane variants' registers out of
+// scratch memory)
+constexpr int kHvpThreads = 768;
+
 template <int L>
-__global__ __launch_bounds__(kMaxThreads) void k_hvp(Dims d, const Box *__restrict__ boxes,
+__global__ __launch_bounds__(kHvpThreads) void k_hvp(Dims d, const Box *__restrict__ boxes,
                                                      const int32_t *__restrict__ blk_box, Pos x,
                                                      const int32_t *__restrict__ hood_tab,
                                                      const int32_t *__restrict__ cnt,
@@ -2069,8 +2141,8 @@ hipError_t launch_gather(const Dims &d, const double *const src[3], const int32_
 // wavefronts.
 static void hvp_shape(const Dims &d, int &lanes, int &threads) {
     const double per_wg = double(d.nt) / (double(d.nblk) * d.parts);
-    lanes = per_wg * 4.0 <= double(kMaxThreads) ? 4 : (per_wg * 2.0 <= double(kMaxThreads) ? 2 : 1);
-    threads = std::min(kMaxThreads, std::max(64, round_up(int(per_wg * lanes + 0.5), 64)));
+    lanes = per_wg * 4.0 <= double(kHvpThreads) ? 4 : (per_wg * 2.0 <= double(kHvpThreads) ? 2 : 1);
+    threads = std::min(kHvpThreads, std::max(64, round_up(int(per_wg * lanes + 0.5), 64)));
 }
 
 hipError_t launch_hvp(const Dims &d, Buffers &b, const Pos &x, const Pos &w, const Pos &lam_x, const Pos &wout,

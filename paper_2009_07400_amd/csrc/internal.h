@@ -8,7 +8,7 @@
 namespace tmd {
 
 constexpr int kScanTile = 1024;    // elements per workgroup in the cell-count scan
-constexpr int kScanOne = 65536;    // bin slots up to which one workgroup scans (and clears) the counts
+constexpr int kScanOne = 32768;    // bin slots up to which one workgroup scans (and clears) the counts
 constexpr int kPartialStride = 4;  // doubles per block partial: U, W, KE, pad
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kMaxEdge = 3;        // cells per block edge: 2 or 3
