@@ -117,20 +117,57 @@ def _force_roofline(n: int, mean_list: float, avg_s: float, traffic=None, kernel
     return out
 
 
-def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int) -> dict:
+def _trimmed_subcells(side_over_rl: float, k: int = 24) -> float:
+    """Mean number of the 125 half-size subcells around an atom's own
+    (offsets -2..2 per axis) that its cutoff sphere reaches, for an atom
+    placed uniformly in its subcell (midpoint rule, k^3 points): the list
+    build walks only those.  Along an axis, the subcells at offsets -2, -1,
+    +1, +2 begin q + h, q, h - q and 2h - q away (q the atom's distance from
+    its subcell's low edge, h the subcell side)."""
+    h = 0.5 * side_over_rl  # in units of rl
+    q = (np.arange(k) + 0.5) / k * h
+    d = np.stack([q + h, q, np.zeros_like(q), h - q, 2 * h - q])  # [offset, point]
+    sq = d * d
+    tot = 0.0
+    for qx in sq.T:
+        for qy in sq.T:
+            # [dz offset, point z] + [dy offset] + [dx offset] for this x, y
+            s3 = sq[:, None, None, :] + qy[None, :, None, None] + qx[None, None, :, None]
+            tot += (s3 < 1.0).sum()
+    return tot / k ** 3
+
+
+def stencil_candidates(boxes, rl: float = 2.8, block_edge: int = 2) -> float:
+    """Mean candidates per atom of the list build over boxes [(n_atoms, L)]:
+    atoms per subcell times the subcells walked, the trimmed stencil where a
+    block's neighborhood holds no cell twice (cells per axis >= block edge +
+    2), else every distinct subcell of the 5^3 stencil."""
+    tot = 0.0
+    n_all = 0
+    for n, L in boxes:
+        nc = int(np.floor(L / rl))
+        per_sub = n / (8.0 * nc ** 3)
+        subs = _trimmed_subcells(L / nc / rl) if nc >= block_edge + 2 else float(min(5, 2 * nc) ** 3)
+        tot += n * per_sub * subs
+        n_all += n
+    return tot / n_all
+
+
+def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int, cand: float) -> dict:
     """Roofline figures of the binning and list-build kernels, per call (one
     call = one rebuild: the binning bucket sums its four to eight launches).
 
     Binning moves 132 algorithmic bytes per atom (read x and the atom id,
     28; the permutation reads x, v and id and writes them, 52 + 52).  The
     list build reads x (24) and writes the count (4) and the list (4 bytes
-    per entry at the method's index width) and tests the atoms of 125
-    half-size subcells per atom (125 / 8 cells' worth; 27 whole cells hold
-    1.73x as many), 8 unfused FP64 instructions each (3 differences, 3
-    squares, 2 sums, no fused multiply-add so that its decisions match any
-    IEEE evaluation): it is bound by FP64 instruction issue, so its fraction
-    is taken against the issue rate of unfused FP64 instructions, with the
-    HBM fraction beside it."""
+    per entry at the method's index width) and tests cand candidates per
+    atom (stencil_candidates(): the atoms of the half-size subcells that the
+    cutoff sphere reaches; 27 whole cells hold about 2.6x as many), 8
+    unfused FP64 instructions each (3 differences, 3 squares, 2 sums, no
+    fused multiply-add so that its decisions match any IEEE evaluation): it
+    is bound by FP64 instruction issue, so its fraction is taken against the
+    issue rate of unfused FP64 instructions, with the HBM fraction beside
+    it."""
     out = {}
     if tm.get("binning", (0, 0))[1]:
         ms, calls = tm["binning"]
@@ -142,7 +179,6 @@ def _build_rooflines(tm: dict, n: int, mean_list: float, n_cells: int) -> dict:
         ms, calls = tm["neighbor"]
         t = ms / calls * 1e-3
         b = (28.0 + 4.0 * mean_list) * n
-        cand = 125.0 / 8.0 * n / n_cells
         ops = 8.0 * cand * n
         out["neighbor"] = {"bound": "alu", "achieved": ops / t / 1e12, "peak": FP64_ISSUE_PEAK_T,
                            "unit": "T FP64 instr/s", "frac": ops / t / 1e12 / FP64_ISSUE_PEAK_T,
@@ -195,6 +231,7 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
     g.sync()
     ms, launches = tm["force"]
     avg_s = ms / max(launches, 1) * 1e-3
+    sched = _schedule(g)
     res = {
         "n": s.n,
         "steps": steps,
@@ -204,11 +241,12 @@ def run_gpu(workload: str, steps: int, warmup: int, schedule=None):
         "value": s.n * steps / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
         "mean_list_length": mean_list,
-        "schedule": _schedule(g),
+        "schedule": sched,
         "kernel_ms": {k: (v[0] / max(v[1], 1), v[1]) for k, v in tm.items() if v[1]},
         "roofline": _force_roofline(s.n, mean_list, avg_s, _traffic(workload),
                                     "k_force<2,false>: LDS-staged block force + kick + kick + drift"),
-        "build_rooflines": _build_rooflines(tm, s.n, mean_list, n_cells),
+        "build_rooflines": _build_rooflines(tm, s.n, mean_list, n_cells,
+                                            stencil_candidates([(s.n, s.L)], block_edge=sched["block_edge"])),
     }
     g.close()
     return res
@@ -256,7 +294,8 @@ def run_batched(steps: int = 200, warmup: int = 20, n_boxes: int = 512):
     ms, launches = tm["force"]
     roof = _force_roofline(total, mean_list, ms / max(launches, 1) * 1e-3,
                            kernel="k_force<2,false>: one launch over every box's blocks")
-    brf = _build_rooflines(tm, total, mean_list, int(info["n_cells"]))
+    brf = _build_rooflines(tm, total, mean_list, int(info["n_cells"]),
+                           stencil_candidates([(b.n, b.L) for b in boxes], block_edge=sched["block_edge"]))
     seq = []
     for b in boxes:
         s = System(b.n, b.L, max_neighbors=128)

@@ -873,6 +873,62 @@ __device__ __forceinline__ bool row_next(const SubGrid &G, int gy0, RowWalk &w) 
 // Kinds of block for the list build's row walk.
 enum { kRowsInterior = 0, kRowsFace = 1, kRowsWrap = 2 };
 
+// Which of the 25 rows of atom i's 5 x 5 x 5 subcell stencil its cutoff
+// sphere reaches, and how far along x in each.  Along one axis the atom lies
+// at distance q from the low edge of its own subcell (side hs); the
+// subcells at offsets -2, -1, +1, +2 begin q + hs, q, hs - q and 2 hs - q
+// away.  A row (offsets dy, dz) is needed if its nearest point lies within
+// the cutoff, and in a needed row the x-run keeps the subcells at offsets
+// -2 and -1 (+1 and +2) while theirs do: the needed subcells of a row are
+// contiguous around dx = 0.  Every atom in a subcell left out is farther than
+// rl from i by more than the rounding of its difference (the test admits
+// rounding through a margin far above it), so the distance test would reject
+// it: leaving it out changes no list.  Bit r of need marks row r = 5 kz + ky;
+// four bits per row in lo and hi (two for the offsets kept below x = 0, two
+// above).
+struct RowTrim {
+    unsigned need;
+    uint64_t lo, hi;  // codes of rows 0-15 and 16-24 (no indexed array: it would live in scratch memory)
+};
+
+__device__ __forceinline__ RowTrim row_trim(double xi, double yi, double zi, int X, int Y, int Z, const Box &B) {
+    const double hs = B.hside;
+    // rounding of positions and subcell edges stays below a few ulp(L)
+    const double R = B.rl2 + 2e-12 * B.L * sqrt(B.rl2);
+    auto q5 = [&](double p, int s, double q[5]) {
+        const double o = p - double(s) * hs;
+        const double lo1 = max(o, 0.0), hi1 = max(hs - o, 0.0);
+        q[0] = (lo1 + hs) * (lo1 + hs);
+        q[1] = lo1 * lo1;
+        q[2] = 0.0;
+        q[3] = hi1 * hi1;
+        q[4] = (hi1 + hs) * (hi1 + hs);
+    };
+    double qx[5], qy[5], qz[5];
+    q5(xi, X, qx);
+    q5(yi, Y, qy);
+    q5(zi, Z, qz);
+    RowTrim T;
+    T.need = 0;
+    T.lo = T.hi = 0;
+#pragma unroll
+    for (int kz = 0; kz < 5; ++kz)
+#pragma unroll
+        for (int ky = 0; ky < 5; ++ky) {
+            const int r = 5 * kz + ky;
+            const double dyz = qy[ky] + qz[kz];
+            const unsigned lo = (qx[0] + dyz < R) ? 2u : ((qx[1] + dyz < R) ? 1u : 0u);
+            const unsigned hi = (qx[4] + dyz < R) ? 2u : ((qx[3] + dyz < R) ? 1u : 0u);
+            T.need |= (dyz < R ? 1u : 0u) << r;
+            const uint64_t cr = uint64_t(lo | (hi << 2));
+            if (r < 16)
+                T.lo |= cr << (4 * r);
+            else
+                T.hi |= cr << (4 * (r - 16));
+        }
+    return T;
+}
+
 // Atom i's runs in the subcell-row copy, one lane per atom (BL = 1) or two
 // lanes testing alternate candidates (BL = 2, lane p).  A round reads four
 // (eight) consecutive slots unconditionally, up to three (seven) past the
@@ -884,9 +940,9 @@ enum { kRowsInterior = 0, kRowsFace = 1, kRowsWrap = 2 };
 // whole wavefront then waits out).
 //
 // GEOM says how the differences get their periodic images:
-//   kRowsInterior: the neighborhood neither wraps the box nor spans half of
-//     it, so no raw difference exceeds L/2;
-//   kRowsFace: the neighborhood wraps a face but holds no cell twice.  A
+//   kRowsInterior: the neighborhood crosses no face of the box, so no raw
+//     difference exceeds L/2;
+//   kRowsFace: the neighborhood crosses a face but holds no cell twice.  A
 //     candidate's image is then fixed by where its subcell sits in the grid:
 //     subcells before grid index bl (past the low face) take d - (-L),
 //     subcells from bh on (past the high face) take d - L, the rest d - 0.
@@ -897,11 +953,13 @@ enum { kRowsInterior = 0, kRowsFace = 1, kRowsWrap = 2 };
 //   kRowsWrap: the neighborhood holds every cell of some axis (small
 //     boxes): rows and runs wrap, and each difference takes the minimum
 //     image of its value.
-// Returns the number of neighbors found.
+// The first two walk the rows and x-runs of row_trim(); the third the
+// whole stencil.  Returns the number of neighbors found.
 template <int BL, int GEOM>
 __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const lds_u16 *soff, const SubGrid &G,
                                           int gx, int gy, int gz, int fself, double xi, double yi, double zi,
-                                          const Box &B, int maxnb, int p, uint16_t *nbr16, int i, int nchunk) {
+                                          const RowTrim &T, const Box &B, int maxnb, int p, uint16_t *nbr16, int i,
+                                          int nchunk) {
     constexpr bool WRAP = GEOM == kRowsWrap, SHIFT = GEOM == kRowsFace;
     RowWalk w;
     w.gz = wrap_index(gz - 2, G.nz);
@@ -911,10 +969,9 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
     w.xb = G.m - w.xa;
     w.kz = w.ky = w.piece = 0;
     const int gy0 = w.gy;
-    // without wrapping: run r starts at table index idx, the next at idx + nx
-    // (+ nx (ny - 5) after every fifth)
-    int idx = (w.gz * G.ny + w.gy) * G.nx + w.xs, ky = 0, kz = 0, row = 0;
-    const int zskip = G.nx * (G.ny - 5), idx_max = G.ng - 5;
+    // without wrapping: row r = 5 kz + ky of the stencil starts at table
+    // index base + kz nx ny + ky nx (its subcell at x offset -2)
+    const int base = ((gz - 2) * G.ny + (gy - 2)) * G.nx + (gx - 2), zstride = G.nx * G.ny;
     // face shifts: grid indices below bl lie past the low face, from bh on
     // past the high face (per axis)
     const int blx = 2 - 2 * G.c0[0], bhx = G.nsub - 2 * G.c0[0] + 2;
@@ -933,16 +990,28 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
             dgb = bhx - (gx - 2);
         }
     }
-    auto shift_of = [&](int g, int bl, int bh) { return g < bl ? -B.L : (g >= bh ? B.L : 0.0); };
-    double sy = SHIFT ? shift_of(gy - 2, bly, bhy) : 0.0, sz = SHIFT ? shift_of(gz - 2, blz, bhz) : 0.0;
     const bool xshift = SHIFT && (sxa != 0.0 || sxb != 0.0);
-    int t, e;
+    auto shift_of = [&](int g, int bl, int bh) { return g < bl ? -B.L : (g >= bh ? B.L : 0.0); };
+    double sy = 0.0, sz = 0.0;
+    // slots [t, e) of stencil row r, and tw for it
+    auto trim_run = [&](int r, int &t_, int &e_, int &tw_, double &sy_, double &sz_) {
+        const int kz = (r * 13) >> 6, ky = r - 5 * kz;  // r / 5, r % 5 for r < 25
+        const unsigned c = unsigned((r < 16 ? T.lo : T.hi) >> ((r & 15) * 4)) & 15u;
+        const int rb = base + kz * zstride + ky * G.nx;
+        t_ = soff[rb + 2 - int(c & 3u)];
+        e_ = soff[rb + 3 + int(c >> 2)];
+        if (SHIFT) {
+            tw_ = xshift ? int(soff[rb + dgb]) : -1;
+            sy_ = shift_of(gy - 2 + ky, bly, bhy);
+            sz_ = shift_of(gz - 2 + kz, blz, bhz);
+        }
+    };
+    int t, e, row = 0;
     if (WRAP) {
         row_run(G, soff, w, t, e);
     } else {
-        t = soff[idx];
-        e = soff[idx + 5];
-        tw = xshift ? int(soff[idx + dgb]) : -1;
+        row = __builtin_ctz(T.need);  // the centre row is always needed
+        trim_run(row, t, e, tw, sy, sz);
     }
     // difference of one candidate along the three axes, with its image
     auto dist = [&](double xj, double yj, double zj, int tj) {
@@ -1022,23 +1091,19 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
             w.ky = adv ? w2.ky : w.ky;
             w.piece = adv ? w2.piece : w.piece;
         } else {
-            const bool zstep = ky == 4;
-            const int nidx = min(idx + G.nx + (zstep ? zskip : 0), idx_max);
-            nt = soff[nidx];
-            ne = soff[nidx + 5];
-            more = row + 1 < 25;
+            // the next needed row (row itself when there is none)
+            const unsigned rest = row < 24 ? T.need & (~0u << (row + 1)) : 0u;
+            more = rest != 0u;
+            const int nrow = more ? __builtin_ctz(rest) : row;
+            int ntw = tw;
+            double nsy = sy, nsz = sz;
+            trim_run(nrow, nt, ne, ntw, nsy, nsz);
             if (SHIFT) {
-                const int ky2 = zstep ? 0 : ky + 1, kz2 = zstep ? kz + 1 : kz;
-                const int ntw = xshift ? int(soff[min(nidx + dgb, G.ng)]) : -1;
-                const double nsy = shift_of(gy - 2 + ky2, bly, bhy), nsz = shift_of(gz - 2 + kz2, blz, bhz);
                 sy = adv ? nsy : sy;
                 sz = adv ? nsz : sz;
                 tw = adv ? ntw : tw;
-                kz = adv ? kz2 : kz;
             }
-            idx = adv ? nidx : idx;
-            ky = adv ? (zstep ? 0 : ky + 1) : ky;
-            row += adv ? 1 : 0;
+            row = adv ? nrow : row;
         }
         if (adv && !more)
             break;
@@ -1151,14 +1216,17 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                       gz = wrap_index(Z - 2 * G.c0[2] + 2, G.nz);
             const int us = ((gz >> 1) * G.n[1] + (gy >> 1)) * G.n[0] + (gx >> 1);
             const int fself = h.off[us] + (i - h.cs[us]);
+            RowTrim T{};
+            if (!wraps)
+                T = row_trim(xi, yi, zi, X, Y, Z, B);
             if (wraps)
-                c = build_rows<BL, kRowsWrap>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16, i,
+                c = build_rows<BL, kRowsWrap>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, T, B, d.maxnb, p, nbr16, i,
                                               d.nchunk);
             else if (interior)
-                c = build_rows<BL, kRowsInterior>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16,
+                c = build_rows<BL, kRowsInterior>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, T, B, d.maxnb, p, nbr16,
                                                   i, d.nchunk);
             else
-                c = build_rows<BL, kRowsFace>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, B, d.maxnb, p, nbr16, i,
+                c = build_rows<BL, kRowsFace>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, T, B, d.maxnb, p, nbr16, i,
                                               d.nchunk);
         } else if (p == 0) {
             c = build_global(B, G, h, fits, cell_start, x, y, z, i, xi, yi, zi, X, Y, Z, d.maxnb, nbr, d.nchunk);
