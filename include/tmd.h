@@ -106,6 +106,7 @@ typedef struct {
     int32_t build_lanes;     /* lanes per atom in the list build (1 or 2) */
     int32_t graph_captures;  /* rebuild intervals captured as graphs (tmd_set_graphs) */
     int64_t graph_launches;  /* rebuild intervals run as graph launches */
+    int32_t half_list;       /* 1: half lists inside blocks (tmd_set_half_list) */
 } tmd_info;
 
 /* Kernel classes reported by tmd_get_timing(). */
@@ -247,12 +248,33 @@ tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms,
                             int32_t block_parts, int32_t lanes_per_atom, int32_t build_threads,
                             int32_t build_lanes);
 
-/* Pick the schedule (block edge 2 or 3, workgroups per block 1, 2 or 4,
- * lanes per atom 1, 2 or 4, threads per force and per build workgroup,
- * lanes per atom of the build 1 or 2)
+/* Half neighbor lists with Newton's third law (Sec. 3.2: each pair stored
+ * once, its force applied to both atoms; the half_nb variant of Sec. 4.2),
+ * applied inside each block of cells: a pair of two atoms of one block is
+ * listed once, by the atom staged first, and the force kernel adds the
+ * partner's reaction to a sum in the workgroup's LDS; a pair whose atoms lie
+ * in different blocks is listed by both atoms, each block computing only its
+ * own atoms' forces (no workgroup writes another's atoms, no global
+ * atomics).  Blocks whose neighborhood does not fit in LDS, holds a cell
+ * twice (boxes of fewer than block edge + 2 cells per axis) or whose own
+ * cells span more LDS slots than the reaction sums hold keep full lists.
+ * tmd_get_neighbors then returns each atom's half list (in original ids,
+ * rows sorted), the same physics as the full list.  The LDS sums are
+ * atomic adds, so forces may differ from run to run in their last bits.
+ * half: 1 on, 0 off (the default).  Lennard-Jones only, with one workgroup
+ * per block and one lane per atom (tmd_set_schedule refuses block_parts or
+ * lanes_per_atom above 1 while it is on); not with the adjoint
+ * (tmd_adjoint_forward returns TMD_EINVAL).  Marks the list stale.
+ * TMD_EINVAL for other values or combinations.  Host only. */
+tmd_status tmd_set_half_list(tmd_system *sys, int32_t half);
+
+/* Pick the schedule (block edge 2 or 3, full or half lists - the latter
+ * for Lennard-Jones, with one workgroup per block and one lane per atom -,
+ * workgroups per block 1, 2 or 4, lanes per atom 1, 2 or 4, threads per
+ * force and per build workgroup, lanes per atom of the build 1 or 2)
  * with the shortest time per step for the current positions - one launch
  * of the step kernel (force sum, kicks and drift) plus 1/rebuild_every of a
- * list build: for each edge and workgroups per block, times `repeats`
+ * list build: for each edge, list kind and workgroups per block, times `repeats`
  * builds per (build lanes, build threads) and `repeats` step-kernel launches per
  * (lanes, threads) candidate, threads from one lane group per mean block
  * atom (in whole wavefronts) up to two wavefronts more, on `stream` with HIP

@@ -50,6 +50,10 @@ def _load():
         lib.orc_forces.argtypes = [_I, _P, _P, _P, _D, _P, _P, _I, _D, _D, _D, _P, _P, _P, _P, _P, _P]
         lib.orc_atom_force.restype = None
         lib.orc_atom_force.argtypes = [_I, _P, _P, _P, _D, _I, _D, _D, _D, _P, _P]
+        lib.orc_half_list.restype = None
+        lib.orc_half_list.argtypes = [_I, _P, _P, _I, _P, _P]
+        lib.orc_forces_half.restype = None
+        lib.orc_forces_half.argtypes = [_I, _P, _P, _P, _D, _P, _P, _I, _D, _D, _D, _P, _P, _P, _P, _P]
         lib.orc_run.restype = _L
         lib.orc_run.argtypes = [_I, _P, _P, _P, _P, _P, _P, _D, _D, _D, _D, _D, _D, _D, _I, _I, _I, _P, _P, _P, _P, _P,
                                 _P]
@@ -141,6 +145,32 @@ def forces(x, y, z, L, count, nbr, eps=1.0, sigma=1.0, rc=2.5):
     _load().orc_forces(n, _ptr(x), _ptr(y), _ptr(z), L, _ptr(count), _ptr(nbr), nbr.shape[1], eps, sigma, rc,
                        _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), _ptr(scale), C.byref(U), C.byref(W))
     return f.T.copy(), scale, U.value, W.value
+
+
+def half_list(count, nbr):
+    """Half list of a full list (each pair once, by the lower index);
+    returns (hcount[N], hnbr[N, maxnb])."""
+    count = np.ascontiguousarray(count, dtype=np.int32)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    n, maxnb = nbr.shape
+    hcount = np.zeros(n, dtype=np.int32)
+    hnbr = np.full((n, maxnb), -1, dtype=np.int32)
+    _load().orc_half_list(n, _ptr(count), _ptr(nbr), maxnb, _ptr(hcount), _ptr(hnbr))
+    return hcount, hnbr
+
+
+def forces_half(x, y, z, L, hcount, hnbr, eps=1.0, sigma=1.0, rc=2.5):
+    """Forces from a half list by Newton's third law; returns (F[N,3], U, W)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.shape[0]
+    hcount = np.ascontiguousarray(hcount, dtype=np.int32)
+    hnbr = np.ascontiguousarray(hnbr, dtype=np.int32)
+    f = np.zeros((3, n))
+    U = C.c_double()
+    W = C.c_double()
+    _load().orc_forces_half(n, _ptr(x), _ptr(y), _ptr(z), L, _ptr(hcount), _ptr(hnbr), hnbr.shape[1], eps, sigma,
+                            rc, _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), C.byref(U), C.byref(W))
+    return f.T.copy(), U.value, W.value
 
 
 def atom_force(x, y, z, L, i, eps=1.0, sigma=1.0, rc=2.5):

@@ -16,7 +16,9 @@
  *     axis, positions wrapped into [0, L) after each drift.
  *   - Cell lists of side >= r = cutoff + skin and the Verlet list of all atoms
  *     within r (Sec. 3.2, Fig. 1 and its caption), full list (each pair stored
- *     for both atoms; Sec. 4.2 and the evaluation setup in Sec. 6).
+ *     for both atoms; Sec. 4.2 and the evaluation setup in Sec. 6); the half
+ *     list (each pair once) and its forces by Newton's third law (Sec. 3.2,
+ *     the half_nb variant of Sec. 4.2).
  *   - Time integration of Newton's law (Sec. 3.2, Eq. 1) read as
  *     velocity Verlet; lists rebuilt every `rebuild_every` steps (Sec. 6).
  *   - The exact derivative of that discrete map with lists and cutoff
@@ -377,6 +379,63 @@ void orc_forces(int n, const double *x, const double *y, const double *z, double
         *virial = 0.5 * ksum_value(&W);
     free(ui);
     free(wi);
+}
+
+/*
+ * Half neighbor list (Sec. 3.2, the paragraph on half lists): every pair of
+ * the full list stored once, by the atom of lower index - hlist(i) = { j in
+ * list(i) : j > i }, in list order.
+ */
+void orc_half_list(int n, const int *count, const int *nbr, int maxnb, int *hcount, int *hnbr)
+{
+    for (int i = 0; i < n; ++i) {
+        int c = 0;
+        for (int k = 0; k < count[i]; ++k) {
+            int j = nbr[(size_t)i * maxnb + k];
+            if (j > i)
+                hnbr[(size_t)i * maxnb + c++] = j;
+        }
+        hcount[i] = c;
+    }
+}
+
+/*
+ * Forces from a half list with Newton's third law (Sec. 3.2: the force of a
+ * pair is added to i and subtracted from j; the half_nb variant of
+ * compute_potential in Sec. 4.2): for i in ascending order and j in hlist(i)
+ * with s < rc^2, F_i += f d_ij and F_j -= f d_ij.  One thread, so the order
+ * of every sum is the loop order.  Energy and virial count each listed pair
+ * once.
+ */
+void orc_forces_half(int n, const double *x, const double *y, const double *z, double L, const int *hcount,
+                     const int *hnbr, int maxnb, double eps, double sigma, double rc, double *fx, double *fy,
+                     double *fz, double *energy, double *virial)
+{
+    double rc2 = rc * rc;
+    ksum_t U = {0.0, 0.0}, W = {0.0, 0.0};
+    for (int i = 0; i < n; ++i)
+        fx[i] = fy[i] = fz[i] = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < hcount[i]; ++k) {
+            int j = hnbr[(size_t)i * maxnb + k];
+            double dx, dy, dz;
+            double s = dist2(x, y, z, i, j, L, &dx, &dy, &dz);
+            if (s < rc2) {
+                double f = orc_pair_force(s, eps, sigma);
+                fx[i] += f * dx;
+                fy[i] += f * dy;
+                fz[i] += f * dz;
+                fx[j] -= f * dx;
+                fy[j] -= f * dy;
+                fz[j] -= f * dz;
+                ksum_add(&U, orc_pair_energy(s, eps, sigma));
+                ksum_add(&W, s * f);
+            }
+        }
+    if (energy)
+        *energy = ksum_value(&U);
+    if (virial)
+        *virial = ksum_value(&W);
 }
 
 /* Force on atom i from every atom j within rc (no list): the all-pairs

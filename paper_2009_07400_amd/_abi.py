@@ -66,6 +66,7 @@ class TmdInfo(C.Structure):
         ("build_lanes", C.c_int32),
         ("graph_captures", C.c_int32),
         ("graph_launches", C.c_int64),
+        ("half_list", C.c_int32),
     ]
 
 
@@ -104,6 +105,7 @@ def load_library():
         "tmd_sync": (_S, [_P, _P]),
         "tmd_get_info": (_S, [_P, C.POINTER(TmdInfo)]),
         "tmd_set_schedule": (_S, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+        "tmd_set_half_list": (_S, [_P, C.c_int32]),
         "tmd_set_lj_params": (_S, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]),
         "tmd_adjoint_workspace_size": (_S, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
         "tmd_adjoint_forward": (_S, [_P, C.c_int32, _P, C.c_size_t, _P]),
@@ -234,6 +236,10 @@ def tmd_set_schedule(handle, threads: int, lds_atoms: int, block_edge: int = 0, 
     _check(load_library().tmd_set_schedule(handle, threads, lds_atoms, block_edge, block_parts, lanes_per_atom,
                                            build_threads, build_lanes),
            handle)
+
+
+def tmd_set_half_list(handle, half: int) -> None:
+    _check(load_library().tmd_set_half_list(handle, half), handle)
 
 
 def tmd_set_lj_params(handle, epsilon, sigma, stream: int) -> None:

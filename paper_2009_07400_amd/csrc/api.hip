@@ -989,6 +989,7 @@ tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
     info->build_lanes = s->d.blanes;
     info->graph_captures = s->graph_captures;
     info->graph_launches = s->graph_launches;
+    info->half_list = s->d.half;
     return TMD_OK;
 }
 
@@ -1000,7 +1001,7 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
         lds_atoms % 64 != 0 || (block_edge != 0 && block_edge != 2 && block_edge != 3) ||
         (block_parts != 0 && block_parts != 1 && block_parts != 2 && block_parts != 4) ||
         (lanes_per_atom != 0 && lanes_per_atom != 1 && lanes_per_atom != 2 && lanes_per_atom != 4) ||
-        (lanes_per_atom > 1 && s->d.model == 1))
+        (lanes_per_atom > 1 && s->d.model == 1) || (s->d.half && (block_parts > 1 || lanes_per_atom > 1)))
         return TMD_EINVAL;
     if (block_edge != 0 && block_edge != s->d.edge) {
         layout_blocks(s, block_edge);  // resets threads and capacity to that edge's defaults
@@ -1030,6 +1031,19 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
         s->prepared = false;  // LDS attribute of the block kernels must follow
         // the list encodes LDS slots only for neighborhoods that fit
         s->list_valid = s->force_valid = false;
+        s->gen++;
+    }
+    return TMD_OK;
+}
+
+tmd_status tmd_set_half_list(tmd_system *s, int32_t half) {
+    if (!s || (half != 0 && half != 1))
+        return TMD_EINVAL;
+    if (half && (s->d.model != TMD_MODEL_LJ || s->d.parts != 1 || s->d.lpa != 1))
+        return TMD_EINVAL;
+    if (half != s->d.half) {
+        s->d.half = half;
+        s->list_valid = s->force_valid = false;  // another list, forces summed in another order
         s->gen++;
     }
     return TMD_OK;
@@ -1098,13 +1112,20 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
         return hip_fail(s, e, "autotune");
     float best = 1e30f;
     int32_t best_edge = s->d.edge, best_t = s->d.threads, best_p = s->d.parts, best_l = s->d.lpa,
-            best_bt = s->d.bthreads, best_bl = s->d.blanes;
-    for (int32_t E = 2; E <= kMaxEdge && e == hipSuccess; ++E) {
+            best_bt = s->d.bthreads, best_bl = s->d.blanes, best_h = s->d.half;
+    // half lists (Lennard-Jones only) take one workgroup per block and one
+    // lane per atom
+    const int32_t hmax = s->d.model == TMD_MODEL_LJ ? 1 : 0;
+    for (int32_t EH = 0; EH < (kMaxEdge - 1) * (hmax + 1) && e == hipSuccess; ++EH) {
+        const int32_t E = 2 + EH / (hmax + 1), H = EH % (hmax + 1);
         layout_blocks(s, E);
+        s->d.half = H;
+        s->d.parts = 1;
+        s->d.lpa = 1;
         s->list_valid = s->force_valid = false;
         if ((st = rebuild(s, hs)) != TMD_OK)
             break;
-        for (int32_t P = 1; P <= kMaxParts && e == hipSuccess; P *= 2) {
+        for (int32_t P = 1; P <= (H ? 1 : kMaxParts) && e == hipSuccess; P *= 2) {
             s->d.parts = P;
             // the list build's lanes per atom and threads are tuned on their
             // own (the build and the force kernel share only the blocks)
@@ -1131,7 +1152,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
             }
             s->d.bthreads = bt_best;
             s->d.blanes = bl_best;
-            for (int32_t Lp = 1; Lp <= (s->d.model == 1 ? 1 : 4) && e == hipSuccess; Lp *= 2) {
+            for (int32_t Lp = 1; Lp <= (s->d.model == 1 || H ? 1 : 4) && e == hipSuccess; Lp *= 2) {
                 s->d.lpa = Lp;
                 // from one lane group per mean block atom (in whole
                 // wavefronts) up to two wavefronts more: fewer threads put
@@ -1153,6 +1174,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
                         best_l = Lp;
                         best_bt = bt_best;
                         best_bl = bl_best;
+                        best_h = H;
                     }
                 }
             }
@@ -1165,6 +1187,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     if (e != hipSuccess)
         return hip_fail(s, e, "autotune");
     layout_blocks(s, best_edge);
+    s->d.half = best_h;
     s->d.parts = best_p;
     s->d.lpa = best_l;
     s->d.threads = best_t;
@@ -1199,7 +1222,7 @@ tmd_status tmd_set_lj_params(tmd_system *s, const double *epsilon, const double 
 tmd_status tmd_adjoint_workspace_size(const tmd_system *s, int32_t n_steps, size_t *bytes) {
     if (!s || !bytes || n_steps < 1)
         return TMD_EINVAL;
-    *bytes = carve_adj(s->dmax,s->rebuild_every, n_steps, nullptr, nullptr);
+    *bytes = carve_adj(s->dmax, s->rebuild_every, n_steps, nullptr, nullptr);
     return TMD_OK;
 }
 
@@ -1208,16 +1231,18 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
     if (st != TMD_OK)
         return st;
     if (n_steps < 1 || !ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 ||
-        bytes < carve_adj(s->dmax,s->rebuild_every, n_steps, nullptr, nullptr))
+        bytes < carve_adj(s->dmax, s->rebuild_every, n_steps, nullptr, nullptr))
         return fail(s, TMD_EINVAL, "adjoint_forward: n_steps < 1 or workspace missing, misaligned or too small");
     if (s->d.model != TMD_MODEL_LJ)
         return fail(s, TMD_EINVAL, "adjoint_forward: gradients are implemented for the Lennard-Jones model only");
+    if (s->d.half)
+        return fail(s, TMD_EINVAL, "adjoint_forward: the reverse pass needs full lists (tmd_set_half_list(0))");
     const int32_t R = s->rebuild_every;
     if (s->step % R != 0)
         return fail(s, TMD_ESTATE, "adjoint_forward: the step counter must be a multiple of rebuild_every");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     AdjBuf a{};
-    carve_adj(s->dmax,R, n_steps, static_cast<char *>(ws), &a);
+    carve_adj(s->dmax, R, n_steps, static_cast<char *>(ws), &a);
     const int32_t nseg = (n_steps + R - 1) / R;
     const size_t nt = size_t(s->d.nt), np = size_t(s->d.ntp);
     const int64_t step0 = s->step;
@@ -1299,14 +1324,14 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
     if (!s->adj.recorded || ws != s->adj.ws || s->gen != s->adj.gen)
         return fail(s, TMD_ESTATE, "adjoint_backward: no forward run recorded in this workspace, or the state "
                                    "changed since");
-    if (bytes < carve_adj(s->dmax,s->rebuild_every, s->adj.nsteps, nullptr, nullptr) || !lam_x || !lam_x[0] ||
+    if (bytes < carve_adj(s->dmax, s->rebuild_every, s->adj.nsteps, nullptr, nullptr) || !lam_x || !lam_x[0] ||
         !lam_x[1] || !lam_x[2] || !grad_x0 || !grad_x0[0] || !grad_x0[1] || !grad_x0[2])
         return fail(s, TMD_EINVAL, "adjoint_backward: workspace too small or NULL cotangent / gradient array");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const int32_t R = s->rebuild_every, T = s->adj.nsteps, nseg = s->adj.nseg;
     const size_t nt = size_t(s->d.nt);
     AdjBuf a{};
-    carve_adj(s->dmax,R, T, static_cast<char *>(ws), &a);
+    carve_adj(s->dmax, R, T, static_cast<char *>(ws), &a);
     Buffers &b = s->b;
     hipError_t e = launch_fill_f64(a.acc, 0.0, 2 * s->d.nbox, hs);
     double *const lo_x[3] = {a.lo, a.lo + nt, a.lo + 2 * nt};

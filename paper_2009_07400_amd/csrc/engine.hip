@@ -272,6 +272,73 @@ struct GlobalPos {
 // minimum-image test per pair).  `on` needs at least E + 4 cells per axis;
 // the list build stages without it, as its neighbor decisions take the
 // minimum image of the raw difference.
+// Half lists (Sec. 3.2: each pair listed once, the partner taking the
+// opposite force; the half_nb variant of Sec. 4.2) inside one block: a pair
+// of two atoms of the block is listed once, by the atom with the lower LDS
+// slot, and the force kernel adds the partner's reaction to a sum in LDS; a
+// pair that crosses blocks is listed from both sides, each block computing
+// its own atom's force, so no workgroup writes another's atoms.  The own
+// cells sit at neighborhood coordinates 1..e per axis when the neighborhood
+// holds no cell twice; their LDS slots then lie in [off[first own cell],
+// off[last own cell + 1]), the span the reaction sums cover.
+struct OwnCells {
+    int e[3], n[3];  // own cells and neighborhood cells per axis
+};
+
+__device__ __forceinline__ bool own_cells(const Box &B, int lb, OwnCells &o) {
+    const int nbx = B.nbx;
+    const int bc[3] = {lb % nbx, (lb / nbx) % nbx, lb / (nbx * nbx)};
+    bool plain = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o.e[a] = min(B.edge, B.nc - B.edge * bc[a]);
+        o.n[a] = o.e[a] + 2;
+        plain &= B.nc >= o.n[a];
+    }
+    return plain;
+}
+
+// Whether block lb uses half lists, with its span's first slot and length:
+// the system asks for them, one workgroup takes the whole block, its
+// neighborhood is staged in LDS, holds no cell twice, and the span fits the
+// reaction sums.  The list build and the force kernel decide alike from the
+// same neighborhood table.
+__device__ __forceinline__ bool block_half(const Dims &d, const Box &B, int lb, const Hood &h, bool fits, int &s_lo,
+                                          int &span) {
+    s_lo = span = 0;
+    OwnCells o;
+    if (!d.half || d.parts != 1 || !fits || !own_cells(B, lb, o))
+        return false;
+    const int ulo = (o.n[1] + 1) * o.n[0] + 1;
+    const int uhi = (o.e[2] * o.n[1] + o.e[1]) * o.n[0] + o.e[0];
+    s_lo = h.off[ulo];
+    span = h.off[uhi + 1] - s_lo;
+    return span <= react_cap(d.cap);
+}
+
+// LDS slot of the block's own atom i (global index) in a half-list block:
+// the own cells in global order are those of compact index k over (lz, ly,
+// lx), at neighborhood index ((lz + 1) n1 + ly + 1) n0 + lx + 1; i lies in
+// the last of them that starts at or before it.
+__device__ __forceinline__ int own_slot(const Box &B, int lb, const Hood &h, int i) {
+    OwnCells o;
+    own_cells(B, lb, o);
+    const int nown = o.e[0] * o.e[1] * o.e[2];
+    auto uo = [&](int k) {
+        const int lx = k % o.e[0], r = k / o.e[0], ly = r % o.e[1], lz = r / o.e[1];
+        return ((lz + 1) * o.n[1] + ly + 1) * o.n[0] + lx + 1;
+    };
+    int k = 0;
+#pragma unroll
+    for (int st = 16; st > 0; st >>= 1) {  // nown <= 27
+        const int m = k + st;
+        if (m < nown && h.cs[uo(m)] <= i)
+            k = m;
+    }
+    const int u = uo(k);
+    return h.off[u] + (i - h.cs[u]);
+}
+
 struct HoodImage {
     bool on;
     double cx, cy, cz, L, halfL;
@@ -954,8 +1021,11 @@ __device__ __forceinline__ RowTrim row_trim(double xi, double yi, double zi, int
 //     boxes): rows and runs wrap, and each difference takes the minimum
 //     image of its value.
 // The first two walk the rows and x-runs of row_trim(); the third the
-// whole stencil.  Returns the number of neighbors found.
-template <int BL, int GEOM>
+// whole stencil.  HALF (first two only): a candidate in one of the block's
+// own cells is kept only if its force-kernel slot exceeds i's, and its
+// entry carries bit 15 (the partner takes the reaction); along a row the
+// own cells' slots are [to0, to1).  Returns the number of neighbors found.
+template <int BL, int GEOM, bool HALF = false>
 __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const lds_u16 *soff, const SubGrid &G,
                                           int gx, int gy, int gz, int fself, double xi, double yi, double zi,
                                           const RowTrim &T, const Box &B, int maxnb, int p, uint16_t *nbr16, int i,
@@ -993,8 +1063,9 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
     const bool xshift = SHIFT && (sxa != 0.0 || sxb != 0.0);
     auto shift_of = [&](int g, int bl, int bh) { return g < bl ? -B.L : (g >= bh ? B.L : 0.0); };
     double sy = 0.0, sz = 0.0;
-    // slots [t, e) of stencil row r, and tw for it
-    auto trim_run = [&](int r, int &t_, int &e_, int &tw_, double &sy_, double &sz_) {
+    int to0 = 0, to1 = 0;
+    // slots [t, e) of stencil row r, tw for it and its own slots [to0, to1)
+    auto trim_run = [&](int r, int &t_, int &e_, int &tw_, double &sy_, double &sz_, int &to0_, int &to1_) {
         const int kz = (r * 13) >> 6, ky = r - 5 * kz;  // r / 5, r % 5 for r < 25
         const unsigned c = unsigned((r < 16 ? T.lo : T.hi) >> ((r & 15) * 4)) & 15u;
         const int rb = base + kz * zstride + ky * G.nx;
@@ -1005,14 +1076,34 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
             sy_ = shift_of(gy - 2 + ky, bly, bhy);
             sz_ = shift_of(gz - 2 + kz, blz, bhz);
         }
+        if (HALF) {
+            // own cells: neighborhood coordinates 1..n - 2, grid subcells
+            // 2..2n - 3 per axis
+            const int cy = (gy - 2 + ky) >> 1, cz = (gz - 2 + kz) >> 1;
+            const bool rown = cy >= 1 && cy <= G.n[1] - 2 && cz >= 1 && cz <= G.n[2] - 2;
+            const int r0 = rb - (gx - 2);  // the row's grid x = 0
+            const int a0 = soff[r0 + 2], a1 = soff[r0 + 2 * G.n[0] - 2];
+            to0_ = rown ? a0 : 0;
+            to1_ = rown ? a1 : 0;
+        }
     };
     int t, e, row = 0;
     if (WRAP) {
         row_run(G, soff, w, t, e);
     } else {
         row = __builtin_ctz(T.need);  // the centre row is always needed
-        trim_run(row, t, e, tw, sy, sz);
+        trim_run(row, t, e, tw, sy, sz, to0, to1);
     }
+    // whether slot tt is kept, and its list entry
+    auto keep = [&](int tt, int fj, bool near, uint16_t &v) {
+        if (HALF) {
+            const bool own = tt >= to0 && tt < to1;
+            v = uint16_t(fj | (own ? 0x8000 : 0));
+            return near && (own ? fj > fself : fj != fself);
+        }
+        v = uint16_t(fj);
+        return near && fj != fself;
+    };
     // difference of one candidate along the three axes, with its image
     auto dist = [&](double xj, double yj, double zj, int tj) {
         if (WRAP)
@@ -1043,8 +1134,9 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const double s = dist(px[r], py[r], pz[r], t + r);
-                if (s < B.rl2 && t + r < e && tr[r] != fself)
-                    put16(wp, c, maxnb, tr[r]);
+                uint16_t v;
+                if (keep(t + r, tr[r], s < B.rl2 && t + r < e, v))
+                    put16(wp, c, maxnb, v);
             }
             t += 4;
         } else {
@@ -1060,10 +1152,11 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
                 tr[r] = F[t + p + 2 * r];
             }
             unsigned mine = 0;  // bit 2r + p: slot t + 2r + p accepted
+            uint16_t vr[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const double s = dist(px[r], py[r], pz[r], t + 2 * r + p);
-                mine |= (s < B.rl2 && t + 2 * r + p < e && tr[r] != fself) ? (1u << (2 * r + p)) : 0u;
+                mine |= keep(t + 2 * r + p, tr[r], s < B.rl2 && t + 2 * r + p < e, vr[r]) ? (1u << (2 * r + p)) : 0u;
             }
             const unsigned m8 = mine | unsigned(__shfl_xor(int(mine), 1, 64));
 #pragma unroll
@@ -1072,7 +1165,7 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
                 if (mine & (1u << j)) {
                     const int pos = c + __popc(m8 & ((1u << j) - 1u));
                     if (pos < maxnb)
-                        nbr16[nbr_index16(i, pos, nchunk)] = uint16_t(tr[r]);
+                        nbr16[nbr_index16(i, pos, nchunk)] = vr[r];
                 }
             }
             c += __popc(m8);
@@ -1095,13 +1188,17 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
             const unsigned rest = row < 24 ? T.need & (~0u << (row + 1)) : 0u;
             more = rest != 0u;
             const int nrow = more ? __builtin_ctz(rest) : row;
-            int ntw = tw;
+            int ntw = tw, nto0 = to0, nto1 = to1;
             double nsy = sy, nsz = sz;
-            trim_run(nrow, nt, ne, ntw, nsy, nsz);
+            trim_run(nrow, nt, ne, ntw, nsy, nsz, nto0, nto1);
             if (SHIFT) {
                 sy = adv ? nsy : sy;
                 sz = adv ? nsz : sz;
                 tw = adv ? ntw : tw;
+            }
+            if (HALF) {
+                to0 = adv ? nto0 : to0;
+                to1 = adv ? nto1 : to1;
             }
             row = adv ? nrow : row;
         }
@@ -1204,6 +1301,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
         interior &= c0 >= 1 && c0 + e <= B.nc - 1;
         wraps |= G.n[a] < e + 2;  // the neighborhood holds every cell of the axis
     }
+    // half lists only on the row walk (the other paths list pairs in full,
+    // which the force kernel handles alike)
+    int s_lo, span;
+    const bool half = rows && block_half(d, B, lb, h, fits, s_lo, span);
     const int p = threadIdx.x & (BL - 1);  // lane of the atom's pair (BL = 2)
     for (int i = lo + threadIdx.x / BL; i < hi; i += blockDim.x / BL) {
         const double xi = x[i], yi = y[i], zi = z[i];
@@ -1219,15 +1320,15 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
             RowTrim T{};
             if (!wraps)
                 T = row_trim(xi, yi, zi, X, Y, Z, B);
+#define TMD_ROWS(GEOM, HALF)                                                                                        \
+    build_rows<BL, GEOM, HALF>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, T, B, d.maxnb, p, nbr16, i, d.nchunk)
             if (wraps)
-                c = build_rows<BL, kRowsWrap>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, T, B, d.maxnb, p, nbr16, i,
-                                              d.nchunk);
+                c = TMD_ROWS(kRowsWrap, false);
             else if (interior)
-                c = build_rows<BL, kRowsInterior>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, T, B, d.maxnb, p, nbr16,
-                                                  i, d.nchunk);
+                c = half ? TMD_ROWS(kRowsInterior, true) : TMD_ROWS(kRowsInterior, false);
             else
-                c = build_rows<BL, kRowsFace>(S, F, soff, G, gx, gy, gz, fself, xi, yi, zi, T, B, d.maxnb, p, nbr16, i,
-                                              d.nchunk);
+                c = half ? TMD_ROWS(kRowsFace, true) : TMD_ROWS(kRowsFace, false);
+#undef TMD_ROWS
         } else if (p == 0) {
             c = build_global(B, G, h, fits, cell_start, x, y, z, i, xi, yi, zi, X, Y, Z, d.maxnb, nbr, d.nchunk);
         }
@@ -1576,6 +1677,184 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     }
 }
 
+// One entry of a half list (16-bit LDS slot, bit 15: a pair inside the
+// block listed once): the pair term as in eval2, and for a marked pair the
+// partner's reaction -f d added to its sum in R (LDS, slot - s_lo).  The
+// energy and virial of a marked pair count twice, standing for the entry
+// its partner does not hold.
+template <bool THERMO, bool IMG>
+__device__ __forceinline__ void eval_half(unsigned v, const lds_double *S, lds_double *R, int s_lo, double xi,
+                                          double yi, double zi, const Box &B, double mf6, double mu6, double &ax,
+                                          double &ay, double &az, double &u, double &w) {
+    const int slot = int(v & 0x7FFFu);
+    const lds_double *a = lds_slot(const_cast<lds_double *>(S), slot);
+    double dx, dy, dz;
+    const double s = IMG ? pair_delta_img(xi, yi, zi, a[0], a[1], a[2], dx, dy, dz)
+                         : pair_delta_fma(xi, yi, zi, a[0], a[1], a[2], B.L, B.invL, dx, dy, dz);
+    if (s < B.rc2) {
+        const double sr2 = recip(s);
+        const double q3 = sr2 * sr2 * sr2;
+        const double f = (sr2 * q3) * fma(B.f12, q3, mf6);
+        ax = fma(f, dx, ax);
+        ay = fma(f, dy, ay);
+        az = fma(f, dz, az);
+        const bool pair = (v & 0x8000u) != 0u;
+        if (pair) {
+            lds_double *r = R + 3 * (slot - s_lo);
+            __hip_atomic_fetch_add((double *)r, -f * dx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add((double *)(r + 1), -f * dy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add((double *)(r + 2), -f * dz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if (THERMO) {
+            const double k = pair ? 2.0 : 1.0;
+            u = fma(k * q3, fma(B.u12, q3, mu6), u);
+            w = fma(k * s, f, w);
+        }
+    }
+}
+
+// Sum over one atom's 16-bit half list (c entries, eight per chunk, the
+// chunk after the last all sentinels), the next chunk loaded while this one
+// is evaluated.
+template <bool THERMO, bool IMG>
+__device__ __forceinline__ void pair_sum_half(const v4i *__restrict__ chunks, int c, const lds_double *S,
+                                              lds_double *R, int s_lo, double xi, double yi, double zi, const Box &B,
+                                              double mf6, double mu6, double &ax, double &ay, double &az, double &u,
+                                              double &w) {
+    const int nch = (c + 7) >> 3;
+    v4i cur = __builtin_nontemporal_load(chunks);
+    for (int k = 0; k < nch; ++k) {
+        const v4i nxt = __builtin_nontemporal_load(chunks + (k + 1) * 64);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            eval_half<THERMO, IMG>(unsigned(cur[q]) & 0xFFFFu, S, R, s_lo, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+            eval_half<THERMO, IMG>(unsigned(cur[q]) >> 16, S, R, s_lo, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        }
+        cur = nxt;
+    }
+}
+
+// The end of an atom's step in the force kernels, given its force a: MODE
+// 0 stores F, 1 stores F and kicks v += h F, 2 kicks twice and drifts into
+// the other position buffer (k_force's epilogue).
+template <int MODE, bool THERMO>
+__device__ __forceinline__ void atom_epilogue(int i, double xi, double yi, double zi, double ax, double ay, double az,
+                                              const Box &B, double *vx, double *vy, double *vz, double *fx,
+                                              double *fy, double *fz, double *xo, double *yo, double *zo, double &ke,
+                                              int32_t *err) {
+    if (MODE == 0 || MODE == 1) {
+        fx[i] = ax;
+        fy[i] = ay;
+        fz[i] = az;
+        if (!(isfinite(ax) && isfinite(ay) && isfinite(az)))
+            atomicOr(err, kErrNonFinite);
+    }
+    if (MODE >= 1) {
+        double a = vx[i] + B.h * ax, bb = vy[i] + B.h * ay, c = vz[i] + B.h * az;
+        if (THERMO)
+            ke += a * a + bb * bb + c * c;
+        if (MODE == 2) {
+            a = a + B.h * ax;
+            bb = bb + B.h * ay;
+            c = c + B.h * az;
+            const double nx = xi + B.dt * a, ny = yi + B.dt * bb, nz = zi + B.dt * c;
+            xo[i] = nx;
+            yo[i] = ny;
+            zo[i] = nz;
+            if (!(isfinite(nx) && isfinite(ny) && isfinite(nz)))
+                atomicOr(err, kErrNonFinite);
+        }
+        vx[i] = a;
+        vy[i] = bb;
+        vz[i] = c;
+    }
+}
+
+// k_force for half lists, one lane per atom, one workgroup per block.  In a
+// half-list block (block_half()) each atom's own sum and the reactions of
+// its partners meet in LDS sums over the own cells' slot span; after a
+// barrier every atom takes its total and finishes the step.  The sums are
+// LDS atomics, so their order - and the last bits of the forces - may vary
+// from run to run.  Other blocks (full lists) finish each atom directly.
+template <int MODE, bool THERMO>
+__global__ __launch_bounds__(kMaxThreads) void k_force_half(
+    Dims d, const Box *__restrict__ boxes, const int32_t *__restrict__ blk_box, const double *__restrict__ x,
+    const double *__restrict__ y, const double *__restrict__ z, const int32_t *__restrict__ hood_tab,
+    const int32_t *__restrict__ cnt, const int32_t *__restrict__ nbr, double *__restrict__ vx,
+    double *__restrict__ vy, double *__restrict__ vz, double *__restrict__ fx, double *__restrict__ fy,
+    double *__restrict__ fz, double *__restrict__ xo, double *__restrict__ yo, double *__restrict__ zo,
+    double *__restrict__ partials, int32_t *err) {
+    // the neighborhood copy at LDS address 0, then the table and reduction
+    // scratch (as in k_force), then the reaction sums
+    extern __shared__ double lds[];
+    const int tail = (d.cap + 2 + kHoodPad) * 24;
+    Hood &h = *reinterpret_cast<Hood *>(reinterpret_cast<char *>(lds) + tail);
+    double(*red)[kMaxThreads / 64] =
+        reinterpret_cast<double(*)[kMaxThreads / 64]>(reinterpret_cast<char *>(lds) + tail + kHoodBytes8);
+    lds_double *R = (lds_double *)((lds_char *)lds + tail + kForceLdsTail);
+    int b, part;
+    if (!block_part(d, b, part))
+        return;
+    HoodWords hw;
+    hood_fetch(hood_tab, b, hw);
+    const Box B = block_box(d, boxes, blk_box, b);
+    const double mf6 = -B.f6, mu6 = -B.u6;
+    hood_commit(hw, h);
+    const int total = h.off[h.ncell];
+    const bool fits = total <= d.cap;
+    lds_double *const S = (lds_double *)lds;
+    const GlobalPos gpos{x, y, z};
+    const int lb = b - B.block_off;
+    const HoodImage im = hood_image(B, lb, fits);
+    int s_lo, span;
+    const bool half = block_half(d, B, lb, h, fits, s_lo, span);
+    if (half)
+        for (int k = threadIdx.x; k < 3 * span; k += blockDim.x)
+            R[k] = 0.0;
+    if (fits)
+        hood_stage(h, total, d.cap, x, y, z, S, im);  // ends with a barrier
+    int lo, hi;
+    h.share(part, d.parts, lo, hi);
+    double u = 0.0, w = 0.0, ke = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double xi = x[i], yi = y[i], zi = z[i];
+        const int ci = cnt[i];
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        const v4i *chunks = list_chunks(nbr, i, d.nchunk);
+        if (im.on)
+            pair_sum_half<THERMO, true>(chunks, ci, S, R, s_lo, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        else if (fits)
+            pair_sum_half<THERMO, false>(chunks, ci, S, R, s_lo, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        else
+            pair_sum<THERMO>(chunks, 0, 1, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        if (half) {
+            lds_double *r = R + 3 * (own_slot(B, lb, h, i) - s_lo);
+            __hip_atomic_fetch_add((double *)r, ax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add((double *)(r + 1), ay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add((double *)(r + 2), az, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            atom_epilogue<MODE, THERMO>(i, xi, yi, zi, ax, ay, az, B, vx, vy, vz, fx, fy, fz, xo, yo, zo, ke, err);
+        }
+    }
+    if (half) {
+        __syncthreads();
+        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const lds_double *r = R + 3 * (own_slot(B, lb, h, i) - s_lo);
+            atom_epilogue<MODE, THERMO>(i, x[i], y[i], z[i], r[0], r[1], r[2], B, vx, vy, vz, fx, fy, fz, xo, yo, zo,
+                                        ke, err);
+        }
+    }
+    if (THERMO) {
+        block_sum3(u, w, ke, red);
+        if (threadIdx.x == 0) {
+            const int q = b * d.parts + part;
+            partials[q * kPartialStride + 0] = u;
+            partials[q * kPartialStride + 1] = w;
+            partials[q * kPartialStride + 2] = ke;
+        }
+    }
+}
+
 // First half of a step when F of the current positions is already stored.
 __global__ __launch_bounds__(kAtomThreads) void k_drift(Dims d, const Box *__restrict__ boxes,
                                                         const int32_t *__restrict__ atom_box,
@@ -1657,7 +1936,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_export_neighbors(Dims d, const 
             continue;
         int32_t *row = ids + int64_t(o) * d.maxnb;
         for (int k = 0; k < c; ++k) {
-            int g = fits ? int(nbr16[nbr_index16(i, k, d.nchunk)]) : nbr[nbr_index(i, k, d.nchunk)];
+            // (bit 15 of a 16-bit entry marks a half-list pair inside the block)
+            int g = fits ? int(nbr16[nbr_index16(i, k, d.nchunk)] & 0x7FFFu) : nbr[nbr_index(i, k, d.nchunk)];
             if (fits) {
                 const int uu = hood_find(h, g);
                 g = h.cs[uu] + (g - h.off[uu]);
@@ -2183,6 +2463,12 @@ hipError_t prepare_kernels(int dyn_bytes) {
         reinterpret_cast<const void *>(&k_force_sd<1, true>),
         reinterpret_cast<const void *>(&k_force_sd<2, false>),
         reinterpret_cast<const void *>(&k_force_sd<2, true>),
+        reinterpret_cast<const void *>(&k_force_half<0, false>),
+        reinterpret_cast<const void *>(&k_force_half<0, true>),
+        reinterpret_cast<const void *>(&k_force_half<1, false>),
+        reinterpret_cast<const void *>(&k_force_half<1, true>),
+        reinterpret_cast<const void *>(&k_force_half<2, false>),
+        reinterpret_cast<const void *>(&k_force_half<2, true>),
         reinterpret_cast<const void *>(&k_hvp<1>),
         reinterpret_cast<const void *>(&k_hvp<2>),
         reinterpret_cast<const void *>(&k_hvp<4>),
@@ -2344,6 +2630,13 @@ static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &o
 }
 
 template <int MODE, bool THERMO>
+static void force_half_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
+    k_force_half<MODE, THERMO><<<block_grid(d.nblk * d.parts), d.threads, force_half_lds_bytes(d.cap), s>>>(
+        d, b.boxes, b.blk_box, in.x, in.y, in.z, b.hood_tab, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
+        b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
+}
+
+template <int MODE, bool THERMO>
 static void force_sd_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
     const int vo = MODE >= 1 ? 1 - o : o;  // kicked velocities go to the other half
     k_force_sd<MODE, THERMO><<<block_grid(d.nblk * d.parts), d.threads, 2 * hood_lds_bytes(d.cap), s>>>(
@@ -2361,6 +2654,18 @@ hipError_t launch_force_at(const Dims &d, Buffers &b, const Pos &in, const Pos &
         case 3: force_sd_variant<1, true>(d, b, in, out, o, s); break;
         case 4: force_sd_variant<2, false>(d, b, in, out, o, s); break;
         case 5: force_sd_variant<2, true>(d, b, in, out, o, s); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (d.half) {  // half lists: one lane per atom
+        switch (mode * 2 + (thermo ? 1 : 0)) {
+        case 0: force_half_variant<0, false>(d, b, in, out, o, s); break;
+        case 1: force_half_variant<0, true>(d, b, in, out, o, s); break;
+        case 2: force_half_variant<1, false>(d, b, in, out, o, s); break;
+        case 3: force_half_variant<1, true>(d, b, in, out, o, s); break;
+        case 4: force_half_variant<2, false>(d, b, in, out, o, s); break;
+        case 5: force_half_variant<2, true>(d, b, in, out, o, s); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

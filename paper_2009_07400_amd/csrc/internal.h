@@ -79,6 +79,7 @@ struct Dims {
     int32_t lpa;      // lanes per atom in the force kernel (1, 2 or 4), each taking every lpa-th list chunk
     int32_t blanes;   // lanes per atom in the list build (1 or 2)
     int32_t model;    // force model of every box: 0 Lennard-Jones, 1 Spring-Dashpot
+    int32_t half;     // 1: half lists inside blocks (Newton's third law in the force kernel's LDS)
 };
 
 // Neighbor list layout: neighbor-major within tiles of 64 atoms (one
@@ -153,6 +154,13 @@ inline size_t hood_lds_bytes(int cap) { return size_t(cap + 2 + kHoodPad) * 3 * 
 // reduction scratch in kForceLdsTail bytes.
 constexpr int kForceLdsTail = 1536;
 inline size_t force_lds_bytes(int cap) { return hood_lds_bytes(cap) + kForceLdsTail; }
+
+// Half lists: a block's reaction sums cover the LDS slots from its first
+// own cell's to its last own cell's (about a third of the neighborhood at
+// edge 2, a half at edge 3), at most 5/8 of the staging capacity; blocks
+// whose span is larger keep full lists.
+__host__ __device__ inline int react_cap(int cap) { return cap * 5 / 8 / 64 * 64; }
+inline size_t force_half_lds_bytes(int cap) { return force_lds_bytes(cap) + size_t(react_cap(cap)) * 3 * sizeof(double); }
 
 // Upper bound of the static LDS any block kernel declares (neighborhood
 // table, reduction scratch); engine.hip checks its kernels against it.

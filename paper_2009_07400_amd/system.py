@@ -181,12 +181,19 @@ class System:
         abi.tmd_set_schedule(self._h, threads, lds_atoms, block_edge, block_parts, lanes_per_atom, build_threads,
                              build_lanes)
 
+    def set_half_list(self, half: bool) -> None:
+        """Half neighbor lists inside blocks (Newton's third law) for the
+        Lennard-Jones model; needs one workgroup per block and one lane per
+        atom.  The next step rebuilds the list."""
+        abi.tmd_set_half_list(self._h, 1 if half else 0)
+
     def autotune(self, repeats: int = 5, cache: str | None = None):
-        """Times each schedule (block edge, workgroups per block, lanes per
-        atom, force and build threads) by one force evaluation plus a list
-        build's share per step and keeps the fastest; returns a dict of
-        block_edge, block_parts, lanes_per_atom, block_threads, build_threads,
-        build_lanes and lds_atoms, and "cached".  Rebuilds the list at the
+        """Times each schedule (block edge, full or half lists, workgroups
+        per block, lanes per atom, force and build threads) by one force
+        evaluation plus a list build's share per step and keeps the fastest;
+        returns a dict of block_edge, block_parts, lanes_per_atom,
+        block_threads, build_threads, build_lanes, lds_atoms and half_list,
+        and "cached".  Rebuilds the list at the
         current positions.
 
         With ``cache`` (a JSON file path), a schedule stored there for the
@@ -199,10 +206,12 @@ class System:
                                         self.box_atoms, self.box_lengths, self.params)
             hit = tune_cache.lookup(cache, key)
             if hit is not None:
+                self.set_half_list(False)
                 self.set_schedule(threads=hit["block_threads"], lds_atoms=hit["lds_atoms"],
                                   block_edge=hit["block_edge"], block_parts=hit["block_parts"],
                                   lanes_per_atom=hit["lanes_per_atom"], build_threads=hit["build_threads"],
                                   build_lanes=hit["build_lanes"])
+                self.set_half_list(bool(hit["half_list"]))
                 return dict(hit, cached=True)
         abi.tmd_autotune(self._h, repeats, _stream())
         info = self.info()

@@ -20,7 +20,7 @@ VERSION = 1
 
 # tmd_info fields that make up a schedule, as tmd_set_schedule takes them
 SCHEDULE_KEYS = ("block_threads", "lds_atoms", "block_edge", "block_parts", "lanes_per_atom", "build_threads",
-                 "build_lanes")
+                 "build_lanes", "half_list")
 
 _PARAM_FIELDS = ("epsilon", "sigma", "mass", "cutoff", "skin", "dt", "rebuild_every", "max_neighbors")
 

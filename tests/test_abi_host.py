@@ -233,3 +233,31 @@ def test_unknown_model_and_mixed_batches_are_rejected():
     abi.tmd_destroy(h)
     with pytest.raises(ValueError):
         make_params(model="dem")
+
+
+def test_half_list_switch_validates_on_the_host():
+    h = _create()
+    try:
+        assert abi.tmd_get_info(h)["half_list"] == 0
+        for bad in (2, -1):
+            with pytest.raises(abi.TmdError) as e:
+                abi.tmd_set_half_list(h, bad)
+            assert e.value.status == abi.TMD_EINVAL
+        abi.tmd_set_half_list(h, 1)
+        assert abi.tmd_get_info(h)["half_list"] == 1
+        # one workgroup per block and one lane per atom while it is on
+        for kw in (dict(block_parts=2), dict(lanes_per_atom=4)):
+            with pytest.raises(abi.TmdError):
+                abi.tmd_set_schedule(h, 0, 0, **kw)
+        abi.tmd_set_half_list(h, 0)
+        abi.tmd_set_schedule(h, 0, 0, block_parts=2)
+        with pytest.raises(abi.TmdError):
+            abi.tmd_set_half_list(h, 1)
+    finally:
+        abi.tmd_destroy(h)
+    sd = abi.tmd_create(make_params(model="spring_dashpot", stiffness=100.0, damping=1.0, cutoff=1.0), 100, 13.4)
+    try:
+        with pytest.raises(abi.TmdError):
+            abi.tmd_set_half_list(sd, 1)
+    finally:
+        abi.tmd_destroy(sd)

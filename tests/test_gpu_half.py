@@ -1,0 +1,250 @@
+"""Half neighbor lists with Newton's third law inside blocks (Sec. 3.2, the
+half-list paragraph; the half_nb variant of Sec. 4.2) on the GPU against the
+CPU oracle, through the C ABI.
+
+Lists: every pair of the oracle's full list is held by at least one of its
+atoms; a pair whose atoms lie in different blocks by both, a pair inside a
+block by exactly one in a half-list block (by both in a block that keeps
+full lists), and each block is one or the other.  Forces within 1e-12 of
+each atom's conditioning scale of the oracle's full-list and half-list sums;
+energy and virial within 1e-12; positions and velocities within 1e-9 after
+100 steps.  The reaction sums are LDS atomics, so runs agree to rounding,
+not bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import SplitMix64, md_system
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+from paper_2009_07400_amd import System, TmdError  # noqa: E402
+
+FORCE_TOL = 1e-12
+POS_TOL = 1e-9
+RL = 2.8
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _mic(d, L):
+    return d - L * np.round(d / L)
+
+
+def _liquid(ncell, seed, steps=30):
+    s = md_system(ncell, 0.8442, 1.44, seed=seed)
+    r = oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.L, steps, thermo=False)
+    return r["x"], r["v"], s.L
+
+
+CASES = {
+    "liquid8": lambda: _liquid(8, 41),     # 4 cells per axis
+    "liquid10": lambda: _liquid(10, 42),   # 5: thin blocks at the high faces
+    "liquid12": lambda: _liquid(12, 43),   # 7
+    "jitter9": lambda: (lambda s: (s.pos(), s.vel(), s.L))(md_system(9, jitter=0.02, seed=44)),
+    "nc3_liquid6": lambda: _liquid(6, 45),  # 3 cells per axis: every block keeps full lists
+    "uniform": lambda: (SplitMix64(46).next_double(3 * 2000).reshape(2000, 3) * 15.0, np.zeros((2000, 3)), 15.0),
+}
+
+
+def _blocks(pos, L, edge):
+    nc = int(np.floor(L / RL))
+    side = L / nc
+    c = np.clip(np.floor(pos / side), 0, nc - 1).astype(np.int64)
+    b = c // edge
+    nb = (nc + edge - 1) // edge
+    return (b[:, 2] * nb + b[:, 1]) * nb + b[:, 0]
+
+
+def _plain_blocks(L, edge):
+    """Blocks whose neighborhood holds no cell twice: e + 2 <= cells per axis
+    along every axis, e the block's own cells there (thinner at the high
+    faces) - the only ones that may hold half lists."""
+    nc = int(np.floor(L / RL))
+    nb = (nc + edge - 1) // edge
+    ok = [nc >= min(edge, nc - edge * b) + 2 for b in range(nb)]
+    return {(bz * nb + by) * nb + bx for bz in range(nb) for by in range(nb) for bx in range(nb)
+            if ok[bx] and ok[by] and ok[bz]}
+
+
+def _check_half_lists(g, pos, L):
+    """Returns the fraction of blocks (with an intra-block pair) that hold
+    half lists."""
+    counts, ids = g.get_neighbors()
+    g.sync()
+    counts, ids = counts.cpu().numpy(), ids.cpu().numpy()
+    c_o, n_o, _ = oracle.build_list(pos[:, 0], pos[:, 1], pos[:, 2], L, RL, maxnb=ids.shape[1])
+    n = pos.shape[0]
+    mine = [set(ids[i, : counts[i]].tolist()) for i in range(n)]
+    assert all(len(mine[i]) == counts[i] for i in range(n))  # no pair twice in one list
+    assert (ids[np.arange(ids.shape[1])[None, :] >= counts[:, None]] == -1).all()
+    for i in range(n):
+        assert np.array_equal(ids[i, : counts[i]], np.sort(ids[i, : counts[i]]))
+        assert mine[i] <= set(n_o[i, : c_o[i]].tolist()), i
+    blk = _blocks(pos, L, g.info()["block_edge"])
+    once, twice = {}, {}
+    for i in range(n):
+        for j in n_o[i, : c_o[i]]:
+            if j < i:
+                continue
+            a, b = j in mine[i], i in mine[j]
+            assert a or b, (i, j)
+            if blk[i] != blk[j]:
+                assert a and b, (i, j)
+            else:
+                d = twice if (a and b) else once
+                d[blk[i]] = d.get(blk[i], 0) + 1
+    assert not set(once) & set(twice)  # a block lists all its inner pairs once, or all twice
+    assert set(once) <= _plain_blocks(L, g.info()["block_edge"])
+    return c_o, n_o, len(once) / max(len(once) + len(twice), 1)
+
+
+def _check_forces(g, pos, L, c_o, n_o):
+    F, ev = g.compute_forces()
+    g.sync()
+    F = F.cpu().numpy()
+    U, W = ev.cpu().numpy()
+    Fo, sc, Uo, Wo = oracle.forces(pos[:, 0], pos[:, 1], pos[:, 2], L, c_o, n_o)
+    hc, hn = oracle.half_list(c_o, n_o)
+    Fh, Uh, Wh = oracle.forces_half(pos[:, 0], pos[:, 1], pos[:, 2], L, hc, hn)
+    for ref in (Fo, Fh):
+        err = np.linalg.norm(F - ref, axis=1)
+        assert (err <= FORCE_TOL * np.maximum(sc, 1e-300)).all(), float((err / np.maximum(sc, 1e-300)).max())
+    assert U == pytest.approx(Uo, rel=FORCE_TOL, abs=1e-12) and U == pytest.approx(Uh, rel=FORCE_TOL, abs=1e-12)
+    assert W == pytest.approx(Wo, rel=FORCE_TOL, abs=1e-12) and W == pytest.approx(Wh, rel=FORCE_TOL, abs=1e-12)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("sched", [dict(), dict(block_edge=2), dict(block_edge=3), dict(build_lanes=2),
+                                   dict(lds_atoms=512)])
+def test_half_lists_and_forces_match_oracle(case, sched):
+    pos, vel, L = CASES[case]()
+    _say(f"half lists: {case}, {pos.shape[0]} atoms, schedule {sched}")
+    g = System(pos.shape[0], L, max_neighbors=256)
+    g.set_state(torch.from_numpy(pos), torch.from_numpy(vel))
+    if sched:
+        g.set_schedule(**sched)
+    g.set_half_list(True)
+    assert g.info()["half_list"] == 1
+    g.build_neighbors()
+    c_o, n_o, frac = _check_half_lists(g, pos, L)
+    nc = int(np.floor(L / RL))
+    if nc >= g.info()["block_edge"] + 2 and not sched.get("lds_atoms"):
+        # at edge 2 nearly every block fits its neighborhood and reaction
+        # sums in LDS; at edge 3 in a box of a few large cells some
+        # neighborhoods exceed the staging capacity
+        assert frac > (0.9 if g.info()["block_edge"] == 2 else 0.0), frac
+    _check_forces(g, pos, L, c_o, n_o)
+    g.close()
+
+
+@pytest.mark.parametrize("ncell,edge", [(10, 2), (10, 3), (12, 2)])
+def test_half_list_trajectory_matches_oracle(ncell, edge):
+    s = md_system(ncell, 0.8442, 1.44, seed=50 + ncell + edge)
+    _say(f"half-list trajectory: {s.n} atoms, edge {edge}, 100 steps")
+    g = System(s.n, s.L)
+    g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
+    g.set_schedule(block_edge=edge)
+    g.set_half_list(True)
+    th = g.integrate(100, thermo_every=25).cpu().numpy()
+    p, v, step = g.get_state()
+    g.sync()
+    r = oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.L, 100)
+    assert step == 100
+    assert np.abs(_mic(p.cpu().numpy() - r["x"], s.L)).max() < POS_TOL
+    assert np.abs(v.cpu().numpy() - r["v"]).max() < POS_TOL
+    for row, k in zip(th, range(25, 101, 25)):
+        assert row == pytest.approx(r["thermo"][k], rel=1e-9, abs=1e-12)
+    g.close()
+
+
+def test_half_list_graph_mode_matches_oracle():
+    s = md_system(10, 0.8442, 1.44, seed=61)
+    g = System(s.n, s.L)
+    g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
+    g.set_half_list(True)
+    g.integrate(5)
+    g.set_graphs(True)
+    g.integrate(75)
+    p, v, _ = g.get_state()
+    g.sync()
+    assert g.info()["graph_launches"] > 0
+    r = oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.L, 80, thermo=False)
+    assert np.abs(_mic(p.cpu().numpy() - r["x"], s.L)).max() < POS_TOL
+    assert np.abs(v.cpu().numpy() - r["v"]).max() < POS_TOL
+    g.close()
+
+
+def test_half_list_batch_matches_oracle():
+    specs = [(5, 0.80, 1.0, 71), (7, 0.85, 1.2, 72), (9, 0.84, 1.44, 73), (4, 0.9, 0.8, 74)]
+    boxes = [md_system(n, rho, T, seed=sd) for n, rho, T, sd in specs]
+    g = System.batch([b.n for b in boxes], [b.L for b in boxes], dict(max_neighbors=128))
+    g.set_state(torch.from_numpy(np.concatenate([b.pos() for b in boxes])),
+                torch.from_numpy(np.concatenate([b.vel() for b in boxes])))
+    g.set_half_list(True)
+    g.integrate(60)
+    p, v, _ = g.get_state()
+    g.sync()
+    p, v = p.cpu().numpy(), v.cpu().numpy()
+    off = 0
+    for b in boxes:
+        r = oracle.run(b.x, b.y, b.z, b.vx, b.vy, b.vz, b.L, 60, thermo=False)
+        assert np.abs(_mic(p[off:off + b.n] - r["x"], b.L)).max() < POS_TOL
+        assert np.abs(v[off:off + b.n] - r["v"]).max() < POS_TOL
+        off += b.n
+    g.close()
+
+
+def test_half_list_full_size_forces():
+    """131,072 atoms (FCC 32^3), after 20 steps of the liquid: every atom's
+    force, the energy and the virial against the oracle, at the tuned
+    edge-2 schedule with half lists."""
+    s = md_system(32, 0.8442, 1.44, seed=1000)
+    r = oracle.run(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.L, 20, thermo=False)
+    pos = r["x"]
+    g = System(s.n, s.L)
+    g.set_state(torch.from_numpy(pos), torch.from_numpy(r["v"]))
+    g.set_schedule(block_edge=2)
+    g.set_half_list(True)
+    g.build_neighbors()
+    c_o, n_o, _ = oracle.build_list(pos[:, 0], pos[:, 1], pos[:, 2], s.L, RL, maxnb=128)
+    _check_forces(g, pos, s.L, c_o, n_o)
+    counts = g.neighbor_counts().cpu().numpy()
+    g.sync()
+    # about 54% of an edge-2 block's pairs stay inside it and are listed once
+    assert 0.6 < counts.sum() / c_o.sum() < 0.8
+    g.close()
+
+
+def test_half_list_rejections_and_autotune():
+    s = md_system(8, seed=81)
+    g = System(s.n, s.L)
+    g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
+    g.set_half_list(True)
+    with pytest.raises(TmdError):
+        g.set_schedule(block_parts=2)
+    with pytest.raises(TmdError):
+        g.set_schedule(lanes_per_atom=2)
+    with pytest.raises(TmdError):
+        g.adjoint_forward(20)
+    g.set_half_list(False)
+    g.set_schedule(block_parts=2)
+    with pytest.raises(TmdError):
+        g.set_half_list(True)
+    g.set_schedule(block_parts=1)
+    sched = g.autotune(repeats=2)
+    assert sched["half_list"] in (0, 1)
+    g.close()

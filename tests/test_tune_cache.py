@@ -7,7 +7,7 @@ from paper_2009_07400_amd import tune_cache
 from paper_2009_07400_amd.system import make_params
 
 SCHED = {"block_threads": 640, "lds_atoms": 3328, "block_edge": 3, "block_parts": 1, "lanes_per_atom": 1,
-         "build_threads": 512, "build_lanes": 1}
+         "build_threads": 512, "build_lanes": 1, "half_list": 0}
 
 
 def _key(**over):
