@@ -264,8 +264,11 @@ tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms,
  * half: 1 on, 0 off (the default).  Lennard-Jones only, with one workgroup
  * per block and one lane per atom (tmd_set_schedule refuses block_parts or
  * lanes_per_atom above 1 while it is on); not with the adjoint
- * (tmd_adjoint_forward returns TMD_EINVAL).  Marks the list stale.
- * TMD_EINVAL for other values or combinations.  Host only. */
+ * (tmd_adjoint_forward returns TMD_EINVAL).  A change splits each
+ * workgroup's LDS anew between the neighborhood copy and the reaction sums,
+ * which resets threads and lds_atoms to the block edge's defaults, and
+ * marks the list stale.  TMD_EINVAL for other values or combinations.  Host
+ * only. */
 tmd_status tmd_set_half_list(tmd_system *sys, int32_t half);
 
 /* Pick the schedule (block edge 2 or 3, full or half lists - the latter

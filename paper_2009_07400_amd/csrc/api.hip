@@ -320,14 +320,20 @@ bool layout_dims(Box *boxes, int32_t nbox, int E, Dims &d) {
     const int need = int(1.15 * worst) + 32;
     // the Spring-Dashpot force kernel stages velocities too: 48 bytes a slot
     const int slot = d.model == 1 ? 48 : 24;
+    // half lists add the reaction sums over the own cells' slot span, sized
+    // like the staging area for the same share of the neighborhood's cells
+    const double span_cells = E == 2 ? 22.0 / 64.0 : 63.0 / 125.0;
+    d.rcap = d.half ? round_up(int(1.15 * worst * span_cells) + 32, 64) : 0;
     d.cap = std::min(kMaxCap, round_up(int(1.3 * worst) + 64, 64));
     for (int wg = 8; wg >= 1; --wg) {
-        const int c = ((kLdsPerCu / wg - kStaticLds) / slot - 2 - kHoodPad) / 64 * 64;  // + slots past the capacity
+        // + slots past the capacity
+        const int c = ((kLdsPerCu / wg - kStaticLds) / slot - 2 - kHoodPad - d.rcap) / 64 * 64;
         if (c >= need) {
             d.cap = std::min(kMaxCap, c);
             break;
         }
     }
+    d.rcap = std::min(d.rcap, d.cap);
     if (d.parts < 1)
         d.parts = 1;
     if (d.lpa < 1)
@@ -538,6 +544,7 @@ bool fit_cap(Dims &d, int max_lds) {
         return false;
     const int fit = int((size_t(max_lds) - size_t(kStaticLds)) / 48) - 2 - kHoodPad;
     d.cap = std::max(64, fit / 64 * 64);
+    d.rcap = std::min(d.rcap, d.cap);  // the reaction sums then fit beside the copy too
     return true;
 }
 
@@ -1028,6 +1035,8 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
         s->d.bthreads = build_threads;
     if (lds_atoms > 0 && lds_atoms != s->d.cap) {
         s->d.cap = lds_atoms;
+        if (s->d.half)
+            s->d.rcap = std::min(s->d.rcap, lds_atoms);
         s->prepared = false;  // LDS attribute of the block kernels must follow
         // the list encodes LDS slots only for neighborhoods that fit
         s->list_valid = s->force_valid = false;
@@ -1043,6 +1052,9 @@ tmd_status tmd_set_half_list(tmd_system *s, int32_t half) {
         return TMD_EINVAL;
     if (half != s->d.half) {
         s->d.half = half;
+        // the LDS split between staging and reaction sums follows; threads
+        // and capacity return to the edge's defaults
+        layout_blocks(s, s->d.edge);
         s->list_valid = s->force_valid = false;  // another list, forces summed in another order
         s->gen++;
     }
@@ -1118,8 +1130,8 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     const int32_t hmax = s->d.model == TMD_MODEL_LJ ? 1 : 0;
     for (int32_t EH = 0; EH < (kMaxEdge - 1) * (hmax + 1) && e == hipSuccess; ++EH) {
         const int32_t E = 2 + EH / (hmax + 1), H = EH % (hmax + 1);
-        layout_blocks(s, E);
         s->d.half = H;
+        layout_blocks(s, E);
         s->d.parts = 1;
         s->d.lpa = 1;
         s->list_valid = s->force_valid = false;
@@ -1186,8 +1198,8 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
         return st;
     if (e != hipSuccess)
         return hip_fail(s, e, "autotune");
-    layout_blocks(s, best_edge);
     s->d.half = best_h;
+    layout_blocks(s, best_edge);
     s->d.parts = best_p;
     s->d.lpa = best_l;
     s->d.threads = best_t;

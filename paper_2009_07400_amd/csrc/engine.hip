@@ -313,7 +313,7 @@ __device__ __forceinline__ bool block_half(const Dims &d, const Box &B, int lb, 
     const int uhi = (o.e[2] * o.n[1] + o.e[1]) * o.n[0] + o.e[0];
     s_lo = h.off[ulo];
     span = h.off[uhi + 1] - s_lo;
-    return span <= react_cap(d.cap);
+    return span <= d.rcap;
 }
 
 // LDS slot of the block's own atom i (global index) in a half-list block:
@@ -1381,9 +1381,14 @@ __device__ __forceinline__ void fetch2(const POS &pos, int j0, int j1, Duo &q) {
 // -u6.  A NaN sentinel entry fails both tests and adds nothing.  IMG: the
 // partner positions come from a neighborhood copy moved to its images near
 // the block (HoodImage), so the difference needs no minimum-image test.
-template <bool THERMO, bool IMG>
+// HALF: the entries come from a half list (word: the two 16-bit entries,
+// bit 15 marking a pair inside the block that the partner's list does not
+// hold): such a pair also adds the reaction -f d to the partner's sum in R
+// (LDS, index slot - s_lo), and its energy and virial count twice.
+template <bool THERMO, bool IMG, bool HALF = false>
 __device__ __forceinline__ void eval2(const Duo &q, double xi, double yi, double zi, const Box &B, double mf6,
-                                      double mu6, double &ax, double &ay, double &az, double &u, double &w) {
+                                      double mu6, double &ax, double &ay, double &az, double &u, double &w,
+                                      unsigned word = 0u, lds_double *R = nullptr, int s_lo = 0) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         double dx, dy, dz;
@@ -1397,7 +1402,23 @@ __device__ __forceinline__ void eval2(const Duo &q, double xi, double yi, double
             ax = fma(f, dx, ax);
             ay = fma(f, dy, ay);
             az = fma(f, dz, az);
-            if (THERMO) {
+            if (HALF) {
+                const unsigned v = m ? word >> 16 : word & 0xFFFFu;
+                const bool pair = (v & 0x8000u) != 0u;
+                if (pair) {
+                    lds_double *r = R + 3 * (int(v & 0x7FFFu) - s_lo);
+                    __hip_atomic_fetch_add((double *)r, -f * dx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add((double *)(r + 1), -f * dy, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add((double *)(r + 2), -f * dz, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                if (THERMO) {
+                    const double k = pair ? 2.0 : 1.0;
+                    u = fma(k * q3, fma(B.u12, q3, mu6), u);
+                    w = fma(k * s, f, w);
+                }
+            } else if (THERMO) {
                 u = fma(q3, fma(B.u12, q3, mu6), u);
                 w = fma(s, f, w);
             }
@@ -1474,38 +1495,52 @@ __device__ __forceinline__ void fetch2w(int word, Duo &q) {
 // load them before the count is known.  The only exit
 // is at the end of the body: a loop with several exits loses the exact wait
 // counts at its head.
-template <bool THERMO, bool IMG>
+template <bool THERMO, bool IMG, bool HALF = false>
 __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int p, int L, int c,
                                            double xi, double yi, double zi, const Box &B, double mf6, double mu6,
-                                           double &ax, double &ay, double &az, double &u, double &w) {
+                                           double &ax, double &ay, double &az, double &u, double &w,
+                                           lds_double *R = nullptr, int s_lo = 0) {
     const int nch = (c + 7) >> 3;
     // this lane's k-th chunk is chunk p + L k of the atom's list
     auto ld = [&](int k) {
         const int q = p + L * k;
         return __builtin_nontemporal_load(chunks + (q < nch ? q : nch) * 64);
     };
-    Duo P, Q;
-    fetch2w(i0[0], P);
+    // a half list's words keep their marks for the evaluation; the slots
+    // drop them for the address
+    Duo P_, Q_;
+    unsigned wP = 0u, wQ = 0u;
+    auto fetchP = [&](int word) {
+        wP = unsigned(word);
+        fetch2w(HALF ? int(unsigned(word) & 0x7FFF7FFFu) : word, P_);
+    };
+    auto fetchQ = [&](int word) {
+        wQ = unsigned(word);
+        fetch2w(HALF ? int(unsigned(word) & 0x7FFF7FFFu) : word, Q_);
+    };
+    auto evalP = [&]() { eval2<THERMO, IMG, HALF>(P_, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w, wP, R, s_lo); };
+    auto evalQ = [&]() { eval2<THERMO, IMG, HALF>(Q_, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w, wQ, R, s_lo); };
+    fetchP(i0[0]);
     int k = 0;
     for (;; k += 2) {
-        fetch2w(i0[1], Q);
-        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(i0[2], P);
-        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(i0[3], Q);
-        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(i1[0], P);
+        fetchQ(i0[1]);
+        evalP();
+        fetchP(i0[2]);
+        evalQ();
+        fetchQ(i0[3]);
+        evalP();
+        fetchP(i1[0]);
         i0 = ld(k + 2);
-        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(i1[1], Q);
-        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(i1[2], P);
-        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(i1[3], Q);
-        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(i0[0], P);
+        evalQ();
+        fetchQ(i1[1]);
+        evalP();
+        fetchP(i1[2]);
+        evalQ();
+        fetchQ(i1[3]);
+        evalP();
+        fetchP(i0[0]);
         i1 = ld(k + 3);
-        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        evalQ();
         if (!__any(p + L * (k + 3) < nch))
             break;
     }
@@ -1513,13 +1548,13 @@ __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i
     // its first two positions in P) runs here if any lane still has it, so
     // an odd chunk count does not cost a chunk of sentinels
     if (__any(p + L * (k + 2) < nch)) {
-        fetch2w(i0[1], Q);
-        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(i0[2], P);
-        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        fetch2w(i0[3], Q);
-        eval2<THERMO, IMG>(P, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        eval2<THERMO, IMG>(Q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        fetchQ(i0[1]);
+        evalP();
+        fetchP(i0[2]);
+        evalQ();
+        fetchQ(i0[3]);
+        evalP();
+        evalQ();
     }
     __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) expcnt(7) lgkmcnt(0)
 }
@@ -1528,12 +1563,54 @@ __device__ __forceinline__ const v4i *list_chunks(const int32_t *nbr, int i, int
     return reinterpret_cast<const v4i *>(nbr) + (int64_t(i >> 6) * nchunk) * 64 + (i & 63);
 }
 
+// The end of an atom's step in the force kernels, given its force a: MODE
+// 0 stores F, 1 stores F and kicks v += h F, 2 kicks twice and drifts into
+// the other position buffer (k_force's epilogue).
+template <int MODE, bool THERMO>
+__device__ __forceinline__ void atom_epilogue(int i, double xi, double yi, double zi, double ax, double ay, double az,
+                                              const Box &B, double *vx, double *vy, double *vz, double *fx,
+                                              double *fy, double *fz, double *xo, double *yo, double *zo, double &ke,
+                                              int32_t *err) {
+    if (MODE == 0 || MODE == 1) {
+        fx[i] = ax;
+        fy[i] = ay;
+        fz[i] = az;
+        if (!(isfinite(ax) && isfinite(ay) && isfinite(az)))
+            atomicOr(err, kErrNonFinite);
+    }
+    if (MODE >= 1) {
+        double a = vx[i] + B.h * ax, bb = vy[i] + B.h * ay, c = vz[i] + B.h * az;
+        if (THERMO)
+            ke += a * a + bb * bb + c * c;
+        if (MODE == 2) {
+            a = a + B.h * ax;
+            bb = bb + B.h * ay;
+            c = c + B.h * az;
+            const double nx = xi + B.dt * a, ny = yi + B.dt * bb, nz = zi + B.dt * c;
+            xo[i] = nx;
+            yo[i] = ny;
+            zo[i] = nz;
+            if (!(isfinite(nx) && isfinite(ny) && isfinite(nz)))
+                atomicOr(err, kErrNonFinite);
+        }
+        vx[i] = a;
+        vy[i] = bb;
+        vz[i] = c;
+    }
+}
+
 // One workgroup per block, one lane per atom.  MODE 0: store F.  MODE 1:
 // store F and kick v += h F.  MODE 2: kick twice (closing this step and
 // opening the next) and drift into the other position buffer.  With THERMO
 // each block writes its partial sums of the pair energy, of s f(s) and of
 // |v|^2 at the full step - no atomics anywhere.
-template <int MODE, bool THERMO, int L>
+// HALF (L = 1, one workgroup per block): the lists are half lists inside
+// half-list blocks (block_half()); there each atom's own sum and its
+// partners' reactions meet in LDS sums over the own cells' slot span, and
+// after a barrier every atom takes its total and finishes the step.  Those
+// sums are LDS atomics, so their order - and the last bits of the forces -
+// may vary from run to run.  Other blocks finish each atom directly.
+template <int MODE, bool THERMO, int L, bool HALF = false>
 __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__restrict__ boxes,
                                                        const int32_t *__restrict__ blk_box,
                                                        const double *__restrict__ x, const double *__restrict__ y,
@@ -1576,6 +1653,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     lds_double *const S = (lds_double *)lds;
     const GlobalPos gpos{x, y, z};
     const HoodImage im = hood_image(B, b - B.block_off, fits);
+    // half lists: the reaction sums follow the table and reduction scratch
+    lds_double *R = (lds_double *)((lds_char *)lds + tail + kForceLdsTail);
+    int s_lo = 0, span = 0;
+    const bool half = HALF && block_half(d, B, b - B.block_off, h, fits, s_lo, span);
+    if (HALF && half)
+        for (int k = threadIdx.x; k < 3 * span; k += blockDim.x)
+            R[k] = 0.0;  // the staging ends with a barrier
     // The operands of a lane's next atom (position, list length, velocity)
     // are loaded one pass ahead - those of the first pass before the staging
     // barrier, so their latency overlaps the staging.  Past the block's last
@@ -1622,9 +1706,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
         double ax = 0.0, ay = 0.0, az = 0.0;
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
         if (im.on)
-            pair_sum16<THERMO, true>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+            pair_sum16<THERMO, true, HALF>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w, R,
+                                           s_lo);
         else if (fits)
-            pair_sum16<THERMO, false>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+            pair_sum16<THERMO, false, HALF>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w, R,
+                                            s_lo);
         else
             pair_sum<THERMO>(chunks, p, L, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         // combine the L partial sums of the group (a butterfly: addition
@@ -1636,6 +1722,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
             az += __shfl_xor(az, o, 64);
         }
         const bool own = p == 0;  // the group's first lane writes the atom
+        if (HALF && half) {
+            lds_double *r = R + 3 * (own_slot(B, b - B.block_off, h, i) - s_lo);
+            __hip_atomic_fetch_add((double *)r, ax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add((double *)(r + 1), ay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add((double *)(r + 2), az, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            load_atom(i + T);
+            continue;
+        }
         if ((MODE == 0 || MODE == 1) && own) {
             fx[i] = ax;
             fy[i] = ay;
@@ -1666,181 +1760,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
         }
         load_atom(i + T);
     }
-    if (THERMO) {
-        block_sum3(u, w, ke, red);
-        if (threadIdx.x == 0) {
-            const int q = b * d.parts + part;
-            partials[q * kPartialStride + 0] = u;
-            partials[q * kPartialStride + 1] = w;
-            partials[q * kPartialStride + 2] = ke;
-        }
-    }
-}
-
-// One entry of a half list (16-bit LDS slot, bit 15: a pair inside the
-// block listed once): the pair term as in eval2, and for a marked pair the
-// partner's reaction -f d added to its sum in R (LDS, slot - s_lo).  The
-// energy and virial of a marked pair count twice, standing for the entry
-// its partner does not hold.
-template <bool THERMO, bool IMG>
-__device__ __forceinline__ void eval_half(unsigned v, const lds_double *S, lds_double *R, int s_lo, double xi,
-                                          double yi, double zi, const Box &B, double mf6, double mu6, double &ax,
-                                          double &ay, double &az, double &u, double &w) {
-    const int slot = int(v & 0x7FFFu);
-    const lds_double *a = lds_slot(const_cast<lds_double *>(S), slot);
-    double dx, dy, dz;
-    const double s = IMG ? pair_delta_img(xi, yi, zi, a[0], a[1], a[2], dx, dy, dz)
-                         : pair_delta_fma(xi, yi, zi, a[0], a[1], a[2], B.L, B.invL, dx, dy, dz);
-    if (s < B.rc2) {
-        const double sr2 = recip(s);
-        const double q3 = sr2 * sr2 * sr2;
-        const double f = (sr2 * q3) * fma(B.f12, q3, mf6);
-        ax = fma(f, dx, ax);
-        ay = fma(f, dy, ay);
-        az = fma(f, dz, az);
-        const bool pair = (v & 0x8000u) != 0u;
-        if (pair) {
-            lds_double *r = R + 3 * (slot - s_lo);
-            __hip_atomic_fetch_add((double *)r, -f * dx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add((double *)(r + 1), -f * dy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add((double *)(r + 2), -f * dz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        if (THERMO) {
-            const double k = pair ? 2.0 : 1.0;
-            u = fma(k * q3, fma(B.u12, q3, mu6), u);
-            w = fma(k * s, f, w);
-        }
-    }
-}
-
-// Sum over one atom's 16-bit half list (c entries, eight per chunk, the
-// chunk after the last all sentinels), the next chunk loaded while this one
-// is evaluated.
-template <bool THERMO, bool IMG>
-__device__ __forceinline__ void pair_sum_half(const v4i *__restrict__ chunks, int c, const lds_double *S,
-                                              lds_double *R, int s_lo, double xi, double yi, double zi, const Box &B,
-                                              double mf6, double mu6, double &ax, double &ay, double &az, double &u,
-                                              double &w) {
-    const int nch = (c + 7) >> 3;
-    v4i cur = __builtin_nontemporal_load(chunks);
-    for (int k = 0; k < nch; ++k) {
-        const v4i nxt = __builtin_nontemporal_load(chunks + (k + 1) * 64);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            eval_half<THERMO, IMG>(unsigned(cur[q]) & 0xFFFFu, S, R, s_lo, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-            eval_half<THERMO, IMG>(unsigned(cur[q]) >> 16, S, R, s_lo, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        }
-        cur = nxt;
-    }
-}
-
-// The end of an atom's step in the force kernels, given its force a: MODE
-// 0 stores F, 1 stores F and kicks v += h F, 2 kicks twice and drifts into
-// the other position buffer (k_force's epilogue).
-template <int MODE, bool THERMO>
-__device__ __forceinline__ void atom_epilogue(int i, double xi, double yi, double zi, double ax, double ay, double az,
-                                              const Box &B, double *vx, double *vy, double *vz, double *fx,
-                                              double *fy, double *fz, double *xo, double *yo, double *zo, double &ke,
-                                              int32_t *err) {
-    if (MODE == 0 || MODE == 1) {
-        fx[i] = ax;
-        fy[i] = ay;
-        fz[i] = az;
-        if (!(isfinite(ax) && isfinite(ay) && isfinite(az)))
-            atomicOr(err, kErrNonFinite);
-    }
-    if (MODE >= 1) {
-        double a = vx[i] + B.h * ax, bb = vy[i] + B.h * ay, c = vz[i] + B.h * az;
-        if (THERMO)
-            ke += a * a + bb * bb + c * c;
-        if (MODE == 2) {
-            a = a + B.h * ax;
-            bb = bb + B.h * ay;
-            c = c + B.h * az;
-            const double nx = xi + B.dt * a, ny = yi + B.dt * bb, nz = zi + B.dt * c;
-            xo[i] = nx;
-            yo[i] = ny;
-            zo[i] = nz;
-            if (!(isfinite(nx) && isfinite(ny) && isfinite(nz)))
-                atomicOr(err, kErrNonFinite);
-        }
-        vx[i] = a;
-        vy[i] = bb;
-        vz[i] = c;
-    }
-}
-
-// k_force for half lists, one lane per atom, one workgroup per block.  In a
-// half-list block (block_half()) each atom's own sum and the reactions of
-// its partners meet in LDS sums over the own cells' slot span; after a
-// barrier every atom takes its total and finishes the step.  The sums are
-// LDS atomics, so their order - and the last bits of the forces - may vary
-// from run to run.  Other blocks (full lists) finish each atom directly.
-template <int MODE, bool THERMO>
-__global__ __launch_bounds__(kMaxThreads) void k_force_half(
-    Dims d, const Box *__restrict__ boxes, const int32_t *__restrict__ blk_box, const double *__restrict__ x,
-    const double *__restrict__ y, const double *__restrict__ z, const int32_t *__restrict__ hood_tab,
-    const int32_t *__restrict__ cnt, const int32_t *__restrict__ nbr, double *__restrict__ vx,
-    double *__restrict__ vy, double *__restrict__ vz, double *__restrict__ fx, double *__restrict__ fy,
-    double *__restrict__ fz, double *__restrict__ xo, double *__restrict__ yo, double *__restrict__ zo,
-    double *__restrict__ partials, int32_t *err) {
-    // the neighborhood copy at LDS address 0, then the table and reduction
-    // scratch (as in k_force), then the reaction sums
-    extern __shared__ double lds[];
-    const int tail = (d.cap + 2 + kHoodPad) * 24;
-    Hood &h = *reinterpret_cast<Hood *>(reinterpret_cast<char *>(lds) + tail);
-    double(*red)[kMaxThreads / 64] =
-        reinterpret_cast<double(*)[kMaxThreads / 64]>(reinterpret_cast<char *>(lds) + tail + kHoodBytes8);
-    lds_double *R = (lds_double *)((lds_char *)lds + tail + kForceLdsTail);
-    int b, part;
-    if (!block_part(d, b, part))
-        return;
-    HoodWords hw;
-    hood_fetch(hood_tab, b, hw);
-    const Box B = block_box(d, boxes, blk_box, b);
-    const double mf6 = -B.f6, mu6 = -B.u6;
-    hood_commit(hw, h);
-    const int total = h.off[h.ncell];
-    const bool fits = total <= d.cap;
-    lds_double *const S = (lds_double *)lds;
-    const GlobalPos gpos{x, y, z};
-    const int lb = b - B.block_off;
-    const HoodImage im = hood_image(B, lb, fits);
-    int s_lo, span;
-    const bool half = block_half(d, B, lb, h, fits, s_lo, span);
-    if (half)
-        for (int k = threadIdx.x; k < 3 * span; k += blockDim.x)
-            R[k] = 0.0;
-    if (fits)
-        hood_stage(h, total, d.cap, x, y, z, S, im);  // ends with a barrier
-    int lo, hi;
-    h.share(part, d.parts, lo, hi);
-    double u = 0.0, w = 0.0, ke = 0.0;
-    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const double xi = x[i], yi = y[i], zi = z[i];
-        const int ci = cnt[i];
-        double ax = 0.0, ay = 0.0, az = 0.0;
-        const v4i *chunks = list_chunks(nbr, i, d.nchunk);
-        if (im.on)
-            pair_sum_half<THERMO, true>(chunks, ci, S, R, s_lo, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        else if (fits)
-            pair_sum_half<THERMO, false>(chunks, ci, S, R, s_lo, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        else
-            pair_sum<THERMO>(chunks, 0, 1, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
-        if (half) {
-            lds_double *r = R + 3 * (own_slot(B, lb, h, i) - s_lo);
-            __hip_atomic_fetch_add((double *)r, ax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add((double *)(r + 1), ay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add((double *)(r + 2), az, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
-            atom_epilogue<MODE, THERMO>(i, xi, yi, zi, ax, ay, az, B, vx, vy, vz, fx, fy, fz, xo, yo, zo, ke, err);
-        }
-    }
-    if (half) {
+    if (HALF && half) {
         __syncthreads();
-        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const lds_double *r = R + 3 * (own_slot(B, lb, h, i) - s_lo);
-            atom_epilogue<MODE, THERMO>(i, x[i], y[i], z[i], r[0], r[1], r[2], B, vx, vy, vz, fx, fy, fz, xo, yo, zo,
+        for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+            const lds_double *r = R + 3 * (own_slot(B, b - B.block_off, h, k) - s_lo);
+            atom_epilogue<MODE, THERMO>(k, x[k], y[k], z[k], r[0], r[1], r[2], B, vx, vy, vz, fx, fy, fz, xo, yo, zo,
                                         ke, err);
         }
     }
@@ -2463,12 +2387,12 @@ hipError_t prepare_kernels(int dyn_bytes) {
         reinterpret_cast<const void *>(&k_force_sd<1, true>),
         reinterpret_cast<const void *>(&k_force_sd<2, false>),
         reinterpret_cast<const void *>(&k_force_sd<2, true>),
-        reinterpret_cast<const void *>(&k_force_half<0, false>),
-        reinterpret_cast<const void *>(&k_force_half<0, true>),
-        reinterpret_cast<const void *>(&k_force_half<1, false>),
-        reinterpret_cast<const void *>(&k_force_half<1, true>),
-        reinterpret_cast<const void *>(&k_force_half<2, false>),
-        reinterpret_cast<const void *>(&k_force_half<2, true>),
+        reinterpret_cast<const void *>(&k_force<0, false, 1, true>),
+        reinterpret_cast<const void *>(&k_force<0, true, 1, true>),
+        reinterpret_cast<const void *>(&k_force<1, false, 1, true>),
+        reinterpret_cast<const void *>(&k_force<1, true, 1, true>),
+        reinterpret_cast<const void *>(&k_force<2, false, 1, true>),
+        reinterpret_cast<const void *>(&k_force<2, true, 1, true>),
         reinterpret_cast<const void *>(&k_hvp<1>),
         reinterpret_cast<const void *>(&k_hvp<2>),
         reinterpret_cast<const void *>(&k_hvp<4>),
@@ -2631,7 +2555,7 @@ static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &o
 
 template <int MODE, bool THERMO>
 static void force_half_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
-    k_force_half<MODE, THERMO><<<block_grid(d.nblk * d.parts), d.threads, force_half_lds_bytes(d.cap), s>>>(
+    k_force<MODE, THERMO, 1, true><<<block_grid(d.nblk * d.parts), d.threads, force_half_lds_bytes(d.cap, d.rcap), s>>>(
         d, b.boxes, b.blk_box, in.x, in.y, in.z, b.hood_tab, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
         b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
 }

@@ -80,6 +80,7 @@ struct Dims {
     int32_t blanes;   // lanes per atom in the list build (1 or 2)
     int32_t model;    // force model of every box: 0 Lennard-Jones, 1 Spring-Dashpot
     int32_t half;     // 1: half lists inside blocks (Newton's third law in the force kernel's LDS)
+    int32_t rcap;     // LDS slots of a block's reaction sums with half lists (0 without)
 };
 
 // Neighbor list layout: neighbor-major within tiles of 64 atoms (one
@@ -156,11 +157,12 @@ constexpr int kForceLdsTail = 1536;
 inline size_t force_lds_bytes(int cap) { return hood_lds_bytes(cap) + kForceLdsTail; }
 
 // Half lists: a block's reaction sums cover the LDS slots from its first
-// own cell's to its last own cell's (about a third of the neighborhood at
-// edge 2, a half at edge 3), at most 5/8 of the staging capacity; blocks
-// whose span is larger keep full lists.
-__host__ __device__ inline int react_cap(int cap) { return cap * 5 / 8 / 64 * 64; }
-inline size_t force_half_lds_bytes(int cap) { return force_lds_bytes(cap) + size_t(react_cap(cap)) * 3 * sizeof(double); }
+// own cell's to its last own cell's (22 of the 64 neighborhood cells at edge
+// 2, 63 of 125 at edge 3), rcap slots of 24 bytes after the force kernel's
+// tail; blocks whose span is larger keep full lists.
+inline size_t force_half_lds_bytes(int cap, int rcap) {
+    return force_lds_bytes(cap) + size_t(rcap) * 3 * sizeof(double);
+}
 
 // Upper bound of the static LDS any block kernel declares (neighborhood
 // table, reduction scratch); engine.hip checks its kernels against it.
