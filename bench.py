@@ -336,10 +336,11 @@ def run_adjoint(steps: int = 200, replicas: int = 64):
     v0 = torch.from_numpy(np.concatenate([r.vel() for r in reps]))
     g = System.batch([r.n for r in reps], [r.L for r in reps], dict(max_neighbors=128))
     lam = torch.randn(total, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(5))
-    # one schedule for both runs, tuned a rebuild interval into the run
+    # one schedule for both runs (of those the adjoint runs with: full lists,
+    # SoA positions), tuned a rebuild interval into the run
     g.set_state(x0, v0)
     g.integrate(20)
-    g.autotune(repeats=3)
+    g.autotune(repeats=3, for_adjoint=True)
     sched = _schedule(g)
     for _ in range(2):  # second pass is the timed one
         g.set_state(x0, v0)

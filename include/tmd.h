@@ -107,6 +107,7 @@ typedef struct {
     int32_t graph_captures;  /* rebuild intervals captured as graphs (tmd_set_graphs) */
     int64_t graph_launches;  /* rebuild intervals run as graph launches */
     int32_t half_list;       /* 1: half lists inside blocks (tmd_set_half_list) */
+    int32_t layout;          /* position layout (TMD_LAYOUT_*, tmd_set_layout) */
 } tmd_info;
 
 /* Kernel classes reported by tmd_get_timing(). */
@@ -123,7 +124,7 @@ enum {
 
 /* Create a system of n_atoms atoms in a periodic cube of side box_length.
  * Host only; touches no GPU.  Returns TMD_EINVAL for a NULL pointer, n_atoms
- * <= 0 or > 2^31-1, a non-finite or non-positive epsilon, sigma, mass, cutoff,
+ * <= 0 or > 7e8, a non-finite or non-positive epsilon, sigma, mass, cutoff,
  * dt, box_length, a negative skin, rebuild_every < 1 or max_neighbors outside
  * [1, 4096], an unknown model, and for the Spring-Dashpot model a negative or
  * non-finite stiffness or damping or cutoff < sigma; TMD_EBOX when cutoff +
@@ -136,8 +137,9 @@ tmd_status tmd_create(const tmd_params *params, int64_t n_atoms, double box_leng
  * Box k has n_atoms[k] atoms, side box_lengths[k] and parameters params[k];
  * its atoms occupy the slots [sum_{m<k} n_atoms[m], ...) of every per-atom
  * array the caller exchanges (concatenated original order).  All boxes must
- * share rebuild_every and max_neighbors (TMD_EINVAL otherwise); every other
- * check of tmd_create() applies per box.  Outputs that are per system in
+ * share rebuild_every and max_neighbors (TMD_EINVAL otherwise) and hold at
+ * most 7e8 atoms together; every other check of tmd_create() applies per
+ * box.  Outputs that are per system in
  * tmd_create() become per box (see tmd_compute_forces, tmd_integrate).
  * With n_boxes == 1 this is tmd_create(). */
 tmd_status tmd_create_batch(int32_t n_boxes, const int64_t *n_atoms, const double *box_lengths,
@@ -248,6 +250,24 @@ tmd_status tmd_set_schedule(tmd_system *sys, int32_t threads, int32_t lds_atoms,
                             int32_t block_parts, int32_t lanes_per_atom, int32_t build_threads,
                             int32_t build_lanes);
 
+/* Memory layouts of the device position buffers (the particle data
+ * layouts of Sec. 4.2, which the paper specialises its kernels for). */
+enum {
+    TMD_LAYOUT_SOA = 0,   /* column-major: every atom's x, then every y, then every z */
+    TMD_LAYOUT_AOS = 1,   /* row-major: x, y, z of each atom side by side */
+    TMD_LAYOUT_AOSOA = 2  /* clustered: per 64 atoms (one wavefront) their 64 x, 64 y, 64 z */
+};
+
+/* Store the positions in `layout` (TMD_LAYOUT_*): binning, list build, force
+ * and drift kernels then read and write them that way; the state seen
+ * through tmd_set_state()/tmd_get_state() (original order, three arrays)
+ * and every result are unchanged.  The current positions, if a state is
+ * set, are converted on `stream`.  TMD_EINVAL for another value, and for a
+ * layout other than TMD_LAYOUT_SOA with the Spring-Dashpot model; the
+ * adjoint (tmd_adjoint_forward) needs TMD_LAYOUT_SOA (TMD_EINVAL
+ * otherwise).  The list stays valid. */
+tmd_status tmd_set_layout(tmd_system *sys, int32_t layout, tmd_stream stream);
+
 /* Half neighbor lists with Newton's third law (Sec. 3.2: each pair stored
  * once, its force applied to both atoms; the half_nb variant of Sec. 4.2),
  * applied inside each block of cells: a pair of two atoms of one block is
@@ -288,8 +308,17 @@ tmd_status tmd_set_half_list(tmd_system *sys, int32_t half);
  * the same length, favours fewer lanes per atom than a liquid does.  Positions and velocities are not changed, but the list is
  * rebuilt at the current positions, as by tmd_build_neighbors(); call it
  * right after tmd_set_state() or at a rebuild step to keep the fixed
- * rebuild schedule. */
-tmd_status tmd_autotune(tmd_system *sys, int32_t repeats, tmd_stream stream);
+ * rebuild schedule.  Last, at the chosen schedule, the position layout
+ * (tmd_set_layout) whose list build plus step kernel time is shortest
+ * (Lennard-Jones).  flags: 0, or TMD_TUNE_ADJOINT to keep to full lists
+ * and TMD_LAYOUT_SOA, which tmd_adjoint_forward() needs; TMD_EINVAL for
+ * other bits. */
+tmd_status tmd_autotune(tmd_system *sys, int32_t repeats, int32_t flags, tmd_stream stream);
+
+/* Flags of tmd_autotune(). */
+enum {
+    TMD_TUNE_ADJOINT = 1 /* only schedules the adjoint runs with: full lists, TMD_LAYOUT_SOA */
+};
 
 /* Replace epsilon and sigma of every box (host arrays of n_boxes values, each
  * finite and positive); the copy to the device is enqueued on `stream`.  The

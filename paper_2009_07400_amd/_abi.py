@@ -67,6 +67,7 @@ class TmdInfo(C.Structure):
         ("graph_captures", C.c_int32),
         ("graph_launches", C.c_int64),
         ("half_list", C.c_int32),
+        ("layout", C.c_int32),
     ]
 
 
@@ -106,11 +107,12 @@ def load_library():
         "tmd_get_info": (_S, [_P, C.POINTER(TmdInfo)]),
         "tmd_set_schedule": (_S, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "tmd_set_half_list": (_S, [_P, C.c_int32]),
+        "tmd_set_layout": (_S, [_P, C.c_int32, _P]),
         "tmd_set_lj_params": (_S, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]),
         "tmd_adjoint_workspace_size": (_S, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
         "tmd_adjoint_forward": (_S, [_P, C.c_int32, _P, C.c_size_t, _P]),
         "tmd_adjoint_backward": (_S, [_P, _P, C.c_size_t, _P, _P, _P, _P, _P, _P, _P]),
-        "tmd_autotune": (_S, [_P, C.c_int32, _P]),
+        "tmd_autotune": (_S, [_P, C.c_int32, C.c_int32, _P]),
         "tmd_set_timing": (_S, [_P, C.c_int32]),
         "tmd_set_graphs": (_S, [_P, C.c_int32]),
         "tmd_get_timing": (_S, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -238,6 +240,13 @@ def tmd_set_schedule(handle, threads: int, lds_atoms: int, block_edge: int = 0, 
            handle)
 
 
+TMD_LAYOUT_SOA, TMD_LAYOUT_AOS, TMD_LAYOUT_AOSOA = 0, 1, 2
+
+
+def tmd_set_layout(handle, layout: int, stream: int) -> None:
+    _check(load_library().tmd_set_layout(handle, layout, stream), handle)
+
+
 def tmd_set_half_list(handle, half: int) -> None:
     _check(load_library().tmd_set_half_list(handle, half), handle)
 
@@ -266,8 +275,11 @@ def tmd_adjoint_backward(handle, ws_ptr: int, nbytes: int, lam_x, lam_v, grad_x0
            handle)
 
 
-def tmd_autotune(handle, repeats: int, stream: int) -> None:
-    _check(load_library().tmd_autotune(handle, repeats, stream), handle)
+TMD_TUNE_ADJOINT = 1
+
+
+def tmd_autotune(handle, repeats: int, stream: int, flags: int = 0) -> None:
+    _check(load_library().tmd_autotune(handle, repeats, flags, stream), handle)
 
 
 def tmd_set_timing(handle, enable: bool) -> None:

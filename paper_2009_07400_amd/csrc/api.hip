@@ -76,6 +76,9 @@ struct tmd_system {
 namespace {
 
 constexpr size_t kAlign = 256;
+// Atoms of a system, at most: the position layouts address a buffer of 3 ntp
+// doubles with 32-bit offsets.
+constexpr int64_t kMaxAtoms = 700000000;
 constexpr int kMaxCap = 4096;       // atoms staged per block neighborhood (96 KB of LDS at most)
 constexpr int kLdsPerCu = 163840;   // gfx950: 160 KB of LDS per compute unit
 constexpr int kStaticLds = kBlockStaticLds;  // static LDS of a block kernel (neighborhood tables, reductions)
@@ -373,7 +376,7 @@ int default_edge(const Box *boxes, int32_t nbox) {
 // Check one box's parameters (the argument rules of tmd_create) and fill
 // its descriptor; its atoms start at slot atom_off of the concatenated arrays.
 tmd_status make_box(const tmd_params &p, int64_t n, double L, int64_t atom_off, Box &B) {
-    if (n <= 0 || n > INT32_MAX)
+    if (n <= 0 || n > kMaxAtoms)
         return TMD_EINVAL;
     if (!positive(p.epsilon) || !positive(p.sigma) || !positive(p.mass) || !positive(p.cutoff) ||
         !positive(p.dt) || !positive(L) || !isfinite(p.skin) || p.skin < 0.0)
@@ -438,7 +441,7 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
         if (st != TMD_OK)
             return st;
         total += n_atoms[k];
-        if (total > INT32_MAX - 256)
+        if (total > kMaxAtoms)
             return TMD_EINVAL;
     }
     tmd_system *s = new (std::nothrow) tmd_system();
@@ -997,6 +1000,7 @@ tmd_status tmd_get_info(const tmd_system *s, tmd_info *info) {
     info->graph_captures = s->graph_captures;
     info->graph_launches = s->graph_launches;
     info->half_list = s->d.half;
+    info->layout = s->d.layout;
     return TMD_OK;
 }
 
@@ -1043,6 +1047,32 @@ tmd_status tmd_set_schedule(tmd_system *s, int32_t threads, int32_t lds_atoms, i
         s->gen++;
     }
     return TMD_OK;
+}
+
+static_assert(TMD_LAYOUT_SOA == kLayoutSoA && TMD_LAYOUT_AOS == kLayoutAoS && TMD_LAYOUT_AOSOA == kLayoutAoSoA,
+              "public and internal layout codes agree");
+
+// Convert the current positions to `layout` (the other position half takes
+// them, and the sentinel in both halves follows).
+static tmd_status relayout(tmd_system *s, int32_t layout, hipStream_t hs) {
+    if (layout == s->d.layout)
+        return TMD_OK;
+    if (s->have_state) {
+        const hipError_t e = launch_relayout(s->d, s->b, s->cur, layout, hs);
+        if (e != hipSuccess)
+            return hip_fail(s, e, "set_layout");
+        s->cur.x = 1 - s->cur.x;
+    }
+    s->d.layout = layout;
+    return TMD_OK;
+}
+
+tmd_status tmd_set_layout(tmd_system *s, int32_t layout, tmd_stream stream) {
+    if (!s || (layout != kLayoutSoA && layout != kLayoutAoS && layout != kLayoutAoSoA))
+        return TMD_EINVAL;
+    if (layout != kLayoutSoA && s->d.model != TMD_MODEL_LJ)
+        return fail(s, TMD_EINVAL, "set_layout: the Spring-Dashpot model keeps SoA positions");
+    return relayout(s, layout, static_cast<hipStream_t>(stream));
 }
 
 tmd_status tmd_set_half_list(tmd_system *s, int32_t half) {
@@ -1109,12 +1139,13 @@ static hipError_t time_build(tmd_system *s, int32_t repeats, hipStream_t hs, hip
     return e;
 }
 
-tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
+tmd_status tmd_autotune(tmd_system *s, int32_t repeats, int32_t flags, tmd_stream stream) {
     tmd_status st = check_ready(s, true);
     if (st != TMD_OK)
         return st;
-    if (repeats < 1)
-        return fail(s, TMD_EINVAL, "autotune: repeats < 1");
+    if (repeats < 1 || (flags & ~TMD_TUNE_ADJOINT) != 0)
+        return fail(s, TMD_EINVAL, "autotune: repeats < 1 or unknown flags");
+    const bool for_adjoint = (flags & TMD_TUNE_ADJOINT) != 0;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
@@ -1127,7 +1158,7 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
             best_bt = s->d.bthreads, best_bl = s->d.blanes, best_h = s->d.half;
     // half lists (Lennard-Jones only) take one workgroup per block and one
     // lane per atom
-    const int32_t hmax = s->d.model == TMD_MODEL_LJ ? 1 : 0;
+    const int32_t hmax = s->d.model == TMD_MODEL_LJ && !for_adjoint ? 1 : 0;
     for (int32_t EH = 0; EH < (kMaxEdge - 1) * (hmax + 1) && e == hipSuccess; ++EH) {
         const int32_t E = 2 + EH / (hmax + 1), H = EH % (hmax + 1);
         s->d.half = H;
@@ -1206,7 +1237,44 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, tmd_stream stream) {
     s->d.bthreads = best_bt;
     s->d.blanes = best_bl;
     s->list_valid = s->force_valid = false;
-    return rebuild(s, hs);
+    if ((st = rebuild(s, hs)) != TMD_OK)
+        return st;
+    // the position layout, at the chosen schedule: a list build and the
+    // step kernel read positions (binning does too, once per rebuild, as
+    // the build)
+    if (for_adjoint && (st = relayout(s, kLayoutSoA, hs)) != TMD_OK)
+        return st;
+    if (s->d.model == TMD_MODEL_LJ && !for_adjoint) {
+        e = hipEventCreate(&a);
+        if (e == hipSuccess)
+            e = hipEventCreate(&b);
+        const int32_t start = s->d.layout;
+        float lbest = 1e30f;
+        int32_t best_lay = start;
+        for (int32_t lay = 0; lay < 3 && e == hipSuccess && st == TMD_OK; ++lay) {
+            if ((st = relayout(s, lay, hs)) != TMD_OK)
+                break;
+            float mb = 0.0f, mf = 0.0f;
+            e = time_build(s, repeats, hs, a, b, mb);
+            if (e == hipSuccess)
+                e = time_force(s, repeats, hs, a, b, mf);
+            const float ms = mf + mb / float(s->rebuild_every);
+            // within 1% the earlier (SoA first) layout stays
+            if (e == hipSuccess && ms < 0.99f * lbest) {
+                lbest = ms;
+                best_lay = lay;
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (st == TMD_OK && e == hipSuccess)
+            st = relayout(s, best_lay, hs);
+        if (st != TMD_OK)
+            return st;
+        if (e != hipSuccess)
+            return hip_fail(s, e, "autotune");
+    }
+    return TMD_OK;
 }
 
 tmd_status tmd_set_lj_params(tmd_system *s, const double *epsilon, const double *sigma, tmd_stream stream) {
@@ -1249,6 +1317,8 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
         return fail(s, TMD_EINVAL, "adjoint_forward: gradients are implemented for the Lennard-Jones model only");
     if (s->d.half)
         return fail(s, TMD_EINVAL, "adjoint_forward: the reverse pass needs full lists (tmd_set_half_list(0))");
+    if (s->d.layout != kLayoutSoA)
+        return fail(s, TMD_EINVAL, "adjoint_forward: the reverse pass needs TMD_LAYOUT_SOA positions");
     const int32_t R = s->rebuild_every;
     if (s->step % R != 0)
         return fail(s, TMD_ESTATE, "adjoint_forward: the step counter must be a multiple of rebuild_every");

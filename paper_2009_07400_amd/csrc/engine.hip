@@ -254,15 +254,27 @@ __device__ __forceinline__ lds_double *lds_slot(lds_double *base, int slot) {
 }
 
 struct GlobalPos {
-    const double *__restrict__ x;
-    const double *__restrict__ y;
-    const double *__restrict__ z;
-    __device__ __forceinline__ void get(int j, double &a, double &b, double &c) const {
-        a = x[j];
-        b = y[j];
-        c = z[j];
-    }
+    PosL P;
+    __device__ __forceinline__ void get(int j, double &a, double &b, double &c) const { P.get(j, a, b, c); }
 };
+
+// Atom i of position buffer p in layout `lay`, for kernels that take the
+// buffer as a restrict-qualified argument (so that its reads may move past
+// the kernel's stores).  A kernel may pass its layout as a template
+// constant: the list build does.
+__device__ __forceinline__ void pos_get(int lay, int ntp, const double *__restrict__ p, int i, double &a, double &b,
+                                        double &c) {
+    PosL{const_cast<double *>(p), ntp, lay}.get(i, a, b, c);
+}
+
+__device__ __forceinline__ void pos_put(int lay, int ntp, double *__restrict__ p, int i, double a, double b,
+                                        double c) {
+    PosL{p, ntp, lay}.put(i, a, b, c);
+}
+
+__device__ __forceinline__ PosL pos_of(int lay, int ntp, const double *p) {
+    return PosL{const_cast<double *>(p), ntp, lay};
+}
 
 // Periodic images of a neighborhood copy (the role of the shifted ghost
 // copies of Sec. 4.3).  With `on`, every staged position is moved to its
@@ -369,9 +381,8 @@ __device__ __forceinline__ HoodImage hood_image(const Box &B, int lb, bool want)
 // LDS capacity, the same slot for every block): list padding points there,
 // and every comparison with a NaN distance is false, so padded entries need
 // no test.  Ends with a workgroup barrier.
-__device__ __forceinline__ void hood_stage(const Hood &h, int total, int sent, const double *__restrict__ x,
-                                           const double *__restrict__ y, const double *__restrict__ z,
-                                           lds_double *s, const HoodImage &im) {
+__device__ __forceinline__ void hood_stage(const Hood &h, int total, int sent, const PosL &P, lds_double *s,
+                                           const HoodImage &im) {
     // four slots per thread per round: the four searches, then all twelve
     // global loads in flight together, then the LDS writes.  Every memory
     // operation is unconditional: a slot past the end copies the last atom
@@ -389,11 +400,8 @@ __device__ __forceinline__ void hood_stage(const Hood &h, int total, int sent, c
             g[r] = h.cs[us[r]] + (ts[r] - h.off[us[r]]);
         double px[R], py[R], pz[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            px[r] = x[g[r]];
-            py[r] = y[g[r]];
-            pz[r] = z[g[r]];
-        }
+        for (int r = 0; r < R; ++r)
+            P.get(g[r], px[r], py[r], pz[r]);
         if (im.on) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -472,17 +480,16 @@ __global__ __launch_bounds__(kAtomThreads) void k_load_state(Dims d, const Box *
                                                              const double *__restrict__ iz,
                                                              const double *__restrict__ ivx,
                                                              const double *__restrict__ ivy,
-                                                             const double *__restrict__ ivz, double *x, double *y,
-                                                             double *z, double *vx, double *vy, double *vz,
-                                                             int32_t *orig, double *x2, double *y2, double *z2,
+                                                             const double *__restrict__ ivz, PosL P, double *vx,
+                                                             double *vy, double *vz, int32_t *orig, PosL P2,
                                                              int32_t *err) {
     const int i = blockIdx.x * kAtomThreads + threadIdx.x;
     if (i == 0) {
         // sentinel atom at slot nt of both position buffers: list padding of
         // blocks that gather from global memory points here
         const double nan = __builtin_nan("");
-        x[d.nt] = y[d.nt] = z[d.nt] = nan;
-        x2[d.nt] = y2[d.nt] = z2[d.nt] = nan;
+        P.put(d.nt, nan, nan, nan);
+        P2.put(d.nt, nan, nan, nan);
     }
     if (i >= d.nt)
         return;
@@ -493,35 +500,24 @@ __global__ __launch_bounds__(kAtomThreads) void k_load_state(Dims d, const Box *
         atomicOr(err, kErrNonFinite);
     if (!(px >= 0.0 && px < L && py >= 0.0 && py < L && pz >= 0.0 && pz < L))
         atomicOr(err, isfinite(px) && isfinite(py) && isfinite(pz) ? kErrOutOfBox : kErrNonFinite);
-    x[i] = px;
-    y[i] = py;
-    z[i] = pz;
+    P.put(i, px, py, pz);
     vx[i] = a;
     vy[i] = b;
     vz[i] = c;
     orig[i] = i;
 }
 
-// Scatter per-atom vectors back to original order; with boxes, they are
-// positions, wrapped into [0, L) on the way (they drift unwrapped between
-// list builds).
+// Scatter per-atom vectors back to original order.
 __global__ __launch_bounds__(kAtomThreads) void k_unload(int n, const double *__restrict__ ax,
                                                          const double *__restrict__ ay,
                                                          const double *__restrict__ az,
                                                          const int32_t *__restrict__ orig, double *o0, double *o1,
-                                                         double *o2, const Box *__restrict__ boxes,
-                                                         const int32_t *__restrict__ atom_box) {
+                                                         double *o2) {
     const int p = blockIdx.x * kAtomThreads + threadIdx.x;
     if (p >= n)
         return;
     const int o = orig[p];
-    double a = ax[p], b = ay[p], c = az[p];
-    if (boxes) {
-        const double L = boxes[atom_box[p]].L;
-        a = wrap(a, L);
-        b = wrap(b, L);
-        c = wrap(c, L);
-    }
+    const double a = ax[p], b = ay[p], c = az[p];
     if (o0)
         o0[o] = a;
     if (o1)
@@ -530,21 +526,56 @@ __global__ __launch_bounds__(kAtomThreads) void k_unload(int n, const double *__
         o2[o] = c;
 }
 
+// Positions back to original order, wrapped into [0, L) on the way (they
+// drift unwrapped between list builds).
+__global__ __launch_bounds__(kAtomThreads) void k_unload_pos(int n, PosL P, const int32_t *__restrict__ orig,
+                                                             double *o0, double *o1, double *o2,
+                                                             const Box *__restrict__ boxes,
+                                                             const int32_t *__restrict__ atom_box) {
+    const int p = blockIdx.x * kAtomThreads + threadIdx.x;
+    if (p >= n)
+        return;
+    const int o = orig[p];
+    double a, b, c;
+    P.get(p, a, b, c);
+    const double L = boxes[atom_box[p]].L;
+    o0[o] = wrap(a, L);
+    o1[o] = wrap(b, L);
+    o2[o] = wrap(c, L);
+}
+
+// Copy a position buffer (all ntp slots, the sentinel included) into
+// another layout, and put the sentinel into the other buffer in that layout.
+__global__ __launch_bounds__(kAtomThreads) void k_relayout(int ntp, int nt, PosL from, PosL to, PosL other) {
+    const int i = blockIdx.x * kAtomThreads + threadIdx.x;
+    if (i >= ntp)
+        return;
+    double a, b, c;
+    from.get(i, a, b, c);
+    to.put(i, a, b, c);
+    if (i == nt) {
+        const double nan = __builtin_nan("");
+        other.put(nt, nan, nan, nan);
+    }
+}
+
 // ------------------------------------------------------------------ binning
 
 // Cell slot of every atom and its (arbitrary) arrival rank within the cell.
 __global__ __launch_bounds__(kAtomThreads) void k_bin_count(Dims d, const Box *__restrict__ boxes,
-                                                            const int32_t *__restrict__ atom_box,
-                                                            const double *__restrict__ x,
-                                                            const double *__restrict__ y,
-                                                            const double *__restrict__ z, int32_t *cell_of,
-                                                            int32_t *slot, int32_t *cell_count, int32_t *err) {
+                                                            const int32_t *__restrict__ atom_box, PosL P,
+                                                            int32_t *cell_of, int32_t *slot, int32_t *cell_count,
+                                                            int32_t *err) {
     const int i = blockIdx.x * kAtomThreads + threadIdx.x;
     if (i >= d.nt)
         return;
     const Box &B = boxes[atom_box[i]];
     // positions drift unwrapped between list builds
-    const double px = wrap(x[i], B.L), py = wrap(y[i], B.L), pz = wrap(z[i], B.L);
+    double px, py, pz;
+    P.get(i, px, py, pz);
+    px = wrap(px, B.L);
+    py = wrap(py, B.L);
+    pz = wrap(pz, B.L);
     if (!(isfinite(px) && isfinite(py) && isfinite(pz)))
         atomicOr(err, kErrNonFinite);
     const int sx = sub_coord(px, B.hside, B.nc), sy = sub_coord(py, B.hside, B.nc),
@@ -715,10 +746,9 @@ __global__ __launch_bounds__(kAtomThreads) void k_scatter(int n, const int32_t *
 __global__ __launch_bounds__(kAtomThreads) void k_rank_permute(
     int n, int nbox, const Box *__restrict__ boxes, const int32_t *__restrict__ atom_box, const int32_t *__restrict__ tmp_idx,
     const int32_t *__restrict__ cell_of,
-    const int32_t *__restrict__ cell_start, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
-    const double *__restrict__ vz, const int32_t *__restrict__ orig, double *x2, double *y2, double *z2,
-    double *vx2, double *vy2, double *vz2, int32_t *orig2) {
+    const int32_t *__restrict__ cell_start, PosL P, const double *__restrict__ vx, const double *__restrict__ vy,
+    const double *__restrict__ vz, const int32_t *__restrict__ orig, PosL P2, double *vx2, double *vy2,
+    double *vz2, int32_t *orig2) {
     __shared__ int32_t keys[kAtomThreads];
     const int q0 = blockIdx.x * kAtomThreads, q = q0 + threadIdx.x;
     const int p = q < n ? tmp_idx[q] : 0;
@@ -730,7 +760,9 @@ __global__ __launch_bounds__(kAtomThreads) void k_rank_permute(
     // everything that depends only on the source slot is requested at once
     const int c = cell_of[p];
     const double L = boxes[nbox == 1 ? 0 : atom_box[p]].L;  // a box keeps its slot range
-    const double px = x[p], py = y[p], pz = z[p], pvx = vx[p], pvy = vy[p], pvz = vz[p];
+    double px, py, pz;
+    P.get(p, px, py, pz);
+    const double pvx = vx[p], pvy = vy[p], pvz = vz[p];
     const int b = cell_start[c], e = cell_start[c + 1];
     int rank = 0;
     for (int r = b; r < e; ++r) {
@@ -738,9 +770,7 @@ __global__ __launch_bounds__(kAtomThreads) void k_rank_permute(
         rank += int(kr < key);
     }
     const int dst = b + rank;
-    x2[dst] = wrap(px, L);
-    y2[dst] = wrap(py, L);
-    z2[dst] = wrap(pz, L);
+    P2.put(dst, wrap(px, L), wrap(py, L), wrap(pz, L));
     vx2[dst] = pvx;
     vy2[dst] = pvy;
     vz2[dst] = pvz;
@@ -858,9 +888,8 @@ __device__ __forceinline__ int sub_bin(const Box &B, const SubGrid &G, int g, in
 // soff[g] = first slot of grid subcell g, soff[ng] = atoms staged.  Ends
 // with a barrier.
 __device__ __forceinline__ void sub_stage(const Box &B, const SubGrid &G, const Hood &h,
-                                          const int32_t *__restrict__ cell_start, const double *__restrict__ x,
-                                          const double *__restrict__ y, const double *__restrict__ z,
-                                          lds_double *S, lds_u16 *F, lds_u16 *soff, int *wsum) {
+                                          const int32_t *__restrict__ cell_start, const PosL &P, lds_double *S,
+                                          lds_u16 *F, lds_u16 *soff, int *wsum) {
     const int T = blockDim.x;
     for (int g = threadIdx.x; g < G.ng; g += T) {
         int u;
@@ -876,9 +905,11 @@ __device__ __forceinline__ void sub_stage(const Box &B, const SubGrid &G, const 
         const int dst = soff[g], fb = h.off[u] + (st - h.cs[u]);
         for (int k = 0; k < n; ++k) {
             lds_double *a = lds_slot(S, dst + k);
-            a[0] = x[st + k];
-            a[1] = y[st + k];
-            a[2] = z[st + k];
+            double px, py, pz;
+            P.get(st + k, px, py, pz);
+            a[0] = px;
+            a[1] = py;
+            a[2] = pz;
             F[dst + k] = uint16_t(fb + k);
         }
     }
@@ -1214,8 +1245,7 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
 // first lane alone).  fits: store force-kernel slots (16-bit), else global
 // indices (32-bit).  Returns the number of neighbors found.
 __device__ __forceinline__ int build_global(const Box &B, const SubGrid &G, const Hood &h, bool fits,
-                                            const int32_t *__restrict__ cell_start, const double *__restrict__ x,
-                                            const double *__restrict__ y, const double *__restrict__ z, int i,
+                                            const int32_t *__restrict__ cell_start, const PosL &P, int i,
                                             double xi, double yi, double zi, int X, int Y, int Z, int maxnb,
                                             int32_t *__restrict__ nbr, int nchunk) {
     uint16_t *nbr16 = reinterpret_cast<uint16_t *>(nbr);
@@ -1235,8 +1265,9 @@ __device__ __forceinline__ int build_global(const Box &B, const SubGrid &G, cons
                               wrap_index(cx - G.c0[0] + 1, B.nc);
                 const int fb = h.off[u] - h.cs[u];
                 for (int g = st; g < en; ++g) {
-                    double dx, dy, dz;
-                    const double s = pair_delta(xi, yi, zi, x[g], y[g], z[g], B.L, B.halfL, B.halfL2, dx, dy, dz);
+                    double dx, dy, dz, xj, yj, zj;
+                    P.get(g, xj, yj, zj);
+                    const double s = pair_delta(xi, yi, zi, xj, yj, zj, B.L, B.halfL, B.halfL2, dx, dy, dz);
                     if (s < B.rl2 && g != i) {
                         if (c < maxnb) {
                             if (fits)
@@ -1253,11 +1284,10 @@ __device__ __forceinline__ int build_global(const Box &B, const SubGrid &G, cons
     return c;
 }
 
-template <int BL>
+template <int BL, int LAY>
 __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__restrict__ boxes,
                                                        const int32_t *__restrict__ blk_box,
-                                                       const double *__restrict__ x, const double *__restrict__ y,
-                                                       const double *__restrict__ z,
+                                                       const double *__restrict__ pin,
                                                        const int32_t *__restrict__ cell_start,
                                                        int32_t *__restrict__ hood_tab, int32_t *__restrict__ cnt,
                                                        int32_t *__restrict__ nbr, int32_t *err) {
@@ -1285,7 +1315,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     lds_u16 *F = (lds_u16 *)((lds_char *)lds + 24 * nslot);
     lds_u16 *soff = F + nslot;
     if (rows)
-        sub_stage(B, G, h, cell_start, x, y, z, S, F, soff, wsum);
+        sub_stage(B, G, h, cell_start, pos_of(LAY, d.ntp, pin), S, F, soff, wsum);
     // list padding points at the NaN sentinel: force-kernel LDS slot cap, or
     // global slot nt
     const int sentinel = fits ? d.cap : d.nt;
@@ -1307,7 +1337,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
     const bool half = rows && block_half(d, B, lb, h, fits, s_lo, span);
     const int p = threadIdx.x & (BL - 1);  // lane of the atom's pair (BL = 2)
     for (int i = lo + threadIdx.x / BL; i < hi; i += blockDim.x / BL) {
-        const double xi = x[i], yi = y[i], zi = z[i];
+        double xi, yi, zi;
+        pos_get(LAY, d.ntp, pin, i, xi, yi, zi);
         const int X = sub_coord(xi, B.hside, B.nc), Y = sub_coord(yi, B.hside, B.nc),
                   Z = sub_coord(zi, B.hside, B.nc);
         int c = 0;
@@ -1330,7 +1361,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_build(Dims d, const Box *__rest
                 c = half ? TMD_ROWS(kRowsFace, true) : TMD_ROWS(kRowsFace, false);
 #undef TMD_ROWS
         } else if (p == 0) {
-            c = build_global(B, G, h, fits, cell_start, x, y, z, i, xi, yi, zi, X, Y, Z, d.maxnb, nbr, d.nchunk);
+            c = build_global(B, G, h, fits, cell_start, pos_of(LAY, d.ntp, pin), i, xi, yi, zi, X, Y, Z, d.maxnb,
+                             nbr, d.nchunk);
         }
         if (p != 0)
             continue;  // the pair's first lane holds the same count and finishes the list
@@ -1567,9 +1599,9 @@ __device__ __forceinline__ const v4i *list_chunks(const int32_t *nbr, int i, int
 // 0 stores F, 1 stores F and kicks v += h F, 2 kicks twice and drifts into
 // the other position buffer (k_force's epilogue).
 template <int MODE, bool THERMO>
-__device__ __forceinline__ void atom_epilogue(int i, double xi, double yi, double zi, double ax, double ay, double az,
-                                              const Box &B, double *vx, double *vy, double *vz, double *fx,
-                                              double *fy, double *fz, double *xo, double *yo, double *zo, double &ke,
+__device__ __forceinline__ void atom_epilogue(const Dims &d, int i, double xi, double yi, double zi, double ax,
+                                              double ay, double az, const Box &B, double *vx, double *vy, double *vz,
+                                              double *fx, double *fy, double *fz, double *pout, double &ke,
                                               int32_t *err) {
     if (MODE == 0 || MODE == 1) {
         fx[i] = ax;
@@ -1587,9 +1619,7 @@ __device__ __forceinline__ void atom_epilogue(int i, double xi, double yi, doubl
             bb = bb + B.h * ay;
             c = c + B.h * az;
             const double nx = xi + B.dt * a, ny = yi + B.dt * bb, nz = zi + B.dt * c;
-            xo[i] = nx;
-            yo[i] = ny;
-            zo[i] = nz;
+            pos_put(d.layout, d.ntp, pout, i, nx, ny, nz);
             if (!(isfinite(nx) && isfinite(ny) && isfinite(nz)))
                 atomicOr(err, kErrNonFinite);
         }
@@ -1613,15 +1643,13 @@ __device__ __forceinline__ void atom_epilogue(int i, double xi, double yi, doubl
 template <int MODE, bool THERMO, int L, bool HALF = false>
 __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__restrict__ boxes,
                                                        const int32_t *__restrict__ blk_box,
-                                                       const double *__restrict__ x, const double *__restrict__ y,
-                                                       const double *__restrict__ z,
+                                                       const double *__restrict__ pin,
                                                        const int32_t *__restrict__ hood_tab,
                                                        const int32_t *__restrict__ cnt,
                                                        const int32_t *__restrict__ nbr, double *__restrict__ vx,
                                                        double *__restrict__ vy, double *__restrict__ vz,
                                                        double *__restrict__ fx, double *__restrict__ fy,
-                                                       double *__restrict__ fz, double *__restrict__ xo,
-                                                       double *__restrict__ yo, double *__restrict__ zo,
+                                                       double *__restrict__ fz, double *__restrict__ pout,
                                                        double *__restrict__ partials, int32_t *err) {
     // no static LDS: the neighborhood copy starts at LDS address 0, where
     // the pair loop's slot addresses point, and the table and reduction
@@ -1651,7 +1679,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     const int total = h.off[h.ncell];
     const bool fits = total <= d.cap;
     lds_double *const S = (lds_double *)lds;
-    const GlobalPos gpos{x, y, z};
+    const GlobalPos gpos{pos_of(d.layout, d.ntp, pin)};
     const HoodImage im = hood_image(B, b - B.block_off, fits);
     // half lists: the reaction sums follow the table and reduction scratch
     lds_double *R = (lds_double *)((lds_char *)lds + tail + kForceLdsTail);
@@ -1676,9 +1704,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     v4i r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0};
     auto load_atom = [&](int k) {
         const int ic = min(k, hi - 1);
-        xi = x[ic];
-        yi = y[ic];
-        zi = z[ic];
+        pos_get(d.layout, d.ntp, pin, ic, xi, yi, zi);
         ci = cnt[ic];
         if (MODE >= 1) {
             vxi = vx[ic];
@@ -1696,10 +1722,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     if (hi > lo)
         load_atom(i);
     if (fits)
-        hood_stage(h, total, d.cap, x, y, z, S, im);
+        hood_stage(h, total, d.cap, pos_of(d.layout, d.ntp, pin), S, im);
     // have every kernel argument in registers before the atom loop: a scalar
     // load still in flight at the pair loop's head costs it exact LDS waits
-    asm volatile("" ::"s"(err), "s"(partials), "s"(xo), "s"(fx));
+    asm volatile("" ::"s"(err), "s"(partials), "s"(pout), "s"(fx));
     __builtin_amdgcn_s_setprio(0);
     double u = 0.0, w = 0.0, ke = 0.0;
     for (; i < hi; i += T) {
@@ -1748,9 +1774,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
                 // not wrapped: between list builds an atom stays next to its
                 // block's cells (the binning wraps)
                 const double nx = xi + B.dt * a, ny = yi + B.dt * bb, nz = zi + B.dt * c;
-                xo[i] = nx;
-                yo[i] = ny;
-                zo[i] = nz;
+                pos_put(d.layout, d.ntp, pout, i, nx, ny, nz);
                 if (!(isfinite(nx) && isfinite(ny) && isfinite(nz)))
                     atomicOr(err, kErrNonFinite);
             }
@@ -1764,8 +1788,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
         __syncthreads();
         for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
             const lds_double *r = R + 3 * (own_slot(B, b - B.block_off, h, k) - s_lo);
-            atom_epilogue<MODE, THERMO>(k, x[k], y[k], z[k], r[0], r[1], r[2], B, vx, vy, vz, fx, fy, fz, xo, yo, zo,
-                                        ke, err);
+            double xk, yk, zk;
+            pos_get(d.layout, d.ntp, pin, k, xk, yk, zk);
+            atom_epilogue<MODE, THERMO>(d, k, xk, yk, zk, r[0], r[1], r[2], B, vx, vy, vz, fx, fy, fz, pout, ke, err);
         }
     }
     if (THERMO) {
@@ -1782,13 +1807,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
 // First half of a step when F of the current positions is already stored.
 __global__ __launch_bounds__(kAtomThreads) void k_drift(Dims d, const Box *__restrict__ boxes,
                                                         const int32_t *__restrict__ atom_box,
-                                                        const double *__restrict__ x, const double *__restrict__ y,
-                                                        const double *__restrict__ z, double *__restrict__ vx,
+                                                        const double *__restrict__ pin, double *__restrict__ vx,
                                                         double *__restrict__ vy, double *__restrict__ vz,
                                                         const double *__restrict__ fx,
                                                         const double *__restrict__ fy,
-                                                        const double *__restrict__ fz, double *__restrict__ xo,
-                                                        double *__restrict__ yo, double *__restrict__ zo,
+                                                        const double *__restrict__ fz, double *__restrict__ pout,
                                                         int32_t *err) {
     const int i = blockIdx.x * kAtomThreads + threadIdx.x;
     if (i >= d.nt)
@@ -1798,10 +1821,10 @@ __global__ __launch_bounds__(kAtomThreads) void k_drift(Dims d, const Box *__res
     vx[i] = a;
     vy[i] = b;
     vz[i] = c;
-    const double nx = x[i] + B.dt * a, ny = y[i] + B.dt * b, nz = z[i] + B.dt * c;  // wrapped at binning
-    xo[i] = nx;
-    yo[i] = ny;
-    zo[i] = nz;
+    double px, py, pz;
+    pos_get(d.layout, d.ntp, pin, i, px, py, pz);
+    const double nx = px + B.dt * a, ny = py + B.dt * b, nz = pz + B.dt * c;  // wrapped at binning
+    pos_put(d.layout, d.ntp, pout, i, nx, ny, nz);
     if (!(isfinite(nx) && isfinite(ny) && isfinite(nz)))
         atomicOr(err, kErrNonFinite);
 }
@@ -2361,8 +2384,12 @@ static_assert(sizeof(Hood) + 3 * (kMaxThreads / 64) * sizeof(double) <= kBlockSt
 
 hipError_t prepare_kernels(int dyn_bytes) {
     const void *fns[] = {
-        reinterpret_cast<const void *>(&k_build<1>),
-        reinterpret_cast<const void *>(&k_build<2>),
+        reinterpret_cast<const void *>(&k_build<1, kLayoutSoA>),
+        reinterpret_cast<const void *>(&k_build<1, kLayoutAoS>),
+        reinterpret_cast<const void *>(&k_build<1, kLayoutAoSoA>),
+        reinterpret_cast<const void *>(&k_build<2, kLayoutSoA>),
+        reinterpret_cast<const void *>(&k_build<2, kLayoutAoS>),
+        reinterpret_cast<const void *>(&k_build<2, kLayoutAoSoA>),
         reinterpret_cast<const void *>(&k_force<0, false, 1>),
         reinterpret_cast<const void *>(&k_force<0, true, 1>),
         reinterpret_cast<const void *>(&k_force<1, false, 1>),
@@ -2487,23 +2514,30 @@ hipError_t launch_load_state(const Dims &d, const double *const pos[3], const do
                              Cursor c, hipStream_t s) {
     const double *v0 = vel ? vel[0] : nullptr, *v1 = vel ? vel[1] : nullptr, *v2 = vel ? vel[2] : nullptr;
     k_load_state<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, pos[0], pos[1], pos[2], v0,
-                                                             v1, v2, b.x[c.x], b.y[c.x], b.z[c.x],
-                                                             b.vx[c.v], b.vy[c.v], b.vz[c.v], b.orig[c.o],
-                                                             b.x[1 - c.x], b.y[1 - c.x], b.z[1 - c.x], b.err);
+                                                             v1, v2, pos_layout(d, b.pos(c.x)), b.vx[c.v], b.vy[c.v],
+                                                             b.vz[c.v], b.orig[c.o], pos_layout(d, b.pos(1 - c.x)),
+                                                             b.err);
     return hipGetLastError();
 }
 
 hipError_t launch_unload(const Dims &d, const double *ax, const double *ay, const double *az, const int32_t *orig,
                          double *const out[3], hipStream_t s) {
-    k_unload<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, ax, ay, az, orig, out[0], out[1], out[2], nullptr,
-                                                         nullptr);
+    k_unload<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, ax, ay, az, orig, out[0], out[1], out[2]);
     return hipGetLastError();
 }
 
 hipError_t launch_unload_pos(const Dims &d, const Buffers &b, const Pos &p, const int32_t *orig, double *const out[3],
                              hipStream_t s) {
-    k_unload<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, p.x, p.y, p.z, orig, out[0], out[1], out[2], b.boxes,
-                                                         b.atom_box);
+    k_unload_pos<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, pos_layout(d, p), orig, out[0], out[1], out[2],
+                                                             b.boxes, b.atom_box);
+    return hipGetLastError();
+}
+
+hipError_t launch_relayout(const Dims &d, Buffers &b, Cursor c, int layout, hipStream_t s) {
+    Dims to = d;
+    to.layout = layout;
+    k_relayout<<<(d.ntp + kAtomThreads - 1) / kAtomThreads, kAtomThreads, 0, s>>>(
+        d.ntp, d.nt, pos_layout(d, b.pos(c.x)), pos_layout(to, b.pos(1 - c.x)), pos_layout(to, b.pos(c.x)));
     return hipGetLastError();
 }
 
@@ -2515,7 +2549,7 @@ hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, bool counts_clear, hi
         if (e != hipSuccess)
             return e;
     }
-    k_bin_count<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, b.x[xc], b.y[xc], b.z[xc],
+    k_bin_count<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, pos_layout(d, b.pos(xc)),
                                                             b.cell_of, b.slot, b.cell_count, b.err);
     if (nbin <= kScanOne) {
         k_scan_one<<<1, 1024, 0, s>>>(b.cell_count, b.cell_start, nbin);
@@ -2527,37 +2561,41 @@ hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, bool counts_clear, hi
     }
     k_scatter<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.cell_of, b.slot, b.cell_start, b.tmp_idx);
     k_rank_permute<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, d.nbox, b.boxes, b.atom_box, b.tmp_idx, b.cell_of,
-                                                               b.cell_start, b.x[xc],
-                                                               b.y[xc], b.z[xc], b.vx[v], b.vy[v], b.vz[v],
-                                                               b.orig[o], b.x[xn], b.y[xn], b.z[xn], b.vx[vn],
-                                                               b.vy[vn], b.vz[vn], b.orig[on]);
+                                                               b.cell_start, pos_layout(d, b.pos(xc)), b.vx[v],
+                                                               b.vy[v], b.vz[v], b.orig[o], pos_layout(d, b.pos(xn)),
+                                                               b.vx[vn], b.vy[vn], b.vz[vn], b.orig[on]);
     return hipGetLastError();
 }
 
 hipError_t launch_build(const Dims &d, Buffers &b, Cursor c, hipStream_t s) {
-    if (d.blanes == 2)
-        k_build<2><<<block_grid(d.nblk * d.parts), d.bthreads, hood_lds_bytes(d.cap), s>>>(
-            d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.hood_tab, b.nbr_count, b.nbr,
-            b.err);
-    else
-        k_build<1><<<block_grid(d.nblk * d.parts), d.bthreads, hood_lds_bytes(d.cap), s>>>(
-            d, b.boxes, b.blk_box, b.x[c.x], b.y[c.x], b.z[c.x], b.cell_start, b.hood_tab, b.nbr_count, b.nbr,
-            b.err);
+#define TMD_BUILD(BL, LAY)                                                                                          \
+    k_build<BL, LAY><<<block_grid(d.nblk * d.parts), d.bthreads, hood_lds_bytes(d.cap), s>>>(                          \
+        d, b.boxes, b.blk_box, b.x[c.x], b.cell_start, b.hood_tab, b.nbr_count, b.nbr, b.err)
+    switch ((d.blanes == 2 ? 3 : 0) + d.layout) {
+    case 0: TMD_BUILD(1, kLayoutSoA); break;
+    case 1: TMD_BUILD(1, kLayoutAoS); break;
+    case 2: TMD_BUILD(1, kLayoutAoSoA); break;
+    case 3: TMD_BUILD(2, kLayoutSoA); break;
+    case 4: TMD_BUILD(2, kLayoutAoS); break;
+    case 5: TMD_BUILD(2, kLayoutAoSoA); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef TMD_BUILD
     return hipGetLastError();
 }
 
 template <int MODE, bool THERMO, int L>
 static void force_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
     k_force<MODE, THERMO, L><<<block_grid(d.nblk * d.parts), d.threads, force_lds_bytes(d.cap), s>>>(
-        d, b.boxes, b.blk_box, in.x, in.y, in.z, b.hood_tab, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
-        b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
+        d, b.boxes, b.blk_box, in.x, b.hood_tab, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx, b.fy, b.fz,
+        out.x, b.partials, b.err);
 }
 
 template <int MODE, bool THERMO>
 static void force_half_variant(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
     k_force<MODE, THERMO, 1, true><<<block_grid(d.nblk * d.parts), d.threads, force_half_lds_bytes(d.cap, d.rcap), s>>>(
-        d, b.boxes, b.blk_box, in.x, in.y, in.z, b.hood_tab, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx,
-        b.fy, b.fz, out.x, out.y, out.z, b.partials, b.err);
+        d, b.boxes, b.blk_box, in.x, b.hood_tab, b.nbr_count, b.nbr, b.vx[o], b.vy[o], b.vz[o], b.fx, b.fy, b.fz,
+        out.x, b.partials, b.err);
 }
 
 template <int MODE, bool THERMO>
@@ -2624,8 +2662,8 @@ hipError_t launch_force(const Dims &d, Buffers &b, Cursor c, int mode, bool ther
 }
 
 hipError_t launch_drift_at(const Dims &d, Buffers &b, const Pos &in, const Pos &out, int o, hipStream_t s) {
-    k_drift<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, in.x, in.y, in.z, b.vx[o], b.vy[o],
-                                                        b.vz[o], b.fx, b.fy, b.fz, out.x, out.y, out.z, b.err);
+    k_drift<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d, b.boxes, b.atom_box, in.x, b.vx[o], b.vy[o], b.vz[o], b.fx,
+                                                        b.fy, b.fz, out.x, b.err);
     return hipGetLastError();
 }
 

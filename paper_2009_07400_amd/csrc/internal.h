@@ -81,6 +81,7 @@ struct Dims {
     int32_t model;    // force model of every box: 0 Lennard-Jones, 1 Spring-Dashpot
     int32_t half;     // 1: half lists inside blocks (Newton's third law in the force kernel's LDS)
     int32_t rcap;     // LDS slots of a block's reaction sums with half lists (0 without)
+    int32_t layout;   // position layout: 0 SoA, 1 AoS, 2 AoSoA of 64-atom clusters (PosL)
 };
 
 // Neighbor list layout: neighbor-major within tiles of 64 atoms (one
@@ -105,6 +106,60 @@ __host__ __device__ inline int64_t nbr_index16(int i, int k, int nchunk) {
 struct Pos {
     double *x, *y, *z;
 };
+
+// One position buffer of 3 ntp doubles in one of the particle layouts of
+// Sec. 4.2 (ArrayLayout): 0 SoA (column-major: x of every atom, then y,
+// then z), 1 AoS (row-major: x, y, z of an atom side by side), 2 AoSoA
+// (clustered: 64 atoms - one wavefront - per cluster, their 64 x, 64 y and
+// 64 z in turn).  Every layout keeps slot nt (the NaN sentinel atom) and the
+// padding below ntp inside the buffer (ntp is a multiple of 256).  Offsets
+// are 32-bit (3 ntp < 2^31): the list build keeps fewer registers, and AoS
+// and AoSoA reach y and z at constant offsets from x.
+enum { kLayoutSoA = 0, kLayoutAoS = 1, kLayoutAoSoA = 2 };
+
+struct PosL {
+    double *p;
+    int32_t ntp, layout;
+    __device__ __forceinline__ void get(int i, double &a, double &b, double &c) const {
+        if (layout == kLayoutSoA) {
+            a = p[i];
+            b = p[i + ntp];
+            c = p[i + 2 * ntp];
+        } else if (layout == kLayoutAoS) {
+            const double *q = p + 3 * i;
+            a = q[0];
+            b = q[1];
+            c = q[2];
+        } else {
+            const double *q = p + ((i >> 6) * 192 + (i & 63));
+            a = q[0];
+            b = q[64];
+            c = q[128];
+        }
+    }
+    __device__ __forceinline__ void put(int i, double a, double b, double c) const {
+        if (layout == kLayoutSoA) {
+            p[i] = a;
+            p[i + ntp] = b;
+            p[i + 2 * ntp] = c;
+        } else if (layout == kLayoutAoS) {
+            double *q = p + 3 * i;
+            q[0] = a;
+            q[1] = b;
+            q[2] = c;
+        } else {
+            double *q = p + ((i >> 6) * 192 + (i & 63));
+            q[0] = a;
+            q[64] = b;
+            q[128] = c;
+        }
+    }
+};
+
+// The buffer behind a Pos whose y and z follow x at strides of ntp (every
+// position buffer of the workspace and of the adjoint's storage), read in
+// layout d.layout.
+inline PosL pos_layout(const Dims &d, const Pos &q) { return PosL{q.x, d.ntp, d.layout}; }
 
 // Device pointers carved from the caller's workspace.
 struct Buffers {
@@ -186,6 +241,10 @@ hipError_t launch_unload(const Dims &d, const double *ax, const double *ay, cons
 // launch_unload for positions, wrapped into [0, L) on the way.
 hipError_t launch_unload_pos(const Dims &d, const Buffers &b, const Pos &p, const int32_t *orig, double *const out[3],
                              hipStream_t s);
+// Copy the current positions (half c.x, layout d.layout) into the other half
+// in `layout`, with the NaN sentinel in both halves in that layout; the
+// caller then flips c.x.
+hipError_t launch_relayout(const Dims &d, Buffers &b, Cursor c, int layout, hipStream_t s);
 // Binning (both halves flip).  counts_clear: the cell counts are known to be
 // zero (left so by the previous binning's one-workgroup scan), which skips
 // clearing them first.

@@ -181,29 +181,38 @@ class System:
         abi.tmd_set_schedule(self._h, threads, lds_atoms, block_edge, block_parts, lanes_per_atom, build_threads,
                              build_lanes)
 
+    LAYOUTS = {"soa": 0, "aos": 1, "aosoa": 2}
+
+    def set_layout(self, layout) -> None:
+        """Memory layout of the device positions: "soa", "aos" or "aosoa"
+        (or 0, 1, 2); converts the current positions on the current stream."""
+        code = self.LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+        abi.tmd_set_layout(self._h, code, _stream())
+
     def set_half_list(self, half: bool) -> None:
         """Half neighbor lists inside blocks (Newton's third law) for the
         Lennard-Jones model; needs one workgroup per block and one lane per
         atom.  The next step rebuilds the list."""
         abi.tmd_set_half_list(self._h, 1 if half else 0)
 
-    def autotune(self, repeats: int = 5, cache: str | None = None):
+    def autotune(self, repeats: int = 5, cache: str | None = None, for_adjoint: bool = False):
         """Times each schedule (block edge, full or half lists, workgroups
-        per block, lanes per atom, force and build threads) by one force
-        evaluation plus a list build's share per step and keeps the fastest;
-        returns a dict of block_edge, block_parts, lanes_per_atom,
-        block_threads, build_threads, build_lanes, lds_atoms and half_list,
-        and "cached".  Rebuilds the list at the
+        per block, lanes per atom, force and build threads, then the position
+        layout) by one force evaluation plus a list build's share per step
+        and keeps the fastest; returns a dict of block_edge, block_parts,
+        lanes_per_atom, block_threads, build_threads, build_lanes, lds_atoms,
+        half_list and layout, and "cached".  Rebuilds the list at the
         current positions.
 
         With ``cache`` (a JSON file path), a schedule stored there for the
         same device, library build and system shape is applied instead of
         tuning ("cached": True; the list is rebuilt at the next step), and
-        a fresh pick is stored."""
+        a fresh pick is stored.  for_adjoint keeps to the schedules the
+        adjoint runs with (full lists, SoA positions)."""
         key = None
         if cache is not None:
             key = tune_cache.system_key(torch.cuda.get_device_name(self.device), tune_cache.file_digest(abi.LIB_PATH),
-                                        self.box_atoms, self.box_lengths, self.params)
+                                        self.box_atoms, self.box_lengths, self.params, for_adjoint)
             hit = tune_cache.lookup(cache, key)
             if hit is not None:
                 self.set_half_list(False)
@@ -212,8 +221,9 @@ class System:
                                   lanes_per_atom=hit["lanes_per_atom"], build_threads=hit["build_threads"],
                                   build_lanes=hit["build_lanes"])
                 self.set_half_list(bool(hit["half_list"]))
+                self.set_layout(hit["layout"])
                 return dict(hit, cached=True)
-        abi.tmd_autotune(self._h, repeats, _stream())
+        abi.tmd_autotune(self._h, repeats, _stream(), abi.TMD_TUNE_ADJOINT if for_adjoint else 0)
         info = self.info()
         sched = {k: info[k] for k in tune_cache.SCHEDULE_KEYS}
         if key is not None:

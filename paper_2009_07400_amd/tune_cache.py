@@ -20,7 +20,7 @@ VERSION = 1
 
 # tmd_info fields that make up a schedule, as tmd_set_schedule takes them
 SCHEDULE_KEYS = ("block_threads", "lds_atoms", "block_edge", "block_parts", "lanes_per_atom", "build_threads",
-                 "build_lanes", "half_list")
+                 "build_lanes", "half_list", "layout")
 
 _PARAM_FIELDS = ("epsilon", "sigma", "mass", "cutoff", "skin", "dt", "rebuild_every", "max_neighbors")
 
@@ -41,10 +41,12 @@ def file_digest(path: str) -> str:
 
 
 def system_key(device: str, library: str, box_atoms: Sequence[int], box_lengths: Sequence[float],
-               params: Sequence) -> str:
+               params: Sequence, for_adjoint: bool = False) -> str:
     """Signature of a system: device name, library digest, per-box atom
-    counts, box lengths (exact, as repr) and parameters."""
+    counts, box lengths (exact, as repr), parameters, and whether the
+    schedule is for the adjoint."""
     sig = {
+        "adjoint": bool(for_adjoint),
         "device": device,
         "library": library,
         "atoms": [int(n) for n in box_atoms],

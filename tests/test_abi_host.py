@@ -83,6 +83,7 @@ def test_graph_mode_switch_needs_no_gpu():
     ({}, 10, float("nan"), abi.TMD_EINVAL),
     ({}, 10, 5.6, abi.TMD_EBOX),      # cutoff + skin = 2.8 = L/2
     ({}, 10, 5.0, abi.TMD_EBOX),
+    ({}, 700_000_001, 2000.0, abi.TMD_EINVAL),  # 3 n_padded doubles addressed with 32-bit offsets
     # Spring-Dashpot (Eq. 3): non-negative finite K and gamma, list radius
     # base cutoff >= the diameter sigma
     (dict(model="spring_dashpot", stiffness=-1.0, cutoff=1.0), 10, 13.4, abi.TMD_EINVAL),
@@ -259,5 +260,27 @@ def test_half_list_switch_validates_on_the_host():
     try:
         with pytest.raises(abi.TmdError):
             abi.tmd_set_half_list(sd, 1)
+    finally:
+        abi.tmd_destroy(sd)
+
+
+def test_layout_switch_validates_on_the_host():
+    h = _create()
+    try:
+        assert abi.tmd_get_info(h)["layout"] == abi.TMD_LAYOUT_SOA
+        for bad in (3, -1):
+            with pytest.raises(abi.TmdError) as e:
+                abi.tmd_set_layout(h, bad, 0)
+            assert e.value.status == abi.TMD_EINVAL
+        for lay in (abi.TMD_LAYOUT_AOS, abi.TMD_LAYOUT_AOSOA, abi.TMD_LAYOUT_SOA):
+            abi.tmd_set_layout(h, lay, 0)  # no state yet: nothing to convert, no GPU call
+            assert abi.tmd_get_info(h)["layout"] == lay
+    finally:
+        abi.tmd_destroy(h)
+    sd = abi.tmd_create(make_params(model="spring_dashpot", stiffness=100.0, damping=1.0, cutoff=1.0), 100, 13.4)
+    try:
+        with pytest.raises(abi.TmdError):
+            abi.tmd_set_layout(sd, abi.TMD_LAYOUT_AOS, 0)
+        abi.tmd_set_layout(sd, abi.TMD_LAYOUT_SOA, 0)
     finally:
         abi.tmd_destroy(sd)

@@ -144,7 +144,7 @@ def replica_grads():
     g = System.batch([n1] * REPLICAS, [L] * REPLICAS, dict(max_neighbors=128))
     g.set_state(torch.from_numpy(x0), torch.from_numpy(v0))
     g.integrate(20)
-    g.autotune(repeats=3)
+    g.autotune(repeats=3, for_adjoint=True)
     ones = torch.ones(REPLICAS, dtype=torch.float64)
     with torch.no_grad():
         tgt = lj_md(1.05 * ones, 0.98 * ones, torch.from_numpy(x0), g, torch.from_numpy(v0), STEPS)

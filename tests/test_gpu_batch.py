@@ -211,7 +211,7 @@ def test_autotune_cache_applies_the_stored_schedule(tmp_path):
     (first, info1), (second, info2) = picks
     assert first["cached"] is False and second["cached"] is True
     keys = ("block_threads", "lds_atoms", "block_edge", "block_parts", "lanes_per_atom", "build_threads",
-            "build_lanes", "half_list")
+            "build_lanes", "half_list", "layout")
     assert {k: first[k] for k in keys} == {k: second[k] for k in keys}
     assert all(info1[k] == info2[k] for k in keys)
 

@@ -7,14 +7,15 @@ from paper_2009_07400_amd import tune_cache
 from paper_2009_07400_amd.system import make_params
 
 SCHED = {"block_threads": 640, "lds_atoms": 3328, "block_edge": 3, "block_parts": 1, "lanes_per_atom": 1,
-         "build_threads": 512, "build_lanes": 1, "half_list": 0}
+         "build_threads": 512, "build_lanes": 1, "half_list": 0, "layout": 0}
 
 
 def _key(**over):
     a = dict(device="AMD Instinct MI355X", library="0123456789abcdef", box_atoms=[4000, 256],
              box_lengths=[16.79596, 6.7183], params=[make_params(), make_params(epsilon=1.05)])
+    adj = over.pop("for_adjoint", False)
     a.update(over)
-    return tune_cache.system_key(a["device"], a["library"], a["box_atoms"], a["box_lengths"], a["params"])
+    return tune_cache.system_key(a["device"], a["library"], a["box_atoms"], a["box_lengths"], a["params"], adj)
 
 
 def test_key_is_stable_and_covers_every_input():
@@ -24,7 +25,7 @@ def test_key_is_stable_and_covers_every_input():
                _key(box_lengths=[16.79596, 6.7183000000000002e0 + 1e-12]),
                _key(params=[make_params(), make_params(epsilon=1.0500000001)]),
                _key(params=[make_params(), make_params(epsilon=1.05, max_neighbors=160)]),
-               _key(box_atoms=[256, 4000], box_lengths=[6.7183, 16.79596])]
+               _key(box_atoms=[256, 4000], box_lengths=[6.7183, 16.79596]), _key(for_adjoint=True)]
     assert len({k, *changed}) == len(changed) + 1
 
 
