@@ -65,7 +65,7 @@ def _traffic(workload: str):
 def _schedule(g) -> dict:
     info = g.info()
     return {k: info[k] for k in ("block_edge", "block_parts", "lanes_per_atom", "block_threads", "build_threads",
-                                 "build_lanes", "lds_atoms")}
+                                 "build_lanes", "lds_atoms", "half_list", "layout")}
 
 
 REBUILD_EVERY = 20  # list rebuild interval of every workload here
@@ -450,6 +450,47 @@ def run_spring_dashpot(steps: int = 200, warmup: int = 20):
     return out
 
 
+def run_axes(steps: int = 40):
+    """The schedule axes the autotuner weighs, measured one by one on the
+    131k- and 3.5M-atom workloads at block edges 2 and 3 (default threads):
+    the position layout (SoA, AoS, AoSoA; full lists) and half lists inside
+    blocks (SoA).  Per variant the mean force (step kernel), list-build and
+    binning times over `steps` steps after one rebuild interval, the mean
+    list length, and the implied time per step."""
+    import torch
+
+    from paper_2009_07400_amd import System
+    from workloads import md_system
+
+    out = {}
+    for wl in ("c1", "c2"):
+        w = WORKLOADS[wl]
+        s = md_system(w["ncell"], w["rho"], w["T"], seed=w["seed"], jitter=w["jitter"])
+        rows = []
+        for edge in (2, 3):
+            for half, layout in ((False, "soa"), (False, "aos"), (False, "aosoa"), (True, "soa")):
+                g = System(s.n, s.L, max_neighbors=128)
+                g.set_state(torch.from_numpy(s.pos()), torch.from_numpy(s.vel()))
+                g.set_schedule(block_edge=edge)
+                g.set_half_list(half)
+                g.set_layout(layout)
+                g.integrate(REBUILD_EVERY)
+                g.set_timing(True)
+                g.integrate(steps)
+                g.sync()
+                tm = g.get_timing()
+                g.set_timing(False)
+                ml = float(g.neighbor_counts().double().mean().item())
+                g.sync()
+                g.close()
+                us = {k: tm[k][0] / tm[k][1] * 1e3 for k in ("force", "neighbor", "binning") if tm[k][1]}
+                rows.append({"block_edge": edge, "half_list": int(half), "layout": layout, "mean_list": ml,
+                             "force_us": us["force"], "build_us": us["neighbor"], "binning_us": us["binning"],
+                             "us_per_step": us["force"] + (us["neighbor"] + us["binning"]) / REBUILD_EVERY})
+        out[wl] = rows
+    return out
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -550,7 +591,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded FCC lattice, SplitMix64 velocities)",
         "config": {"workload": WORKLOADS[args.workload]["name"], "n_atoms": prim["n"],
-                   "neighbor_list": "full", "max_neighbors": 128},
+                   "neighbor_list": "half inside blocks" if prim["schedule"]["half_list"] else "full",
+                   "max_neighbors": 128},
         "roofline": prim["roofline"],
         "kernel_avg_ms": prim["kernel_ms"],
         "build_rooflines": prim["build_rooflines"],
@@ -577,6 +619,10 @@ def main():
         print("# secondary spring-dashpot: " + ", ".join(f"{k} {v['value']:.4g} atom-steps/s" for k, v in sd.items()),
               file=sys.stderr, flush=True)
         out["secondary"]["spring_dashpot"] = sd
+        out["secondary"]["schedule_axes"] = run_axes()
+        print("# secondary schedule axes: " + "; ".join(
+            f"{wl} E{r['block_edge']} {'half' if r['half_list'] else 'full'} {r['layout']} {r['us_per_step']:.1f} us"
+            for wl, rows in out["secondary"]["schedule_axes"].items() for r in rows), file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_steps, args.cpu_single_steps)
     print(json.dumps(out), flush=True)
