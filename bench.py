@@ -81,7 +81,11 @@ def _warm_and_tune(g, warmup: int, schedule=None) -> int:
     in the timed steps, and every wavefront runs to the longest list among
     its atoms, which changes which schedule is fastest."""
     if schedule:  # fixed schedule, e.g. for profiling runs
-        g.set_schedule(**schedule)
+        sched = dict(schedule)
+        half, layout = sched.pop("half_list", 0), sched.pop("layout", 0)
+        g.set_half_list(bool(half))  # (resets threads and capacity: first)
+        g.set_schedule(**sched)
+        g.set_layout(layout)
         g.integrate(warmup)
         return 0
     g.integrate(REBUILD_EVERY)
@@ -543,7 +547,8 @@ def main():
     ap.add_argument("--cpu-single-steps", type=int, default=100, help="oracle steps on one thread")
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule for the primary workload: block edge, workgroups per block, lanes per "
-                         "atom, force threads[, build threads[, build lanes]], e.g. 3,1,1,640 (default: autotune)")
+                         "atom, force threads[, build threads[, build lanes[, half lists (0/1)[, position layout "
+                         "(0 SoA, 1 AoS, 2 AoSoA)]]]], e.g. 3,1,1,640 (default: autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the run, copy a 1 GiB buffer 3 times with torch: a kernel of known traffic "
                          "(1 GiB read + 1 GiB written per launch) to calibrate FETCH_SIZE / WRITE_SIZE counters")
@@ -569,10 +574,11 @@ def main():
     sched = None
     if args.schedule:
         v_ = [int(v) for v in args.schedule.split(",")]
-        if len(v_) not in (4, 5, 6):
-            ap.error("--schedule takes 4 to 6 comma-separated integers")
+        if len(v_) not in (4, 5, 6, 7, 8):
+            ap.error("--schedule takes 4 to 8 comma-separated integers")
         sched = dict(block_edge=v_[0], block_parts=v_[1], lanes_per_atom=v_[2], threads=v_[3],
-                     build_threads=v_[4] if len(v_) >= 5 else 0, build_lanes=v_[5] if len(v_) == 6 else 0)
+                     build_threads=v_[4] if len(v_) >= 5 else 0, build_lanes=v_[5] if len(v_) >= 6 else 0,
+                     half_list=v_[6] if len(v_) >= 7 else 0, layout=v_[7] if len(v_) >= 8 else 0)
     prim = run_gpu(args.workload, steps, args.warmup, sched)
     print(f"# primary {args.workload}: {prim['value']:.4g} atom-steps/s, {prim['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)
