@@ -233,7 +233,7 @@ tmd_status rebuild(tmd_system *s, hipStream_t st) {
     {
         Timed t(s, TMD_T_BINNING, st);
         e = launch_bin(s->d, s->b, s->cur, s->counts_clear, st);
-        s->counts_clear = e == hipSuccess && int64_t(s->d.ncs) * kSub <= kScanOne;
+        s->counts_clear = e == hipSuccess;  // either scan clears the counts
     }
     if (e != hipSuccess)
         return hip_fail(s, e, "binning");

@@ -582,32 +582,38 @@ __global__ __launch_bounds__(kAtomThreads) void k_bin_count(Dims d, const Box *_
               sz = sub_coord(pz, B.hside, B.nc);
     const int c = cell_slot(B, sx >> 1, sy >> 1, sz >> 1) * kSub + ((sz & 1) * 2 + (sy & 1)) * 2 + (sx & 1);
     cell_of[i] = c;  // bin slot: cell slot and subcell
-    // One atomic per distinct cell of the wavefront (atoms arrive nearly
-    // cell-sorted, so a wavefront spans a few cells): the first remaining
-    // lane's cell is counted for every lane that shares it, and those lanes
-    // take consecutive slots in lane order.  (The slot order within a cell is
-    // arbitrary; the later rank by original id makes it deterministic.)
+    // One atomic per distinct bin of the wavefront (atoms arrive nearly
+    // bin-sorted, so a wavefront spans a few dozen subcells): a first pass
+    // over the wave's distinct bins (no memory traffic) gives each lane its
+    // bin's leader, lane count and its rank among them; then every leader
+    // issues its atomic at once, so the wavefront waits for one round trip
+    // instead of one per bin, and each lane takes slot base + rank.  (The
+    // slot order within a bin is arbitrary; the later rank by original id
+    // makes it deterministic.)
     const int lane = threadIdx.x & 63;
     uint64_t todo = __ballot(1);
-    int s = 0;
+    int rank = 0, cnt = 0, leader = lane;
     while (todo) {
-        const int leader = __builtin_ctzll(todo);
-        const int c0 = __shfl(c, leader, 64);
+        const int first = __builtin_ctzll(todo);
+        const int c0 = __shfl(c, first, 64);
         const uint64_t m = __ballot(c == c0);
-        int base = 0;
-        if (lane == leader)
-            base = atomicAdd(&cell_count[c0], __popcll(m));
-        base = __shfl(base, leader, 64);
-        if (c == c0)
-            s = base + __popcll(m & ((uint64_t(1) << lane) - 1));
+        if (c == c0) {
+            leader = first;
+            cnt = __popcll(m);
+            rank = __popcll(m & ((uint64_t(1) << lane) - 1));
+        }
         todo &= ~m;
     }
-    slot[i] = s;
+    int base = 0;
+    if (lane == leader)
+        base = atomicAdd(&cell_count[c], cnt);
+    slot[i] = __shfl(base, leader, 64) + rank;
 }
 
-// Exclusive scan, level 1: each workgroup scans a tile of kScanTile counts
-// (four per thread) and records the tile total.
-__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+// Exclusive scan, pass 1: each workgroup scans a tile of kScanTile counts
+// (four per thread), records the tile total and clears the counts for the
+// next binning (so that binning needs no separate fill).
+__global__ __launch_bounds__(256) void k_scan_tiles(int32_t *__restrict__ in, int32_t *__restrict__ out,
                                                     int32_t *__restrict__ sums, int n) {
     __shared__ int32_t sh[256];
     const int t = threadIdx.x;
@@ -618,6 +624,10 @@ __global__ __launch_bounds__(256) void k_scan_tiles(const int32_t *__restrict__ 
         v[q] = (base + q < n) ? in[base + q] : 0;
         tot += v[q];
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (base + q < n)
+            in[base + q] = 0;
     sh[t] = tot;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
@@ -635,36 +645,6 @@ __global__ __launch_bounds__(256) void k_scan_tiles(const int32_t *__restrict__ 
     }
     if (t == 255)
         sums[blockIdx.x] = sh[255];
-}
-
-// Level 2: one workgroup turns the tile totals into exclusive offsets and
-// writes the grand total to out[n].
-__global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nt, int32_t *out, int n) {
-    __shared__ int32_t sh[1024];
-    const int t = threadIdx.x;
-    const int per = (nt + 1023) / 1024;
-    const int b0 = t * per;
-    int tot = 0;
-    for (int q = 0; q < per; ++q)
-        if (b0 + q < nt)
-            tot += sums[b0 + q];
-    sh[t] = tot;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int add = (t >= off) ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
-    }
-    int run = sh[t] - tot;
-    for (int q = 0; q < per; ++q)
-        if (b0 + q < nt) {
-            const int v = sums[b0 + q];
-            sums[b0 + q] = run;
-            run += v;
-        }
-    if (t == 1023)
-        out[n] = sh[1023];
 }
 
 // The whole scan in one workgroup, for up to kScanOne counts: each thread
@@ -724,10 +704,35 @@ __global__ __launch_bounds__(1024) void k_scan_one(int32_t *counts, int32_t *out
         out[n] = run;
 }
 
-__global__ __launch_bounds__(256) void k_scan_add(int32_t *out, const int32_t *__restrict__ sums, int n) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+// Pass 2: each workgroup (256 counts, inside one tile) sums the totals of
+// the tiles before its own and adds that to its offsets; workgroup 0 also
+// writes the grand total to out[n].
+__global__ __launch_bounds__(256) void k_scan_add(int32_t *out, const int32_t *__restrict__ sums, int ntile,
+                                                  int n) {
+    __shared__ int32_t sh[2][4];
+    const int t = threadIdx.x, tile = blockIdx.x * 256 / kScanTile;
+    int before = 0, all = 0;
+    for (int k = t; k < ntile; k += 256) {
+        const int v = sums[k];
+        before += k < tile ? v : 0;
+        all += v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        before += __shfl_xor(before, o, 64);
+        all += __shfl_xor(all, o, 64);
+    }
+    if ((t & 63) == 0) {
+        sh[0][t >> 6] = before;
+        sh[1][t >> 6] = all;
+    }
+    __syncthreads();
+    before = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    const int i = blockIdx.x * 256 + t;
     if (i < n)
-        out[i] += sums[i / kScanTile];
+        out[i] += before;
+    if (blockIdx.x == 0 && t == 0)
+        out[n] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
 }
 
 __global__ __launch_bounds__(kAtomThreads) void k_scatter(int n, const int32_t *__restrict__ cell_of,
@@ -2556,8 +2561,7 @@ hipError_t launch_bin(const Dims &d, Buffers &b, Cursor c, bool counts_clear, hi
     } else {
         const int nt = scan_blocks(nbin);
         k_scan_tiles<<<nt, 256, 0, s>>>(b.cell_count, b.cell_start, b.scan_sums, nbin);
-        k_scan_sums<<<1, 1024, 0, s>>>(b.scan_sums, nt, b.cell_start, nbin);
-        k_scan_add<<<(nbin + 255) / 256, 256, 0, s>>>(b.cell_start, b.scan_sums, nbin);
+        k_scan_add<<<(nbin + 255) / 256, 256, 0, s>>>(b.cell_start, b.scan_sums, nt, nbin);
     }
     k_scatter<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, b.cell_of, b.slot, b.cell_start, b.tmp_idx);
     k_rank_permute<<<atom_blocks(d.nt), kAtomThreads, 0, s>>>(d.nt, d.nbox, b.boxes, b.atom_box, b.tmp_idx, b.cell_of,
