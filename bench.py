@@ -315,6 +315,7 @@ def run_batched(steps: int = 200, warmup: int = 20, n_boxes: int = 512):
     for s in seq:
         s.sync()
         s.close()
+    per_class = _batch_per_class(boxes, steps, warmup)
     return {"workload": f"{n_boxes} LJ boxes, FCC n^3 with n in 4..12 ({total:,} atoms), rho 0.75-0.90, T 0.7-1.5, "
                         "rc 2.5 + skin 0.3, dt 0.005, rebuild 20",
             "value": total * steps / t_batch, "unit": "atom-steps/s", "steps": steps,
@@ -323,7 +324,45 @@ def run_batched(steps: int = 200, warmup: int = 20, n_boxes: int = 512):
             "schedule": sched, "n_blocks": info["n_blocks"], "lds_atoms": info["lds_atoms"],
             "graph_captures_in_warmup": captured, "graph_launches": info["graph_launches"],
             "graph_captures": info["graph_captures"], "mean_list_length": mean_list, "roofline": roof,
-            "build_rooflines": brf, "kernel_avg_ms": {k: (v[0] / max(v[1], 1), v[1]) for k, v in tm.items() if v[1]}}
+            "build_rooflines": brf, "kernel_avg_ms": {k: (v[0] / max(v[1], 1), v[1]) for k, v in tm.items() if v[1]},
+            "per_class": per_class}
+
+
+def _batch_per_class(boxes, steps: int, warmup: int) -> dict:
+    """The same boxes split by cells per axis into one batch per class, each
+    autotuned on its own and run in graph mode, the classes one after another
+    on one stream: the per-box-class schedule against the one schedule of the
+    whole batch."""
+    import torch
+
+    from paper_2009_07400_amd import System
+
+    classes = {}
+    for b in boxes:
+        classes.setdefault(int(np.floor(b.L / 2.8)), []).append(b)
+    systems, rows = [], []
+    for nc, bs in sorted(classes.items()):
+        g = System.batch([b.n for b in bs], [b.L for b in bs], dict(max_neighbors=128))
+        g.set_state(torch.from_numpy(np.concatenate([b.pos() for b in bs])),
+                    torch.from_numpy(np.concatenate([b.vel() for b in bs])))
+        _warm_and_tune(g, warmup)
+        g.set_graphs(True)
+        g.integrate(2 * REBUILD_EVERY + 1)
+        rows.append({"cells_per_axis": nc, "boxes": len(bs), "atoms": sum(b.n for b in bs), "schedule": _schedule(g)})
+        systems.append(g)
+    for g in systems:
+        g.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in systems:
+        g.integrate(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    for g in systems:
+        g.sync()
+        g.close()
+    total = sum(r["atoms"] for r in rows)
+    return {"value": total * steps / t, "ms_per_step": t / steps * 1e3, "classes": rows}
 
 
 def run_adjoint(steps: int = 200, replicas: int = 64):
@@ -617,6 +656,8 @@ def main():
         print(f"# secondary batched: {bat['value']:.4g} atom-steps/s, {bat['speedup_vs_sequential']:.1f}x "
               "sequential", file=sys.stderr, flush=True)
         out["secondary"]["batched"] = bat
+        print(f"# secondary batched per box class: {bat['per_class']['value']:.4g} atom-steps/s "
+              f"({len(bat['per_class']['classes'])} classes)", file=sys.stderr, flush=True)
         adj = run_adjoint()
         print(f"# secondary adjoint: {adj['value']:.4g} atom-steps/s, {adj['adjoint_over_plain_time']:.2f}x plain "
               "time", file=sys.stderr, flush=True)
