@@ -299,24 +299,28 @@ double expected_hood_atoms(const Box &B, int E) {
 // `nbox` descriptors and the Dims fields that follow from them.  Returns
 // false when the cell slots overflow int32.
 bool layout_dims(Box *boxes, int32_t nbox, int E, Dims &d) {
-    int64_t blocks = 0;
+    int64_t blocks = 0, cells = 0;
     double worst = 0.0;
     for (int32_t k = 0; k < nbox; ++k) {
         Box &B = boxes[k];
-        B.edge = E;
-        B.nbx = (B.nc + E - 1) / E;
+        // a box of at most E + 2 (and at most 4) cells per axis is one block:
+        // every block's neighborhood would hold the whole box anyway, so one
+        // workgroup stages it once instead of each of its blocks staging it
+        const int Eb = B.nc <= std::min(E + 2, kWholeBoxCells) ? B.nc : E;
+        B.edge = Eb;
+        B.nbx = (B.nc + Eb - 1) / Eb;
         B.nblocks = B.nbx * B.nbx * B.nbx;
         B.block_off = int32_t(blocks);
-        B.cell_off = int32_t(blocks * E * E * E);
+        B.cell_off = int32_t(cells);
         blocks += B.nblocks;
-        worst = std::max(worst, expected_hood_atoms(B, E));
-        if (blocks * E * E * E * kSub > INT32_MAX / 2)
+        cells += int64_t(B.nblocks) * Eb * Eb * Eb;
+        worst = std::max(worst, expected_hood_atoms(B, Eb));
+        if (cells * kSub > INT32_MAX / 2)
             return false;
     }
     d.edge = E;
-    d.cpb = E * E * E;
     d.nblk = int32_t(blocks);
-    d.ncs = int32_t(blocks * d.cpb);
+    d.ncs = int32_t(cells);
     // Most workgroups per CU (gfx950: 160 KB of LDS per CU) whose share of
     // LDS still stages at least 15% more atoms than the largest mean
     // neighborhood; the capacity then takes that whole share.

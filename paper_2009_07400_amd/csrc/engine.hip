@@ -50,7 +50,7 @@ __device__ __forceinline__ bool block_part(const Dims &d, int &b, int &part) {
 
 // Block coordinate and offset inside the block of cell coordinate c.
 __device__ __forceinline__ void split_edge(int c, int E, int &blk, int &loc) {
-    blk = (E == 2) ? (c >> 1) : (c / 3);
+    blk = (E == 2) ? (c >> 1) : (c / E);
     loc = c - blk * E;
 }
 
@@ -545,18 +545,20 @@ __global__ __launch_bounds__(kAtomThreads) void k_unload_pos(int n, PosL P, cons
 }
 
 // Copy a position buffer (all ntp slots, the sentinel included) into
-// another layout, and put the sentinel into the other buffer in that layout.
-__global__ __launch_bounds__(kAtomThreads) void k_relayout(int ntp, int nt, PosL from, PosL to, PosL other) {
+// another buffer in another layout.
+__global__ __launch_bounds__(kAtomThreads) void k_relayout(int ntp, PosL from, PosL to) {
     const int i = blockIdx.x * kAtomThreads + threadIdx.x;
     if (i >= ntp)
         return;
     double a, b, c;
     from.get(i, a, b, c);
     to.put(i, a, b, c);
-    if (i == nt) {
-        const double nan = __builtin_nan("");
-        other.put(nt, nan, nan, nan);
-    }
+}
+
+// The NaN sentinel atom at slot nt of a position buffer.
+__global__ void k_put_sentinel(int nt, PosL p) {
+    const double nan = __builtin_nan("");
+    p.put(nt, nan, nan, nan);
 }
 
 // ------------------------------------------------------------------ binning
@@ -2541,8 +2543,11 @@ hipError_t launch_unload_pos(const Dims &d, const Buffers &b, const Pos &p, cons
 hipError_t launch_relayout(const Dims &d, Buffers &b, Cursor c, int layout, hipStream_t s) {
     Dims to = d;
     to.layout = layout;
-    k_relayout<<<(d.ntp + kAtomThreads - 1) / kAtomThreads, kAtomThreads, 0, s>>>(
-        d.ntp, d.nt, pos_layout(d, b.pos(c.x)), pos_layout(to, b.pos(1 - c.x)), pos_layout(to, b.pos(c.x)));
+    k_relayout<<<(d.ntp + kAtomThreads - 1) / kAtomThreads, kAtomThreads, 0, s>>>(d.ntp, pos_layout(d, b.pos(c.x)),
+                                                                                pos_layout(to, b.pos(1 - c.x)));
+    // the old buffer's sentinel in the new layout, once the copy has read
+    // it (its new place may hold another atom's coordinate in the old one)
+    k_put_sentinel<<<1, 1, 0, s>>>(d.nt, pos_layout(to, b.pos(c.x)));
     return hipGetLastError();
 }
 

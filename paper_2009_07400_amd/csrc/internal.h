@@ -11,7 +11,8 @@ constexpr int kScanTile = 1024;    // elements per workgroup in the cell-count s
 constexpr int kScanOne = 32768;    // bin slots up to which one workgroup scans (and clears) the counts
 constexpr int kPartialStride = 4;  // doubles per block partial: U, W, KE, pad
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, each with its own L2
-constexpr int kMaxEdge = 3;        // cells per block edge: 2 or 3
+constexpr int kMaxEdge = 3;        // cells per block edge: 2 or 3 (a whole small box: up to kWholeBoxCells)
+constexpr int kWholeBoxCells = 4;  // boxes of at most this many (and E + 2) cells per axis are one block
 constexpr int kMaxHood = 125;      // cells in a block neighborhood (at most edge + 2 per axis)
 constexpr int kMaxThreads = 1024;  // threads per block workgroup (upper bound)
 constexpr int kAtomThreads = 256;  // threads per workgroup of per-atom kernels
@@ -31,13 +32,15 @@ constexpr int kErrLdsLayout = 8; // the force kernel's dynamic LDS does not star
 
 // One periodic cubic box.  Cells are numbered block-major: a block is E x E x
 // E cells (E = 2 or 3; thinner at the high faces when E does not divide the
-// cell count), each block owns E^3 consecutive cell slots, so the atoms of a
-// block and of each of its cells are contiguous after binning.
+// cell count; a box of at most min(E + 2, kWholeBoxCells) cells per axis is
+// one block of all its cells), each block owns edge^3 consecutive cell
+// slots, so the atoms of a block and of each of its cells are contiguous
+// after binning.
 struct Box {
     int32_t atom_off, n;     // atoms [atom_off, atom_off + n) of the concatenated arrays
     int32_t cell_off, nc;    // first cell slot; cells per axis
     int32_t nbx, block_off;  // blocks per axis (ceil(nc / E)); first block
-    int32_t nblocks, edge;   // blocks of this box; E
+    int32_t nblocks, edge;   // blocks of this box; its block edge: E, or nc when the box is one block
     double L, halfL, side;   // box, half box, cell side L / nc
     double hside;            // subcell side: side / 2
     double halfL2;           // (L/2)^2
@@ -67,9 +70,8 @@ struct Dims {
     int32_t ntp;      // padded stride of the neighbor-major list
     int32_t nbox;     // boxes
     int32_t nblk;     // blocks in all boxes
-    int32_t ncs;      // cell slots in all boxes (E^3 per block); kSub bin slots each
+    int32_t ncs;      // cell slots in all boxes (Box.edge^3 per block); kSub bin slots each
     int32_t edge;     // E, cells per block edge
-    int32_t cpb;      // E^3, cell slots per block
     int32_t maxnb;    // list capacity per atom
     int32_t cap;      // atoms a block neighborhood may stage in LDS
     int32_t threads;  // threads per force workgroup (64..kMaxThreads, multiple of 64)

@@ -135,8 +135,8 @@ def test_batch_create_and_validation():
     try:
         info = abi.tmd_get_info(h)
         assert info["n_boxes"] == 3 and info["n_atoms"] == 256 + 500 + 6912
-        # 2 cells per axis -> 1 block; 3 -> 2^3 blocks (the last one cell thick); 7 -> 4^3 blocks
-        assert info["n_blocks"] == 1 + 8 + 64
+        # 2 and 3 cells per axis (<= E + 2): one block of the whole box; 7 -> 4^3 blocks
+        assert info["n_blocks"] == 1 + 1 + 64
         assert info["n_cells"] == 8 + 27 + 343
         assert info["block_threads"] % 64 == 0 and 64 <= info["block_threads"] <= 1024
         assert info["lds_atoms"] % 64 == 0 and 64 <= info["lds_atoms"] <= 4096

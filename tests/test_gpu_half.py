@@ -60,8 +60,14 @@ CASES = {
 }
 
 
+def _edge(nc, edge):
+    """A box of at most min(E + 2, 4) cells per axis is one block."""
+    return nc if nc <= min(edge + 2, 4) else edge
+
+
 def _blocks(pos, L, edge):
     nc = int(np.floor(L / RL))
+    edge = _edge(nc, edge)
     side = L / nc
     c = np.clip(np.floor(pos / side), 0, nc - 1).astype(np.int64)
     b = c // edge
@@ -74,6 +80,7 @@ def _plain_blocks(L, edge):
     along every axis, e the block's own cells there (thinner at the high
     faces) - the only ones that may hold half lists."""
     nc = int(np.floor(L / RL))
+    edge = _edge(nc, edge)
     nb = (nc + edge - 1) // edge
     ok = [nc >= min(edge, nc - edge * b) + 2 for b in range(nb)]
     return {(bz * nb + by) * nb + bx for bz in range(nb) for by in range(nb) for bx in range(nb)
@@ -142,7 +149,7 @@ def test_half_lists_and_forces_match_oracle(case, sched):
     g.build_neighbors()
     c_o, n_o, frac = _check_half_lists(g, pos, L)
     nc = int(np.floor(L / RL))
-    if nc >= g.info()["block_edge"] + 2 and not sched.get("lds_atoms"):
+    if nc > min(g.info()["block_edge"] + 2, 4) and not sched.get("lds_atoms"):
         # at edge 2 nearly every block fits its neighborhood and reaction
         # sums in LDS; at edge 3 in a box of a few large cells some
         # neighborhoods exceed the staging capacity
