@@ -1,27 +1,33 @@
-// HIP kernels for gfx950 (MI355X): cell binning, full neighbor-list build,
-// Lennard-Jones force sum fused with the velocity-Verlet kicks and drift,
-// deterministic per-box reductions, state load/unload and list export, for
-// one or many independent periodic boxes.
+// HIP kernels for gfx950 (MI355X): cell binning, neighbor-list build (full
+// lists, or half lists inside blocks), the Lennard-Jones and Spring-Dashpot
+// force sums fused with the velocity-Verlet kicks and drift, the adjoint's
+// Hessian-vector product, deterministic per-box reductions, state load and
+// unload, position layout conversion and list export, for one or many
+// independent periodic boxes.
 //
 // Method (tinyMD, arXiv 2009.07400): LJ 12-6 force, Sec. 3.2 Eq. 2 and the
-// compute_potential example of Sec. 4.2; Verlet lists built from cell lists
-// at cutoff + skin, Sec. 3.2 and Fig. 1; neighbor-major list layout for GPUs,
-// Sec. 4.2; velocity Verlet of Newton's law (Sec. 3.2, Eq. 1) with the list
-// rebuilt every `rebuild_every` steps (Sec. 6).
+// compute_potential example of Sec. 4.2; Spring-Dashpot contact force, Sec.
+// 3.2 Eq. 3; Verlet lists built from cell lists at cutoff + skin, Sec. 3.2
+// and Fig. 1 (half lists and the subtracted partner force, Sec. 3.2 and the
+// half_nb variant of Sec. 4.2); the particle layouts of Sec. 4.2; velocity
+// Verlet of Newton's law (Sec. 3.2, Eq. 1) with the list rebuilt every
+// `rebuild_every` steps (Sec. 6).
 //
 // Work decomposition.  Cells have side >= cutoff + skin.  Each box is cut
-// into blocks of 2x2x2 cells and atoms are stored block-major, so the atoms
-// of a block, and of each of its cells, are contiguous.  One workgroup owns
-// one block: it copies the positions of the block's neighborhood (the 4x4x4
-// cells around it, fewer in small boxes) into LDS with coalesced loads, and
-// its lanes - one per atom - gather neighbor positions from LDS instead of
-// from the L2.  The list stores LDS slot numbers for such blocks; a block
-// whose neighborhood exceeds the LDS capacity gathers from global memory and
-// its list stores global atom indices.
+// into blocks of E x E x E cells (E = 2 or 3; a small box is one block) and
+// atoms are stored block-major, so the atoms of a block, and of each of its
+// cells, are contiguous.  One workgroup owns one block: it copies the
+// positions of the block's neighborhood (the (E+2)^3 cells around it, fewer
+// in small boxes) into LDS, and its lanes - one to four per atom - gather
+// neighbor positions from LDS instead of from the L2.  The list stores LDS
+// slot numbers (16 bits) for such blocks; a block whose neighborhood exceeds
+// the LDS capacity gathers from global memory and its list stores global
+// atom indices (32 bits).
 //
-// Layout in HBM: positions, velocities and forces are structure-of-arrays
-// FP64; the list is int32, row k holding the k-th neighbor of every atom
-// (nbr[k * ntp + i]), so a wavefront reads one contiguous 256-byte row.
+// Layout in HBM: velocities and forces are structure-of-arrays FP64,
+// positions SoA, AoS or AoSoA (PosL); the list is tiled neighbor-major (64
+// atoms per tile, rows of 16 bytes per atom), so a wavefront reads one
+// contiguous 1 KB row per load.
 #include <math.h>
 
 #include "device.h"
