@@ -89,7 +89,10 @@ def _warm_and_tune(g, warmup: int, schedule=None) -> int:
         g.integrate(warmup)
         return 0
     g.integrate(REBUILD_EVERY)
-    g.autotune(repeats=5)
+    # 20 launches per candidate: at 131k atoms several schedules lie within
+    # 2% of each other, and five launches ranked them differently from run
+    # to run
+    g.autotune(repeats=20)
     g.integrate(warmup)
     return REBUILD_EVERY
 
