@@ -1340,12 +1340,18 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
         double *t = a.traj + size_t(k) * 3 * np;
         return Pos{t, t + np, t + 2 * np};
     };
-    // Each interval starts from its checkpoint, reloaded and binned as the
-    // backward pass will bin it (the same list and atom order), and runs the
+    // Each interval starts from its checkpoint, binned as the backward pass
+    // will bin it (the same list and atom order), and runs the
     // velocity-Verlet steps of tmd_integrate with explicit output buffers:
     // x_{k+1} of every step goes to store slot k + 1, in the interval's
     // sorted order.  The interval's last step then finishes as tmd_integrate
-    // finishes it (rebuild at a rebuild step, force and closing kick).
+    // finishes it (rebuild at a rebuild step, force and closing kick).  The
+    // first interval reloads its checkpoint and bins it; every later one
+    // starts where the previous one ended, which already is that state:
+    // binning orders atoms by cell and original id whatever their order
+    // before, and wraps positions into the box (wrapping twice changes
+    // nothing), so a reload would give the same positions, order, list and
+    // forces bit for bit.
     for (int32_t m = 0; m < nseg && e == hipSuccess; ++m) {
         const int32_t k_lo = m * R, len = std::min(R, n_steps - k_lo);
         double *c = a.ckpt + size_t(m) * 6 * nt;
@@ -1353,16 +1359,18 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
         double *const vo[3] = {c + 3 * nt, c + 4 * nt, c + 5 * nt};
         if ((st = tmd_get_state(s, po, vo, nullptr, stream)) != TMD_OK)
             return st;
-        const double *const pi[3] = {po[0], po[1], po[2]};
-        const double *const vi[3] = {vo[0], vo[1], vo[2]};
-        e = launch_load_state(s->d, pi, vi, b, Cursor{}, hs);
-        s->cur = Cursor{};
-        if (e == hipSuccess && (st = rebuild(s, hs)) != TMD_OK)
-            return st;
+        if (m == 0) {
+            const double *const pi[3] = {po[0], po[1], po[2]};
+            const double *const vi[3] = {vo[0], vo[1], vo[2]};
+            e = launch_load_state(s->d, pi, vi, b, Cursor{}, hs);
+            s->cur = Cursor{};
+            if (e == hipSuccess && (st = rebuild(s, hs)) != TMD_OK)
+                return st;
+        }
         const int o = s->cur.v;
         const Pos x0 = b.pos(s->cur.x);
         auto traj = [&](int32_t j) { return j == 0 ? x0 : slot(k_lo + j); };
-        if (e == hipSuccess)
+        if (e == hipSuccess && m == 0)
             e = launch_force_at(s->d, b, x0, x0, o, 0, false, hs);
         if (e == hipSuccess)
             e = launch_drift_at(s->d, b, x0, traj(1), o, hs);
