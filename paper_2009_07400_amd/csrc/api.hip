@@ -1428,6 +1428,10 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
     carve_adj(s->dmax, R, T, static_cast<char *>(ws), &a);
     Buffers &b = s->b;
     hipError_t e = launch_fill_f64(a.acc, 0.0, 2 * s->d.nbox, hs);
+    // every reverse step adds its blocks' parameter terms to their partials;
+    // one reduction over each box's blocks follows the sweep
+    if (e == hipSuccess)
+        e = launch_fill_f64(a.partials, 0.0, int64_t(s->d.nblk) * kMaxParts * kPartialStride, hs);
     double *const lo_x[3] = {a.lo, a.lo + nt, a.lo + 2 * nt};
     double *const lo_v[3] = {a.lo + 3 * nt, a.lo + 4 * nt, a.lo + 5 * nt};
     Pos wa = a.wa, wb = a.wb;
@@ -1436,8 +1440,6 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
             Timed t(s, TMD_T_ADJOINT, hs);
             e = launch_hvp(s->d, b, x, wa, a.lx, wb, mult, drift_adj, a.partials, hs);
         }
-        if (e == hipSuccess)
-            e = launch_grad_reduce(s->d, b, a.partials, mult, a.acc, hs);
         if (drift_adj)
             std::swap(wa, wb);
     };
@@ -1488,6 +1490,8 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
                 e = launch_unload(s->d, wa.x, wa.y, wa.z, b.orig[o], grad_v0, hs);
         }
     }
+    if (e == hipSuccess)
+        e = launch_grad_reduce(s->d, b, a.partials, 1.0, a.acc, hs);
     if (e == hipSuccess && (grad_eps || grad_sigma))
         e = launch_split_pairs(a.acc, s->d.nbox, grad_eps, grad_sigma, hs);
     // leave the system in the recorded final state

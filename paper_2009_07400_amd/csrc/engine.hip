@@ -2092,8 +2092,9 @@ __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0
 // For w = lam_v (one lane per atom, one workgroup per block):
 //   (J w)_i = sum_{j in list(i), s < rc^2} [ f(s) (w_i - w_j) + 2 f'(s) ((w_i - w_j) . d_ij) d_ij ]
 // (the terms of hvp_pair); lam_x_i += c (J w)_i, c = mult * dt / (2 m).  The
-// workgroup's partial sums of w_i . dF_i/deps and w_i . dF_i/dsigma go to
-// `partials`.  With drift_adj the adjoint of the drift before this force
+// workgroup adds mult times its partial sums of w_i . dF_i/deps and
+// w_i . dF_i/dsigma to its slot of `partials` (which the reverse sweep
+// clears first and reduces over each box's blocks once, at its end).  With drift_adj the adjoint of the drift before this force
 // evaluation follows: wout_i = w_i + dt lam_x_i.  The neighborhood is staged
 // with w (48 bytes per slot).  L lanes per atom split its list as the force
 // kernel's lanes do (groups of eight entries dealt in turn, on the 32-bit
@@ -2182,8 +2183,9 @@ __global__ __launch_bounds__(kHvpThreads) void k_hvp(Dims d, const Box *__restri
     }
     block_sum3(pe, ps, unused);
     if (threadIdx.x == 0) {
-        partials[(b * d.parts + part) * kPartialStride + 0] = pe;
-        partials[(b * d.parts + part) * kPartialStride + 1] = ps;
+        double *q = partials + (b * d.parts + part) * kPartialStride;
+        q[0] += mult * pe;
+        q[1] += mult * ps;
     }
 }
 
@@ -2313,7 +2315,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_force_sd(Dims d, const Box *__r
 }
 
 // acc[2 box + q] += mult * h * (sum over the box's blocks of partial q), one
-// wavefront per box, fixed order.
+// wavefront per box, fixed order (the reverse sweep's partials hold the sums
+// over all of its steps: it calls this once, with mult 1).
 __global__ __launch_bounds__(64) void k_grad_reduce(const Box *__restrict__ boxes,
                                                     const double *__restrict__ partials, int parts, double mult,
                                                     double *acc) {
