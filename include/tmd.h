@@ -338,7 +338,9 @@ tmd_status tmd_set_lj_params(tmd_system *sys, const double *epsilon, const doubl
  * Hessian-vector product, and each drift adds lam_v += dt lam_x. */
 
 /* Bytes of adjoint workspace for an n_steps run: (x, v) checkpoints at each
- * rebuild, the positions of every step (24 bytes per atom and step),
+ * rebuild, the positions of every step (24 bytes per atom and step), each
+ * rebuild interval's neighbor list with its atom order and tables (about
+ * 40 + 16 * ceil(max_neighbors / 4 + 1) bytes per atom and interval),
  * cotangents. */
 tmd_status tmd_adjoint_workspace_size(const tmd_system *sys, int32_t n_steps, size_t *bytes);
 
@@ -356,10 +358,10 @@ tmd_status tmd_adjoint_forward(tmd_system *sys, int32_t n_steps, void *ws, size_
  * grad_x0[3] = dL/dx_0, grad_v0[3] = dL/dv_0 (nullable), and per box
  * grad_eps[n_boxes], grad_sigma[n_boxes] (device, nullable).  Needs the run
  * recorded by tmd_adjoint_forward() in the same workspace with no
- * state-changing call in between (TMD_ESTATE otherwise).  Rebuilds each
- * interval's list from its checkpoint (the list and atom order of the
- * recorded run) and takes the positions from the store, and leaves the
- * system in the run's final state. */
+ * state-changing call in between (TMD_ESTATE otherwise).  Takes each
+ * interval's list, atom order and positions from the workspace (as the
+ * recorded run built them), and leaves the system in the run's final
+ * state. */
 tmd_status tmd_adjoint_backward(tmd_system *sys, void *ws, size_t bytes, const double *const lam_x[3],
                                 const double *const lam_v[3], double *const grad_x0[3], double *const grad_v0[3],
                                 double *grad_eps, double *grad_sigma, tmd_stream stream);

@@ -495,13 +495,48 @@ tmd_status create_impl(int32_t nbox, const int64_t *n_atoms, const double *lengt
     return TMD_OK;
 }
 
+// One rebuild interval's list as the forward pass built it, kept for the
+// reverse sweep, which then neither reloads nor rebins the interval's
+// checkpoint: the interval's first positions (sorted order, with the NaN
+// sentinel at slot nt), its atom order, and the list with its counts and
+// neighborhood tables.
+struct AdjList {
+    Pos x;
+    int32_t *orig, *cnt, *nbr, *hood;
+};
+
+// Carve one AdjList from base (sizes for dims d); with base == nullptr only
+// the size is computed.
+size_t carve_adj_list(const Dims &d, char *base, AdjList *out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    const size_t np = size_t(d.ntp);
+    AdjList l{};
+    l.x.x = (double *)take(np * 8);
+    l.x.y = (double *)take(np * 8);
+    l.x.z = (double *)take(np * 8);
+    l.orig = (int32_t *)take(np * 4);
+    l.cnt = (int32_t *)take(np * 4);
+    l.nbr = (int32_t *)take(np * size_t(d.nchunk) * 4 * 4);
+    l.hood = (int32_t *)take(size_t(d.nblk) * kHoodWords * 4);
+    if (out)
+        *out = l;
+    return off;
+}
+
 // Adjoint workspace: checkpoints of (x, v) in original order at every
 // rebuild step of the recorded run plus its final state, the positions of
-// every step in the sorted order of its rebuild interval, the cotangents and
-// the parameter gradient accumulators.
+// every step in the sorted order of its rebuild interval, each interval's
+// list (AdjList), the cotangents and the parameter gradient accumulators.
 struct AdjBuf {
     double *ckpt;   // [(nseg + 1) * 6 * nt]
     double *traj;   // [(nsteps + 1) * 3 * ntp]: slot k holds x_k (slot 0 unused)
+    char *lists;    // nseg AdjLists of list_bytes each
+    size_t list_bytes;
     Pos lx, wa, wb; // sorted order, ntp each
     double *lo;     // [6 * nt] cotangents in original order
     double *partials;
@@ -520,6 +555,8 @@ size_t carve_adj(const Dims &d, int32_t R, int32_t nsteps, char *base, AdjBuf *o
     AdjBuf a{};
     a.ckpt = (double *)take(size_t(nseg + 1) * 6 * nt * 8);
     a.traj = (double *)take(size_t(nsteps + 1) * 3 * np * 8);
+    a.list_bytes = carve_adj_list(d, nullptr, nullptr);
+    a.lists = take(size_t(nseg) * a.list_bytes);
     Pos *ps[3] = {&a.lx, &a.wa, &a.wb};
     for (Pos *p : ps) {
         p->x = (double *)take(np * 8);
@@ -1310,6 +1347,30 @@ tmd_status tmd_adjoint_workspace_size(const tmd_system *s, int32_t n_steps, size
     return TMD_OK;
 }
 
+// The list of interval m (the system's current list, atom order and
+// positions) into its AdjList.
+static hipError_t save_adj_list(tmd_system *s, const AdjBuf &a, int32_t m, hipStream_t hs) {
+    AdjList l{};
+    carve_adj_list(s->dmax, a.lists + size_t(m) * a.list_bytes, &l);
+    const Dims &d = s->d;
+    const Buffers &b = s->b;
+    const size_t np = size_t(d.ntp);
+    const double *src[3] = {b.x[s->cur.x], b.y[s->cur.x], b.z[s->cur.x]};
+    double *dst[3] = {l.x.x, l.x.y, l.x.z};
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < 3 && e == hipSuccess; ++q)
+        e = hipMemcpyAsync(dst[q], src[q], np * 8, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(l.orig, b.orig[s->cur.o], size_t(d.nt) * 4, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(l.cnt, b.nbr_count, size_t(d.nt) * 4, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(l.nbr, b.nbr, np * size_t(d.nchunk) * 16, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(l.hood, b.hood_tab, size_t(d.nblk) * kHoodWords * 4, hipMemcpyDeviceToDevice, hs);
+    return e;
+}
+
 tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t bytes, tmd_stream stream) {
     tmd_status st = check_ready(s, true);
     if (st != TMD_OK)
@@ -1370,6 +1431,8 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
         const int o = s->cur.v;
         const Pos x0 = b.pos(s->cur.x);
         auto traj = [&](int32_t j) { return j == 0 ? x0 : slot(k_lo + j); };
+        if (e == hipSuccess)
+            e = save_adj_list(s, a, m, hs);
         if (e == hipSuccess && m == 0)
             e = launch_force_at(s->d, b, x0, x0, o, 0, false, hs);
         if (e == hipSuccess)
@@ -1435,10 +1498,10 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
     double *const lo_x[3] = {a.lo, a.lo + nt, a.lo + 2 * nt};
     double *const lo_v[3] = {a.lo + 3 * nt, a.lo + 4 * nt, a.lo + 5 * nt};
     Pos wa = a.wa, wb = a.wb;
-    auto hvp = [&](const Pos &x, double mult, bool drift_adj) {
+    auto hvp = [&](Buffers &bl, const Pos &x, double mult, bool drift_adj) {
         if (e == hipSuccess) {
             Timed t(s, TMD_T_ADJOINT, hs);
-            e = launch_hvp(s->d, b, x, wa, a.lx, wb, mult, drift_adj, a.partials, hs);
+            e = launch_hvp(s->d, bl, x, wa, a.lx, wb, mult, drift_adj, a.partials, hs);
         }
         if (drift_adj)
             std::swap(wa, wb);
@@ -1449,45 +1512,43 @@ tmd_status tmd_adjoint_backward(tmd_system *s, void *ws, size_t bytes, const dou
     if (e == hipSuccess)
         e = launch_gather(s->d, (lam_v && lam_v[0] && lam_v[1] && lam_v[2]) ? lam_v : nullptr, b.orig[s->cur.o], wa,
                           hs);
-    hvp(b.pos(s->cur.x), 1.0, true);
+    hvp(b, b.pos(s->cur.x), 1.0, true);
     if (e == hipSuccess)
         e = launch_unload(s->d, a.lx.x, a.lx.y, a.lx.z, b.orig[s->cur.o], lo_x, hs);
     if (e == hipSuccess)
         e = launch_unload(s->d, wa.x, wa.y, wa.z, b.orig[s->cur.o], lo_v, hs);
     for (int32_t m = nseg - 1; m >= 0 && e == hipSuccess; --m) {
         const int32_t k_lo = m * R, k_hi = std::min((m + 1) * R, T) - 1;
-        // restore the checkpoint and rebuild the interval's list (and atom
-        // order); its positions are in the store
-        const double *c = a.ckpt + size_t(m) * 6 * nt;
-        const double *const po[3] = {c, c + nt, c + 2 * nt};
-        const double *const vo[3] = {c + 3 * nt, c + 4 * nt, c + 5 * nt};
-        e = launch_load_state(s->d, po, vo, b, Cursor{}, hs);
-        s->cur = Cursor{};
-        if (e == hipSuccess && (st = rebuild(s, hs)) != TMD_OK)
-            return st;
+        // the interval's list, atom order and first positions, as the
+        // forward pass built them; its later positions are in the store
+        AdjList l{};
+        carve_adj_list(s->dmax, a.lists + size_t(m) * a.list_bytes, &l);
+        Buffers bl = b;
+        bl.nbr = l.nbr;
+        bl.nbr_count = l.cnt;
+        bl.hood_tab = l.hood;
         const size_t np = size_t(s->d.ntp);
         auto traj = [&](int32_t j) {
             if (j == 0)
-                return b.pos(s->cur.x);
+                return l.x;
             double *t = a.traj + size_t(k_lo + j) * 3 * np;
             return Pos{t, t + np, t + 2 * np};
         };
-        const int o = s->cur.o;
         if (e == hipSuccess)
-            e = launch_gather(s->d, lo_x, b.orig[o], a.lx, hs);
+            e = launch_gather(s->d, lo_x, l.orig, a.lx, hs);
         if (e == hipSuccess)
-            e = launch_gather(s->d, lo_v, b.orig[o], wa, hs);
+            e = launch_gather(s->d, lo_v, l.orig, wa, hs);
         for (int32_t k = k_hi; k >= k_lo; --k)
-            hvp(traj(k - k_lo), k == 0 ? 1.0 : 2.0, k > 0);
+            hvp(bl, traj(k - k_lo), k == 0 ? 1.0 : 2.0, k > 0);
         double *const *ox = (m == 0) ? grad_x0 : lo_x;
         if (e == hipSuccess)
-            e = launch_unload(s->d, a.lx.x, a.lx.y, a.lx.z, b.orig[o], ox, hs);
+            e = launch_unload(s->d, a.lx.x, a.lx.y, a.lx.z, l.orig, ox, hs);
         if (m > 0) {
             if (e == hipSuccess)
-                e = launch_unload(s->d, wa.x, wa.y, wa.z, b.orig[o], lo_v, hs);
+                e = launch_unload(s->d, wa.x, wa.y, wa.z, l.orig, lo_v, hs);
         } else if (grad_v0 && grad_v0[0] && grad_v0[1] && grad_v0[2]) {
             if (e == hipSuccess)
-                e = launch_unload(s->d, wa.x, wa.y, wa.z, b.orig[o], grad_v0, hs);
+                e = launch_unload(s->d, wa.x, wa.y, wa.z, l.orig, grad_v0, hs);
         }
     }
     if (e == hipSuccess)
