@@ -95,7 +95,9 @@ __device__ __forceinline__ double pair_delta_img(double xi, double yi, double zi
 // j, the image of j nearest to i - provided the box has at least E + 4 cells
 // per axis and atoms move less than a third of cutoff + skin between list
 // builds: then |image - c| <= E a / 2 + (cutoff + skin) + 3 drift < L / 2
-// for cells of side a >= cutoff + skin.
+// for cells of side a >= cutoff + skin.  With E + 3 cells the bound holds
+// for drifts below (3 a / 2 - cutoff - skin) / 3; the pair loops then check
+// each difference (engine.hip, pair_geom).
 __device__ __forceinline__ double nearest_image(double x, double c, double L, double halfL) {
     const double d = x - c;
     return x + ((d > halfL) ? -L : ((d < -halfL) ? L : 0.0));

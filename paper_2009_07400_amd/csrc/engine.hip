@@ -287,9 +287,10 @@ __device__ __forceinline__ PosL pos_of(int lay, int ntp, const double *p) {
 // image nearest to the block's center (nearest_image()), so
 // that for every atom of the block each list partner's copy is its image
 // nearest to that atom and the pair loops take plain differences (no
-// minimum-image test per pair).  `on` needs at least E + 4 cells per axis;
-// the list build stages without it, as its neighbor decisions take the
-// minimum image of the raw difference.
+// minimum-image test per pair).  `on` needs at least E + 3 cells per axis;
+// below E + 4 (`check`) the pair loops also test each difference against
+// L/2 (pair_geom).  The list build stages without images, as its neighbor
+// decisions take the minimum image of the raw difference.
 // Half lists (Sec. 3.2: each pair listed once, the partner taking the
 // opposite force; the half_nb variant of Sec. 4.2) inside one block: a pair
 // of two atoms of the block is listed once, by the atom with the lower LDS
@@ -358,13 +359,15 @@ __device__ __forceinline__ int own_slot(const Box &B, int lb, const Hood &h, int
 }
 
 struct HoodImage {
-    bool on;
+    bool on;     // the neighborhood is staged at images near the block
+    bool check;  // ... and a pair may still need its minimum image (pair_geom<2>)
     double cx, cy, cz, L, halfL;
 };
 
 __device__ __forceinline__ HoodImage hood_image(const Box &B, int lb, bool want) {
     HoodImage m;
-    m.on = want && B.nc >= B.edge + 4;
+    m.on = want && B.nc >= B.edge + 3;
+    m.check = B.nc < B.edge + 4;
     const int nbx = B.nbx;
     const int bc[3] = {lb % nbx, (lb / nbx) % nbx, lb / (nbx * nbx)};
     double c[3];
@@ -380,6 +383,32 @@ __device__ __forceinline__ HoodImage hood_image(const Box &B, int lb, bool want)
     m.L = B.L;
     m.halfL = B.halfL;
     return m;
+}
+
+// Pair difference and |d|^2 for the block kernels' pair loops: IMG 0 takes
+// the minimum image per pair (pair_delta_fma); IMG 1 the staged image
+// (pair_delta_img), which is the image nearest to i when the box has at
+// least E + 4 cells per axis; IMG 2 the staged image for boxes of E + 3
+// cells, where it is the nearest one unless the pair's atoms moved more
+// than (3 a / 2 - cutoff - skin) / 3 since the list build.  A wrong image
+// puts the difference at least L/2 from zero along an axis, so such a
+// pair fails |d|^2 < (L/2)^2 and its difference then takes the minimum
+// image along each axis - the value of the other paths up to the rounding
+// of one more subtraction of L.  With the right images all three give the
+// same bits.
+template <int IMG>
+__device__ __forceinline__ double pair_geom(double xi, double yi, double zi, double xj, double yj, double zj,
+                                            const Box &B, double &dx, double &dy, double &dz) {
+    if (IMG == 0)
+        return pair_delta_fma(xi, yi, zi, xj, yj, zj, B.L, B.invL, dx, dy, dz);
+    double s = pair_delta_img(xi, yi, zi, xj, yj, zj, dx, dy, dz);
+    if (IMG == 2 && s >= B.halfL2) {
+        dx = mic(dx, B.L, B.halfL);
+        dy = mic(dy, B.L, B.halfL);
+        dz = mic(dz, B.L, B.halfL);
+        s = fma(dz, dz, fma(dy, dy, dx * dx));
+    }
+    return s;
 }
 
 // Copy the neighborhood's positions into LDS (the global loads are
@@ -1423,23 +1452,21 @@ __device__ __forceinline__ void fetch2(const POS &pos, int j0, int j1, Duo &q) {
 // use fused multiply-adds here: it decides only the cutoff test, whose pairs
 // at s within an ulp of cutoff^2 have a vanishing share (the neighbor sets
 // themselves come from the build's unfused sum).  mf6 and mu6 are -f6 and
-// -u6.  A NaN sentinel entry fails both tests and adds nothing.  IMG: the
-// partner positions come from a neighborhood copy moved to its images near
-// the block (HoodImage), so the difference needs no minimum-image test.
+// -u6.  A NaN sentinel entry fails both tests and adds nothing.  IMG: how
+// the difference gets its periodic image (pair_geom: per pair, or from a
+// neighborhood copy moved to its images near the block).
 // HALF: the entries come from a half list (word: the two 16-bit entries,
 // bit 15 marking a pair inside the block that the partner's list does not
 // hold): such a pair also adds the reaction -f d to the partner's sum in R
 // (LDS, index slot - s_lo), and its energy and virial count twice.
-template <bool THERMO, bool IMG, bool HALF = false>
+template <bool THERMO, int IMG, bool HALF = false>
 __device__ __forceinline__ void eval2(const Duo &q, double xi, double yi, double zi, const Box &B, double mf6,
                                       double mu6, double &ax, double &ay, double &az, double &u, double &w,
                                       unsigned word = 0u, lds_double *R = nullptr, int s_lo = 0) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         double dx, dy, dz;
-        // with IMG the partner positions already are the images nearest to i
-        const double s = IMG ? pair_delta_img(xi, yi, zi, q.x[m], q.y[m], q.z[m], dx, dy, dz)
-                             : pair_delta_fma(xi, yi, zi, q.x[m], q.y[m], q.z[m], B.L, B.invL, dx, dy, dz);
+        const double s = pair_geom<IMG>(xi, yi, zi, q.x[m], q.y[m], q.z[m], B, dx, dy, dz);
         if (s < B.rc2) {
             const double sr2 = recip(s);
             const double q3 = sr2 * sr2 * sr2;
@@ -1491,13 +1518,13 @@ __device__ __forceinline__ void pair_sum(const v4i *__restrict__ chunks, int p, 
         const v4i e1 = __builtin_nontemporal_load(chunks + (2 * g + 1) * 64);
         Duo q;
         fetch2(pos, e0[0], e0[1], q);
-        eval2<THERMO, false>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, 0>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2(pos, e0[2], e0[3], q);
-        eval2<THERMO, false>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, 0>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2(pos, e1[0], e1[1], q);
-        eval2<THERMO, false>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, 0>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         fetch2(pos, e1[2], e1[3], q);
-        eval2<THERMO, false>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
+        eval2<THERMO, 0>(q, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
     }
 }
 
@@ -1540,7 +1567,7 @@ __device__ __forceinline__ void fetch2w(int word, Duo &q) {
 // load them before the count is known.  The only exit
 // is at the end of the body: a loop with several exits loses the exact wait
 // counts at its head.
-template <bool THERMO, bool IMG, bool HALF = false>
+template <bool THERMO, int IMG, bool HALF = false>
 __device__ __forceinline__ void pair_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int p, int L, int c,
                                            double xi, double yi, double zi, const Box &B, double mf6, double mu6,
                                            double &ax, double &ay, double &az, double &u, double &w,
@@ -1744,12 +1771,15 @@ __global__ __launch_bounds__(kMaxThreads) void k_force(Dims d, const Box *__rest
     for (; i < hi; i += T) {
         double ax = 0.0, ay = 0.0, az = 0.0;
         const v4i *chunks = list_chunks(nbr, i, d.nchunk);
-        if (im.on)
-            pair_sum16<THERMO, true, HALF>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w, R,
-                                           s_lo);
+        if (im.on && !im.check)
+            pair_sum16<THERMO, 1, HALF>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w, R,
+                                        s_lo);
+        else if (im.on)
+            pair_sum16<THERMO, 2, HALF>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w, R,
+                                        s_lo);
         else if (fits)
-            pair_sum16<THERMO, false, HALF>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w, R,
-                                            s_lo);
+            pair_sum16<THERMO, 0, HALF>(chunks, r0, r1, p, L, ci, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w, R,
+                                        s_lo);
         else
             pair_sum<THERMO>(chunks, p, L, ci, gpos, xi, yi, zi, B, mf6, mu6, ax, ay, az, u, w);
         // combine the L partial sums of the group (a butterfly: addition
@@ -2004,14 +2034,13 @@ struct HvpConst {
 // with q = sr2^3, f = sr2 q (f12 q - f6), 2 f' = sr2^2 q (g8 - g14 q),
 // df/deps = sr2 q (e12 q - e6), df/dsigma = sr2 q (h12 q - h6).  IMG as in
 // eval2.
-template <bool IMG>
+template <int IMG>
 __device__ __forceinline__ void hvp_pair(double xj, double yj, double zj, double wxj, double wyj, double wzj,
                                          double xi, double yi, double zi, double wxi, double wyi, double wzi,
                                          const Box &B, const HvpConst &k, double &gx, double &gy, double &gz,
                                          double &pe, double &ps) {
     double dx, dy, dz;
-    const double s = IMG ? pair_delta_img(xi, yi, zi, xj, yj, zj, dx, dy, dz)
-                         : pair_delta_fma(xi, yi, zi, xj, yj, zj, B.L, B.invL, dx, dy, dz);
+    const double s = pair_geom<IMG>(xi, yi, zi, xj, yj, zj, B, dx, dy, dz);
     if (s < B.rc2) {
         const double sr2 = recip_exact(s);
         const double q3 = sr2 * sr2 * sr2;
@@ -2034,7 +2063,7 @@ __device__ __forceinline__ void hvp_pair(double xj, double yj, double zj, double
 // hvp terms over a 16-bit list, with pair_sum16's loop discipline and its
 // split of the list over L lanes per atom (lane p walks chunks p, p + L,
 // ...; i0 and i1 are the lane's first two chunks).
-template <bool IMG>
+template <int IMG>
 __device__ __forceinline__ void hvp_sum16(const v4i *__restrict__ chunks, v4i i0, v4i i1, int p, int L, int c,
                                           lds_double *S, double xi, double yi, double zi, double wxi, double wyi,
                                           double wzi, const Box &B, const HvpConst &k, double &gx, double &gy,
@@ -2146,10 +2175,12 @@ __global__ __launch_bounds__(kHvpThreads) void k_hvp(Dims d, const Box *__restri
             // rows p and p + L (at most row 7): every 16-bit list fills them
             const v4i r0 = __builtin_nontemporal_load(chunks + min(p, d.nchunk - 1) * 64);
             const v4i r1 = __builtin_nontemporal_load(chunks + min(p + L, d.nchunk - 1) * 64);
-            if (im.on)
-                hvp_sum16<true>(chunks, r0, r1, p, L, c, S, xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
+            if (im.on && !im.check)
+                hvp_sum16<1>(chunks, r0, r1, p, L, c, S, xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
+            else if (im.on)
+                hvp_sum16<2>(chunks, r0, r1, p, L, c, S, xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
             else
-                hvp_sum16<false>(chunks, r0, r1, p, L, c, S, xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
+                hvp_sum16<0>(chunks, r0, r1, p, L, c, S, xi, yi, zi, wxi, wyi, wzi, B, k, gx, gy, gz, pe, ps);
         } else {
             // groups of eight entries dealt in turn, as on the 16-bit path;
             // past the count the 32-bit list holds sentinels (global slot nt)
@@ -2158,7 +2189,7 @@ __global__ __launch_bounds__(kHvpThreads) void k_hvp(Dims d, const Box *__restri
             for (int g = p; g < ng; g += L)
                 for (int e = 0; e < 8; ++e) {
                     const int j = nbr[nbr_index(i, 8 * g + e, d.nchunk)];
-                    hvp_pair<false>(x.x[j], x.y[j], x.z[j], w.x[j], w.y[j], w.z[j], xi, yi, zi, wxi, wyi, wzi, B, k,
+                    hvp_pair<0>(x.x[j], x.y[j], x.z[j], w.x[j], w.y[j], w.z[j], xi, yi, zi, wxi, wyi, wzi, B, k,
                                     gx, gy, gz, pe, ps);
                 }
         }
@@ -2196,13 +2227,12 @@ __global__ __launch_bounds__(kHvpThreads) void k_hvp(Dims d, const Box *__restri
 // with u = x_ij / r and v_ij = v_i - v_j; with THERMO the elastic energy
 // K (sigma - r)^2 / 2 and x_ij . F_ij = r times the magnitude.  A NaN
 // sentinel entry fails the overlap test.  IMG as in eval2.
-template <bool THERMO, bool IMG>
+template <bool THERMO, int IMG>
 __device__ __forceinline__ void sd_term(double xj, double yj, double zj, double vxj, double vyj, double vzj,
                                         double xi, double yi, double zi, double vxi, double vyi, double vzi,
                                         const Box &B, double &ax, double &ay, double &az, double &u, double &w) {
     double dx, dy, dz;
-    const double s = IMG ? pair_delta_img(xi, yi, zi, xj, yj, zj, dx, dy, dz)
-                         : pair_delta_fma(xi, yi, zi, xj, yj, zj, B.L, B.invL, dx, dy, dz);
+    const double s = pair_geom<IMG>(xi, yi, zi, xj, yj, zj, B, dx, dy, dz);
     if (s < B.sd_sig2) {
         const double r = sqrt(s);
         const double ir = 1.0 / r;
@@ -2260,17 +2290,20 @@ __global__ __launch_bounds__(kMaxThreads) void k_force_sd(Dims d, const Box *__r
         if (fits) {
             for (int k = 0; k < c; ++k) {
                 const lds_double *a = lds_slot6(S, nbr16[nbr_index16(i, k, d.nchunk)]);
-                if (im.on)
-                    sd_term<THERMO, true>(a[0], a[1], a[2], a[3], a[4], a[5], xi, yi, zi, vxi, vyi, vzi, B, ax, ay,
-                                          az, u, w);
+                if (im.on && !im.check)
+                    sd_term<THERMO, 1>(a[0], a[1], a[2], a[3], a[4], a[5], xi, yi, zi, vxi, vyi, vzi, B, ax, ay, az,
+                                       u, w);
+                else if (im.on)
+                    sd_term<THERMO, 2>(a[0], a[1], a[2], a[3], a[4], a[5], xi, yi, zi, vxi, vyi, vzi, B, ax, ay, az,
+                                       u, w);
                 else
-                    sd_term<THERMO, false>(a[0], a[1], a[2], a[3], a[4], a[5], xi, yi, zi, vxi, vyi, vzi, B, ax,
-                                           ay, az, u, w);
+                    sd_term<THERMO, 0>(a[0], a[1], a[2], a[3], a[4], a[5], xi, yi, zi, vxi, vyi, vzi, B, ax, ay, az,
+                                       u, w);
             }
         } else {
             for (int k = 0; k < c; ++k) {
                 const int j = nbr[nbr_index(i, k, d.nchunk)];
-                sd_term<THERMO, false>(x.x[j], x.y[j], x.z[j], v.x[j], v.y[j], v.z[j], xi, yi, zi, vxi, vyi, vzi, B,
+                sd_term<THERMO, 0>(x.x[j], x.y[j], x.z[j], v.x[j], v.y[j], v.z[j], xi, yi, zi, vxi, vyi, vzi, B,
                                        ax, ay, az, u, w);
             }
         }

@@ -268,3 +268,60 @@ def test_full_size_sampled_parity(ncell, jitter, seed):
     if jitter == 0.0:
         assert U / s.n == pytest.approx(-6.773368053252957, rel=1e-12)
         assert W / s.n == pytest.approx(-22.158199254035498, rel=1e-12)
+
+
+def _wrong_staged_images(x0, x, L, counts, nbr, edge):
+    """Listed pairs whose partner, staged at its image nearest to the centre
+    of the atom's block (blocks of `edge` cells, binned at x0), is not the
+    image nearest to the atom: a difference beyond L/2 along some axis."""
+    nc = oracle.cells_per_axis(L, 2.8)
+    a = L / nc
+    cell = np.clip(np.floor(np.mod(x0, L) / a).astype(int), 0, nc - 1)
+    c0 = cell // edge * edge
+    centre = (c0 + 0.5 * np.minimum(edge, nc - c0)) * a
+    def near(y, c):  # the image of y nearest to c
+        d = y - c
+        return y - L * (d > L / 2) + L * (d < -L / 2)
+
+    wrong = 0
+    for i in range(x.shape[0]):
+        js = nbr[i, : counts[i]]
+        d = near(x[i], centre[i]) - near(x[js], centre[i])
+        wrong += int((np.abs(d) > L / 2).any(axis=1).sum())
+    return wrong
+
+
+@pytest.mark.parametrize("edge,n", [(2, 9), (3, 11)])
+def test_checked_images_after_large_drift(edge, n):
+    """Boxes of E + 3 cells per axis stage each neighborhood at the images
+    nearest to its block and test every difference against L/2.  Here the
+    atoms fly up to three sigma (ballistic: a negligible epsilon) on the
+    list of the first step, so some partners' staged images are not the
+    ones nearest to their atom (about 150 pairs): those pairs take the
+    minimum image per pair, and the forces of the kept list match the
+    oracle's."""
+    s = md_system(n, seed=31 + n)
+    rng = np.random.default_rng(n)
+    u = rng.standard_normal((s.n, 3))
+    vel = u / np.linalg.norm(u, axis=1, keepdims=True) * rng.uniform(0.0, 60.0, (s.n, 1))
+    g = System(s.n, s.L, epsilon=1e-30, rebuild_every=1000)
+    assert g.info()["cells_per_axis"] == edge + 3
+    g.set_schedule(block_edge=edge)
+    x0 = s.pos()
+    g.set_state(torch.from_numpy(x0), torch.from_numpy(vel))
+    g.integrate(10)  # the list of step 0 stays: rebuild every 1000 steps
+    g.set_lj_params([1.0], [1.0])
+    F, ev = g.compute_forces()
+    p, _, _ = g.get_state()
+    counts, ids = g.get_neighbors()
+    g.sync()
+    x = p.cpu().numpy()
+    c0, n0, _ = oracle.build_list(x0[:, 0], x0[:, 1], x0[:, 2], s.L, 2.8, maxnb=160)
+    assert np.array_equal(counts.cpu().numpy(), c0)  # still the list of step 0
+    assert _wrong_staged_images(x0, x, s.L, c0, n0, edge) > 0
+    Fo, scale, Uo, Wo = oracle.forces(x[:, 0], x[:, 1], x[:, 2], s.L, c0, n0)
+    err = np.linalg.norm(F.cpu().numpy() - Fo, axis=1)
+    assert (err <= FORCE_TOL * np.maximum(scale, 1e-300)).all(), float((err / np.maximum(scale, 1e-300)).max())
+    U, W = ev.cpu().numpy().reshape(-1)[:2]
+    assert U == pytest.approx(Uo, rel=FORCE_TOL) and W == pytest.approx(Wo, rel=FORCE_TOL)
+    g.close()
