@@ -265,7 +265,9 @@ enum {
  * set, are converted on `stream`.  TMD_EINVAL for another value, and for a
  * layout other than TMD_LAYOUT_SOA with the Spring-Dashpot model; the
  * adjoint (tmd_adjoint_forward) needs TMD_LAYOUT_SOA (TMD_EINVAL
- * otherwise).  The list stays valid. */
+ * otherwise), and a change of layout between tmd_adjoint_forward and
+ * tmd_adjoint_backward makes the backward pass return TMD_ESTATE.  The
+ * list stays valid. */
 tmd_status tmd_set_layout(tmd_system *sys, int32_t layout, tmd_stream stream);
 
 /* Half neighbor lists with Newton's third law (Sec. 3.2: each pair stored

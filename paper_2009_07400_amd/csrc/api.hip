@@ -1105,6 +1105,7 @@ static tmd_status relayout(tmd_system *s, int32_t layout, hipStream_t hs) {
         s->cur.x = 1 - s->cur.x;
     }
     s->d.layout = layout;
+    s->gen++;  // a recorded adjoint run reads the state's positions as SoA
     return TMD_OK;
 }
 

@@ -142,6 +142,13 @@ def test_adjoint_call_order():
     with pytest.raises(TmdError) as e:
         g.adjoint_backward(z)
     assert e.value.status == abi.TMD_ESTATE
+    g.set_state(torch.from_numpy(boxes[0][0].pos()), torch.from_numpy(boxes[0][0].vel()))
+    g.adjoint_forward(10)
+    g.set_layout("aos")  # the recorded run reads the state as SoA positions
+    with pytest.raises(TmdError) as e:
+        g.adjoint_backward(z)
+    assert e.value.status == abi.TMD_ESTATE
+    g.set_layout("soa")
     g.set_state(torch.from_numpy(boxes[0][0].pos()), torch.from_numpy(boxes[0][0].vel()), step=3)
     with pytest.raises(TmdError) as e:  # not at a rebuild step
         g.adjoint_forward(10)
