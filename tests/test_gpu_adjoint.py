@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from images_helper import wrong_staged_images
 from workloads import md_system
 
 pytestmark = pytest.mark.gpu
@@ -129,6 +130,39 @@ def test_adjoint_forward_ends_in_the_integrate_state_bitwise():
         assert torch.equal(pa, pb) and torch.equal(va, vb), steps
         a.close()
         b.close()
+
+
+def test_adjoint_checked_images_after_large_drift():
+    """A box of E + 3 cells per axis (staged images, each difference tested
+    against L/2) with atoms flying up to three sigma on the list of the
+    first step (a negligible epsilon: ballistic; rebuild every 1000 steps),
+    so the last steps see pairs whose staged image is wrong: the gradients,
+    dL/deps above all (dF/deps = F/eps does not vanish with eps), match the
+    oracle's adjoint, which takes every pair's minimum image."""
+    s = md_system(9, seed=40)
+    rng = np.random.default_rng(40)
+    u = rng.standard_normal((s.n, 3))
+    vel = u / np.linalg.norm(u, axis=1, keepdims=True) * rng.uniform(0.0, 60.0, (s.n, 1))
+    x0 = s.pos()
+    steps, eps = 10, 1e-30
+    g = System(s.n, s.L, epsilon=eps, rebuild_every=1000)
+    assert g.info()["cells_per_axis"] == 5
+    g.set_schedule(block_edge=2)
+    g.set_state(torch.from_numpy(x0), torch.from_numpy(vel))
+    lx = rng.standard_normal((s.n, 3))
+    lv = rng.standard_normal((s.n, 3))
+    g.adjoint_forward(steps)
+    gx, gv, ge, gs = g.adjoint_backward(torch.from_numpy(lx), torch.from_numpy(lv))
+    p, _, _ = g.get_state()
+    g.sync()
+    c0, n0, _ = oracle.build_list(x0[:, 0], x0[:, 1], x0[:, 2], s.L, 2.8, maxnb=160)
+    assert wrong_staged_images(x0, p.cpu().numpy(), s.L, c0, n0, 2) > 0
+    ox, ov, oe, os_ = oracle.adjoint(x0, vel, s.L, steps, lx, lv, eps=eps, sigma=1.0, rebuild_every=1000)
+    _close(gx.cpu().numpy(), ox)
+    _close(gv.cpu().numpy(), ov)
+    assert float(ge.reshape(-1)[0]) == pytest.approx(oe, rel=REL)
+    assert float(gs.reshape(-1)[0]) == pytest.approx(os_, rel=REL)
+    g.close()
 
 
 def test_adjoint_call_order():

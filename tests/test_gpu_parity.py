@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from images_helper import wrong_staged_images
 from workloads import SplitMix64, fcc_positions, md_system
 
 pytestmark = pytest.mark.gpu
@@ -270,27 +271,6 @@ def test_full_size_sampled_parity(ncell, jitter, seed):
         assert W / s.n == pytest.approx(-22.158199254035498, rel=1e-12)
 
 
-def _wrong_staged_images(x0, x, L, counts, nbr, edge):
-    """Listed pairs whose partner, staged at its image nearest to the centre
-    of the atom's block (blocks of `edge` cells, binned at x0), is not the
-    image nearest to the atom: a difference beyond L/2 along some axis."""
-    nc = oracle.cells_per_axis(L, 2.8)
-    a = L / nc
-    cell = np.clip(np.floor(np.mod(x0, L) / a).astype(int), 0, nc - 1)
-    c0 = cell // edge * edge
-    centre = (c0 + 0.5 * np.minimum(edge, nc - c0)) * a
-    def near(y, c):  # the image of y nearest to c
-        d = y - c
-        return y - L * (d > L / 2) + L * (d < -L / 2)
-
-    wrong = 0
-    for i in range(x.shape[0]):
-        js = nbr[i, : counts[i]]
-        d = near(x[i], centre[i]) - near(x[js], centre[i])
-        wrong += int((np.abs(d) > L / 2).any(axis=1).sum())
-    return wrong
-
-
 @pytest.mark.parametrize("edge,n", [(2, 9), (3, 11)])
 def test_checked_images_after_large_drift(edge, n):
     """Boxes of E + 3 cells per axis stage each neighborhood at the images
@@ -318,7 +298,7 @@ def test_checked_images_after_large_drift(edge, n):
     x = p.cpu().numpy()
     c0, n0, _ = oracle.build_list(x0[:, 0], x0[:, 1], x0[:, 2], s.L, 2.8, maxnb=160)
     assert np.array_equal(counts.cpu().numpy(), c0)  # still the list of step 0
-    assert _wrong_staged_images(x0, x, s.L, c0, n0, edge) > 0
+    assert wrong_staged_images(x0, x, s.L, c0, n0, edge) > 0
     Fo, scale, Uo, Wo = oracle.forces(x[:, 0], x[:, 1], x[:, 2], s.L, c0, n0)
     err = np.linalg.norm(F.cpu().numpy() - Fo, axis=1)
     assert (err <= FORCE_TOL * np.maximum(scale, 1e-300)).all(), float((err / np.maximum(scale, 1e-300)).max())
