@@ -969,12 +969,16 @@ __device__ __forceinline__ double cand_dist2(double xi, double yi, double zi, do
     return dist2(xi - xj, yi - yj, zi - zj);
 }
 
-// Entry c of the 16-bit list at wp (the next element, or the first element
-// of the next 16-byte row of the tile), if it is within capacity.
-__device__ __forceinline__ void put16(uint16_t *&wp, int &c, int maxnb, int v) {
+// Element of entry k of a 16-bit list relative to the atom's entry 0
+// (nbr_index16(i, k, n) - nbr_index16(i, 0, n): rows of eight entries, 64
+// atoms to a row of the tile), in 32-bit unsigned arithmetic.
+__device__ __forceinline__ unsigned entry16(int k) { return __umul24(unsigned(k) >> 3, 504u) + unsigned(k); }
+
+// Entry c of the 16-bit list of the atom whose entry 0 is at wp, if it is
+// within capacity.
+__device__ __forceinline__ void put16(uint16_t *wp, int &c, int maxnb, int v) {
     if (c < maxnb)
-        *wp = uint16_t(v);
-    wp += ((c & 7) == 7) ? 505 : 1;
+        wp[entry16(c)] = uint16_t(v);
     ++c;
 }
 
@@ -1190,7 +1194,7 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
         return dist2(xi - xj, yi - yj, zi - zj);
     };
     int c = 0;
-    uint16_t *wp = nbr16 + nbr_index16(i, 0, nchunk);
+    uint16_t *const wp = nbr16 + nbr_index16(i, 0, nchunk);
     for (;;) {
         if (BL == 1) {
             const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t), 24u);
@@ -1238,7 +1242,7 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
                 if (mine & (1u << j)) {
                     const int pos = c + __popc(m8 & ((1u << j) - 1u));
                     if (pos < maxnb)
-                        nbr16[nbr_index16(i, pos, nchunk)] = vr[r];
+                        wp[entry16(pos)] = vr[r];
                 }
             }
             c += __popc(m8);
