@@ -1196,18 +1196,41 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
     int c = 0;
     uint16_t *const wp = nbr16 + nbr_index16(i, 0, nchunk);
     for (;;) {
-        if (BL == 1) {
-            const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t), 24u);
-            double px[4], py[4], pz[4];
-            int tr[4];
+        // the round's candidates: slots t .. t + 3 (BL = 1), or the lane's
+        // four of slots t .. t + 7 (BL = 2)
+        double px[4], py[4], pz[4];
+        int tr[4];
+        {
+            const int t0 = BL == 1 ? t : t + p;
+            const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t0), 24u);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const lds_double *q = (const lds_double *)(pb + r * 24);
+                const lds_double *q = (const lds_double *)(pb + r * 24 * BL);
                 px[r] = q[0];
                 py[r] = q[1];
                 pz[r] = q[2];
-                tr[r] = F[t + r];
+                tr[r] = F[t0 + BL * r];
             }
+        }
+        // where the run after this one lies (taken below once this one is
+        // done), looked up ahead of the round's tests so that its LDS reads
+        // overlap them instead of ending the round
+        int nt, ne;
+        bool more;
+        RowWalk w2 = w;
+        int nrow = row, ntw = tw, nto0 = to0, nto1 = to1;
+        double nsy = sy, nsz = sz;
+        if (WRAP) {
+            more = row_next(G, gy0, w2);
+            row_run(G, soff, w2, nt, ne);
+        } else {
+            // the next needed row (row itself when there is none)
+            const unsigned rest = row < 24 ? T.need & (~0u << (row + 1)) : 0u;
+            more = rest != 0u;
+            nrow = more ? __builtin_ctz(rest) : row;
+            trim_run(nrow, nt, ne, ntw, nsy, nsz, nto0, nto1);
+        }
+        if (BL == 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const double s = dist(px[r], py[r], pz[r], t + r);
@@ -1217,17 +1240,6 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
             }
             t += 4;
         } else {
-            const lds_char *pb = (const lds_char *)S + __umul24(unsigned(t + p), 24u);
-            double px[4], py[4], pz[4];
-            int tr[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const lds_double *q = (const lds_double *)(pb + r * 48);
-                px[r] = q[0];
-                py[r] = q[1];
-                pz[r] = q[2];
-                tr[r] = F[t + p + 2 * r];
-            }
             unsigned mine = 0;  // bit 2r + p: slot t + 2r + p accepted
             uint16_t vr[4];
 #pragma unroll
@@ -1249,25 +1261,13 @@ __device__ __forceinline__ int build_rows(lds_double *S, const lds_u16 *F, const
             t += 8;
         }
         const bool adv = t >= e;
-        int nt, ne;
-        bool more;
         if (WRAP) {
-            RowWalk w2 = w;
-            more = row_next(G, gy0, w2);
-            row_run(G, soff, w2, nt, ne);
             w.gz = adv ? w2.gz : w.gz;
             w.gy = adv ? w2.gy : w.gy;
             w.kz = adv ? w2.kz : w.kz;
             w.ky = adv ? w2.ky : w.ky;
             w.piece = adv ? w2.piece : w.piece;
         } else {
-            // the next needed row (row itself when there is none)
-            const unsigned rest = row < 24 ? T.need & (~0u << (row + 1)) : 0u;
-            more = rest != 0u;
-            const int nrow = more ? __builtin_ctz(rest) : row;
-            int ntw = tw, nto0 = to0, nto1 = to1;
-            double nsy = sy, nsz = sz;
-            trim_run(nrow, nt, ne, ntw, nsy, nsz, nto0, nto1);
             if (SHIFT) {
                 sy = adv ? nsy : sy;
                 sz = adv ? nsz : sz;
