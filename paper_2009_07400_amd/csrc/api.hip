@@ -1348,9 +1348,9 @@ tmd_status tmd_adjoint_workspace_size(const tmd_system *s, int32_t n_steps, size
     return TMD_OK;
 }
 
-// The list of interval m (the system's current list, atom order and
-// positions) into its AdjList.
-static hipError_t save_adj_list(tmd_system *s, const AdjBuf &a, int32_t m, hipStream_t hs) {
+// The atom order and first positions of interval m into its AdjList (its
+// list is built there in place).
+static hipError_t save_adj_state(tmd_system *s, const AdjBuf &a, int32_t m, hipStream_t hs) {
     AdjList l{};
     carve_adj_list(s->dmax, a.lists + size_t(m) * a.list_bytes, &l);
     const Dims &d = s->d;
@@ -1363,14 +1363,40 @@ static hipError_t save_adj_list(tmd_system *s, const AdjBuf &a, int32_t m, hipSt
         e = hipMemcpyAsync(dst[q], src[q], np * 8, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess)
         e = hipMemcpyAsync(l.orig, b.orig[s->cur.o], size_t(d.nt) * 4, hipMemcpyDeviceToDevice, hs);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(l.cnt, b.nbr_count, size_t(d.nt) * 4, hipMemcpyDeviceToDevice, hs);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(l.nbr, b.nbr, np * size_t(d.nchunk) * 16, hipMemcpyDeviceToDevice, hs);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(l.hood, b.hood_tab, size_t(d.nblk) * kHoodWords * 4, hipMemcpyDeviceToDevice, hs);
     return e;
 }
+
+// While the forward pass runs, the system's list buffers (counts, list,
+// neighborhood tables) are those of an interval's AdjList, so each
+// interval's rebuild writes its list straight into the workspace; the
+// system's own buffers come back when this goes out of scope (a run that
+// ends there, on an error, while they are still redirected leaves no valid
+// list or forces).
+struct ListRedirect {
+    tmd_system *s;
+    int32_t *const cnt, *const nbr, *const hood;
+    explicit ListRedirect(tmd_system *s_)
+        : s(s_), cnt(s_->b.nbr_count), nbr(s_->b.nbr), hood(s_->b.hood_tab) {}
+    ~ListRedirect() {
+        if (s->b.nbr != nbr) {
+            s->list_valid = false;
+            s->force_valid = false;
+        }
+        restore();
+    }
+    void to(const AdjList &l) {
+        Buffers &b = s->b;
+        b.nbr_count = l.cnt;
+        b.nbr = l.nbr;
+        b.hood_tab = l.hood;
+    }
+    void restore() {
+        Buffers &b = s->b;
+        b.nbr_count = cnt;
+        b.nbr = nbr;
+        b.hood_tab = hood;
+    }
+};
 
 tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t bytes, tmd_stream stream) {
     tmd_status st = check_ready(s, true);
@@ -1414,6 +1440,13 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
     // before, and wraps positions into the box (wrapping twice changes
     // nothing), so a reload would give the same positions, order, list and
     // forces bit for bit.
+    ListRedirect redirect(s);
+    auto list_of = [&](int32_t m) {
+        AdjList l{};
+        carve_adj_list(s->dmax, a.lists + size_t(m) * a.list_bytes, &l);
+        return l;
+    };
+    bool rebuilt_last = false;
     for (int32_t m = 0; m < nseg && e == hipSuccess; ++m) {
         const int32_t k_lo = m * R, len = std::min(R, n_steps - k_lo);
         double *c = a.ckpt + size_t(m) * 6 * nt;
@@ -1426,6 +1459,7 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
             const double *const vi[3] = {vo[0], vo[1], vo[2]};
             e = launch_load_state(s->d, pi, vi, b, Cursor{}, hs);
             s->cur = Cursor{};
+            redirect.to(list_of(0));
             if (e == hipSuccess && (st = rebuild(s, hs)) != TMD_OK)
                 return st;
         }
@@ -1433,7 +1467,7 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
         const Pos x0 = b.pos(s->cur.x);
         auto traj = [&](int32_t j) { return j == 0 ? x0 : slot(k_lo + j); };
         if (e == hipSuccess)
-            e = save_adj_list(s, a, m, hs);
+            e = save_adj_state(s, a, m, hs);
         if (e == hipSuccess && m == 0)
             e = launch_force_at(s->d, b, x0, x0, o, 0, false, hs);
         if (e == hipSuccess)
@@ -1447,13 +1481,34 @@ tmd_status tmd_adjoint_forward(tmd_system *s, int32_t n_steps, void *ws, size_t 
             double *dst = q == 0 ? xs.x : (q == 1 ? xs.y : xs.z);
             e = hipMemcpyAsync(dst, src, nt * sizeof(double), hipMemcpyDeviceToDevice, hs);
         }
-        if (e == hipSuccess && (step0 + k_lo + len) % R == 0 && (st = rebuild(s, hs)) != TMD_OK)
-            return st;
+        if (e == hipSuccess && (step0 + k_lo + len) % R == 0) {
+            // the next interval's list (past the last interval: the system's)
+            if (m + 1 < nseg)
+                redirect.to(list_of(m + 1));
+            else
+                redirect.restore();
+            if ((st = rebuild(s, hs)) != TMD_OK)
+                return st;
+            rebuilt_last = m + 1 == nseg;
+        }
         if (e == hipSuccess)
             e = launch_force(s->d, b, s->cur, 1, false, hs);
         s->force_valid = true;
         s->step = step0 + k_lo + len;
     }
+    // a run that ends between rebuilds keeps the last interval's list:
+    // the system's own buffers take a copy
+    if (e == hipSuccess && !rebuilt_last) {
+        const AdjList l = list_of(nseg - 1);
+        redirect.restore();
+        e = hipMemcpyAsync(b.nbr_count, l.cnt, nt * 4, hipMemcpyDeviceToDevice, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.nbr, l.nbr, np * size_t(s->d.nchunk) * 16, hipMemcpyDeviceToDevice, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.hood_tab, l.hood, size_t(s->d.nblk) * kHoodWords * 4, hipMemcpyDeviceToDevice,
+                               hs);
+    }
+    redirect.restore();
     if (e != hipSuccess)
         return hip_fail(s, e, "adjoint_forward");
     {
