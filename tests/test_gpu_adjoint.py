@@ -113,7 +113,8 @@ def test_adjoint_forward_ends_in_the_integrate_state_bitwise():
     """The recorded forward run takes the steps of integrate() (each later
     interval continues from the state the previous one left, which is the
     state a reload of its checkpoint gives): positions and velocities equal
-    integrate()'s bit for bit, over whole and partial rebuild intervals."""
+    integrate()'s bit for bit, over whole and partial rebuild intervals, and
+    so do the list it leaves and the steps that follow."""
     for steps in (45, 60):
         s = md_system(10, 0.8442, 1.0, seed=3000)
         a = System(s.n, s.L)
@@ -127,6 +128,18 @@ def test_adjoint_forward_ends_in_the_integrate_state_bitwise():
         a.sync()
         b.sync()
         assert step == steps
+        assert torch.equal(pa, pb) and torch.equal(va, vb), steps
+        # the list the forward leaves (built into the workspace, then the
+        # system's own) is integrate()'s, and later steps run on it alike
+        ca, ia = a.get_neighbors()
+        cb, ib = b.get_neighbors()
+        assert torch.equal(ca, cb) and torch.equal(ia, ib), steps
+        a.integrate(12)
+        b.integrate(12)
+        pa, va, _ = a.get_state()
+        pb, vb, _ = b.get_state()
+        a.sync()
+        b.sync()
         assert torch.equal(pa, pb) and torch.equal(va, vb), steps
         a.close()
         b.close()
