@@ -217,6 +217,28 @@ def test_error_overflow_is_deferred(build_lanes):
     assert "78" in str(e.value)
 
 
+def test_overflowing_lists_keep_the_same_entries_on_both_build_paths():
+    """With max_neighbors below every list's length both list builds store
+    the same first max_neighbors candidates of the canonical walk (the
+    16-bit entries past the capacity are dropped on both paths alike)."""
+    s = md_system(5)
+    out = []
+    for lanes in (1, 2):
+        g = _gpu_system(s.pos(), s.vel(), s.L, max_neighbors=8)
+        g.set_schedule(build_lanes=lanes)
+        g.build_neighbors()
+        counts, ids = g.get_neighbors()
+        with pytest.raises(TmdError) as e:
+            g.sync()
+        assert e.value.status == abi.TMD_ENBR_OVERFLOW
+        out.append((counts.cpu().numpy(), ids.cpu().numpy()))
+        g.close()
+    (c1, i1), (c2, i2) = out
+    assert (c1 == 8).all() and np.array_equal(c1, c2) and np.array_equal(i1, i2)
+    assert (i1 >= 0).all() and (i1 < s.n).all()
+    assert not (i1 == np.arange(s.n)[:, None]).any()  # no atom lists itself
+
+
 def test_error_nonfinite_and_call_order():
     s = md_system(5)
     pos = s.pos()
