@@ -1245,22 +1245,33 @@ tmd_status tmd_autotune(tmd_system *s, int32_t repeats, int32_t flags, tmd_strea
                 // timed back to back on unchanged inputs can rank first
                 // although it is slower in a run
                 const int32_t t0 = default_threads(s->d, Lp);
+                // within 4% the larger workgroup of this sweep wins: its
+                // extra wavefronts stage the neighborhood faster, which
+                // launches timed back to back (inputs in the caches) show
+                // less than a run does (131k atoms: 192 threads can time
+                // level with 320 here, and run 5% slower)
+                float lbest = 1e30f;
+                int32_t lt = t0;
                 for (int32_t t = t0; t <= std::min(kMaxThreads, t0 + 128) && e == hipSuccess; t += 64) {
                     s->d.threads = t;
                     // cost per step: one force evaluation plus the list build's share
                     float ms = 0.0f;
                     e = time_force(s, repeats, hs, a, b, ms);
                     ms += mb / float(s->rebuild_every);
-                    if (e == hipSuccess && ms < best) {
-                        best = ms;
-                        best_edge = E;
-                        best_t = t;
-                        best_p = P;
-                        best_l = Lp;
-                        best_bt = bt_best;
-                        best_bl = bl_best;
-                        best_h = H;
+                    if (e == hipSuccess && ms < 1.04f * lbest) {
+                        lbest = std::min(lbest, ms);
+                        lt = t;
                     }
+                }
+                if (e == hipSuccess && lbest < best) {
+                    best = lbest;
+                    best_edge = E;
+                    best_t = lt;
+                    best_p = P;
+                    best_l = Lp;
+                    best_bt = bt_best;
+                    best_bl = bl_best;
+                    best_h = H;
                 }
             }
         }
